@@ -1,0 +1,180 @@
+/*
+ * percis.h -- C ABI of the MI355X (gfx950) PercIS hot path.
+ *
+ * PercIS (Cruciani & Pellegrina, "Fast Percolation Centrality Approximation
+ * with Importance Sampling") estimates the percolation centrality p(v) of
+ * every node (Definition 1, Eq. 1) by importance sampling: each sample draws
+ * an ordered pair (s,t) with probability kappa~(s,t) proportional to
+ * R(x_s - x_t) = max(0, x_s - x_t) (Section III-A), picks one shortest s-t
+ * path uniformly at random (RandomSP, Section III-B) and credits every
+ * internal node of that path. Because kappa(s,t,v)/kappa~(s,t) equals the
+ * per-node constant d_v = C / S_v for every sampled pair (proof of
+ * Proposition 5), the per-sample output reduces to integer hit counts h_v and
+ * the estimate is p~(v) = d_v h_v / l.
+ *
+ * Conventions
+ *  - Every call returns an int status: PERCIS_OK (0) or a negative error
+ *    code. No C++ exception crosses this boundary. percis_last_error() gives
+ *    a human-readable message for the last failing call on a context.
+ *  - A context owns every device buffer it allocates. Outputs are written
+ *    only into caller-owned buffers; the library never hands an allocation
+ *    to the caller. One context is used by one host thread at a time;
+ *    distinct contexts may be used concurrently.
+ *  - Pointers are host pointers unless the call's flags contain
+ *    PERCIS_DEVICE_PTRS, in which case they are device pointers on the
+ *    context's device (for instance the data of torch tensors).
+ *  - All device work is enqueued on the context's HIP stream (the null
+ *    stream unless one was given); calls that return host results
+ *    synchronise that stream before returning.
+ *  - Percolation states are quantised: x_v = k_v / 65535 with k_v in
+ *    0..65535; all sampling arithmetic is exact integer arithmetic.
+ *  - Graphs are unweighted, given as CSR with int32 node ids; undirected
+ *    graphs store both arcs of every edge. Limits: 1 <= n <= 2^25 nodes
+ *    (so that the integer pair weights fit in 64 bits), m <= 2^31 - 1 arcs.
+ */
+#ifndef PERCIS_H
+#define PERCIS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---- */
+#define PERCIS_OK                 0
+#define PERCIS_E_INVAL           -1  /* bad argument or malformed graph */
+#define PERCIS_E_STATE           -2  /* call out of order (no graph / no states) */
+#define PERCIS_E_NOMEM           -3  /* device or host allocation failed */
+#define PERCIS_E_DEVICE          -4  /* HIP runtime error */
+#define PERCIS_E_DEGENERATE      -5  /* all states equal: kappa~ undefined */
+#define PERCIS_E_TOO_LARGE       -6  /* n > 2^25, or 2^32 or more samples in one call */
+#define PERCIS_E_SIGMA_OVERFLOW  -7  /* a sampled pair has 2^64 or more shortest paths */
+
+/* ---- flags ---- */
+#define PERCIS_DIRECTED     0x1u  /* load_csr: arcs are directed */
+#define PERCIS_DEVICE_PTRS  0x2u  /* pointer arguments are device memory */
+#define PERCIS_ACCUMULATE   0x4u  /* sample_range: add to hits instead of overwriting */
+
+typedef struct percis_ctx percis_ctx;
+
+/* Per-call statistics of the sampler. |I(tau)| is the number of internal
+ * nodes of the sampled path (Section II-A); it is d(s,t) - 1 for a reachable
+ * pair and 0 for an unreachable one. The four work counters count, over all
+ * samples of the call: adjacency entries examined (edges), shortest-path
+ * count accumulations (sigma_adds), vertices whose adjacency was scanned
+ * (vertices_expanded) and vertices first reached (vertices_discovered). */
+typedef struct {
+    uint64_t samples;
+    uint64_t reachable;
+    uint64_t sum_I;
+    uint64_t sum_I2;
+    uint64_t overflow;          /* samples with sigma_st >= 2^64 */
+    uint64_t first_overflow;    /* smallest such sample index, or UINT64_MAX */
+    uint64_t edges;
+    uint64_t sigma_adds;
+    uint64_t vertices_expanded;
+    uint64_t vertices_discovered;
+    double   kernel_ms;         /* device time of the sampling kernel */
+} percis_stats;
+
+/* Result summary of percis_estimate (Algorithm 1). */
+typedef struct {
+    uint64_t l1;          /* phase-1 sample size, ceil(max(1000, ln(1/delta)/eps)) */
+    uint64_t l;           /* phase-2 sample size (Theorem 1 with Alg. 1's constants) */
+    int64_t  D;           /* vertex-diameter bound used */
+    double   d_hat;       /* likelihood ratio max_v C / S_v */
+    double   rho_tilde;   /* phase-1 mean of |I| */
+    double   Lambda;      /* phase-1 unbiased sample variance of |I| */
+    double   rho_hat;     /* Proposition 2 bound, at delta/4 */
+    double   v_hat;       /* Proposition 3 bound, at delta/4 */
+    double   x_hat;       /* d/2 - sqrt(d^2/4 - min(d^2/4, v_hat)) */
+    double   phase1_ms, bounds_ms, phase2_ms, total_ms;
+    uint64_t overflow;    /* overflowed samples over both phases */
+} percis_estimate_info;
+
+/* Creates a context on HIP device `device`. `hip_stream` is a hipStream_t
+ * (NULL = null stream) that every later call enqueues on; it must outlive the
+ * context or be replaced with percis_set_stream. device = PERCIS_HOST_ONLY
+ * creates a context that makes no HIP call at all: it validates graphs and
+ * states and builds their host-side structures, and every call that needs
+ * the device returns PERCIS_E_STATE. The device copies of the graph and of
+ * the pair distribution are uploaded by the first call that needs them. */
+#define PERCIS_HOST_ONLY (-1)
+int percis_create(int device, void* hip_stream, percis_ctx** out);
+void percis_destroy(percis_ctx* ctx);
+int percis_set_stream(percis_ctx* ctx, void* hip_stream);
+
+/* Loads the graph G = (V, E) of Section II-A: row_ptr[n+1], col[m]
+ * (row_ptr[0] = 0, non-decreasing, row_ptr[n] = m, 0 <= col < n). Rejected
+ * with PERCIS_E_INVAL: self-loops, duplicate arcs (E is a set), and for an
+ * undirected graph an arc whose reverse is missing. Rows need not be sorted;
+ * the library keeps its own sorted copy. For a directed graph the library
+ * also builds the in-adjacency. Discards previously set states.
+ * flags: PERCIS_DIRECTED, PERCIS_DEVICE_PTRS. */
+int percis_load_csr(percis_ctx* ctx, int32_t n, int64_t m, const int32_t* row_ptr,
+                    const int32_t* col, uint32_t flags);
+
+/* Sets the percolation states x_v = k[v] / 65535 (k[n] uint16) and builds the
+ * exact integer pair distribution: ranks sorted by (k non-increasing, node id
+ * increasing) (Section II-A, "up to a relabelling"), then the preprocessing of
+ * Algorithm 2 (appendix) in units of 1/65535. Returns PERCIS_E_DEGENERATE if
+ * all states are equal (the total weight C is 0, Definition 1 undefined).
+ * flags: PERCIS_DEVICE_PTRS. */
+int percis_set_states(percis_ctx* ctx, const uint16_t* k, uint32_t flags);
+
+/* Draws samples first .. first+count-1 of the stream (seed, phase): for each,
+ * the pair (s,t) of Algorithm 2, a shortest-path-counting BFS (balanced
+ * bidirectional, Section III-B), the r-th shortest path in canonical order
+ * (r uniform in [0, sigma_st)), and one hit to each internal node.
+ * hits[n] (uint32) receives the per-node hit counts; hit counts over disjoint
+ * index ranges add up. The random stream is Philox4x64-10 with key
+ * (seed, phase) and counter (sample index, variate, attempt, 0), so results do
+ * not depend on launch configuration. Requires count < 2^32. Returns
+ * PERCIS_E_SIGMA_OVERFLOW if any sampled pair has sigma_st >= 2^64 (such
+ * samples add no hits; st reports the count and first index).
+ * st may be NULL. flags: PERCIS_DEVICE_PTRS (hits is device memory),
+ * PERCIS_ACCUMULATE. */
+int percis_sample_range(percis_ctx* ctx, uint64_t first, uint64_t count, uint64_t seed, uint32_t phase,
+                        uint32_t* hits, uint32_t flags, percis_stats* st);
+
+/* percis_sample_range(ctx, 0, n_samples, seed, 0, hits, flags, st). */
+int percis_sample(percis_ctx* ctx, uint64_t n_samples, uint64_t seed, uint32_t* hits, uint32_t flags,
+                  percis_stats* st);
+
+/* Algorithm 1 (PercIS): VertexDiamUB, l1 samples in phase 1, the bounds of
+ * Propositions 2 and 3 and the sample size of Theorem 1 (with the constants
+ * of Alg. 1), l samples in phase 2, and p_out[v] = d_v h_v / l (host array of
+ * n doubles; p := 0 where S_v = 0). Requires 0 < eps < 1, 0 < delta < 1.
+ * info may be NULL. */
+int percis_estimate(percis_ctx* ctx, double eps, double delta, uint64_t seed, double* p_out,
+                    percis_estimate_info* info);
+
+/* Overrides VertexDiamUB with a caller-known bound D >= the maximum number of
+ * internal nodes of any shortest path (D < 0 restores the default: a BFS per
+ * connected component for undirected graphs, the largest weakly connected
+ * component's size minus 2 for directed ones). */
+int percis_set_vertex_diameter(percis_ctx* ctx, int64_t D);
+
+/* Test hook: runs RandomSP on the device for a given pair (s, t) and path
+ * index r. Writes L = d(s,t) (-1 if unreachable) and sigma_st (saturated at
+ * 2^64 - 1 when *overflow is set); if reachable, not overflowed, r < sigma_st
+ * and cap >= L + 1, writes the path s, ..., t into path[] (host). */
+int percis_debug_path(percis_ctx* ctx, int32_t s, int32_t t, uint64_t r, int32_t* path, int32_t cap,
+                      int32_t* L, uint64_t* sigma, int32_t* overflow);
+
+/* Tuning knobs (launch shape only; results never depend on them).
+ * PERCIS_OPT_SLOTS: concurrent samples (resident workgroups), 0 = auto.
+ * PERCIS_OPT_SCRATCH_MB: cap on per-slot scratch memory, 0 = auto. */
+#define PERCIS_OPT_SLOTS       1
+#define PERCIS_OPT_SCRATCH_MB  2
+int percis_set_option(percis_ctx* ctx, int option, int64_t value);
+int percis_get_option(percis_ctx* ctx, int option, int64_t* value);
+
+const char* percis_status_str(int status);
+const char* percis_last_error(const percis_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PERCIS_H */

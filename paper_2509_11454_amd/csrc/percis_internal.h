@@ -1,0 +1,74 @@
+// Library-internal declarations shared by the host side (percis_api.cpp) and
+// the device side (percis_kernels.hip). Nothing here is part of the ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace percis {
+
+// Device view of the graph: out-adjacency and in-adjacency (the same arrays
+// for an undirected graph), rows sorted by increasing node id.
+struct DevGraph {
+    int32_t n;
+    const int32_t* rp;    // [n+1]
+    const int32_t* col;   // [m]
+    const int32_t* irp;   // [n+1]
+    const int32_t* icol;  // [m]
+};
+
+// Device view of the exact integer pair distribution (Algorithm 2 in units
+// of 1/65535): ranks i = 1..n sorted by (k non-increasing, id increasing).
+struct DevCdf {
+    int32_t n;
+    uint64_t C;            // total weight, sum over ordered pairs of R(k_u - k_w)
+    const int32_t* perm;   // [n+1]  perm[i] = node of rank i
+    const uint32_t* kr;    // [n+2]  k of rank i
+    const uint64_t* W;     // [n+2]  W[i] = sum_{j >= i} kr[j], W[n+1] = 0
+    const uint64_t* P;     // [n+1]  P[i] = sum_{j <= i} c_j, c_j = (n-j+1) kr[j] - W[j]
+};
+
+// Per-slot scratch; every array is [slots][stride] and is all-zero between
+// samples (each sample clears what it touched).
+struct DevSlots {
+    uint32_t* lv_s;   // s-side level + 1 (0 = unreached), plus flag bits
+    uint32_t* lv_t;   // t-side level + 1, plus flag bits
+    uint64_t* sg_s;   // shortest-path counts from s
+    uint64_t* sg_t;   // shortest-path counts to t
+    int32_t* q_s;     // s-side BFS queue (levels are contiguous segments)
+    int32_t* q_t;     // t-side BFS queue
+    int32_t* q_d;     // t-side shortest-path DAG, level by level
+    int64_t stride;   // elements per slot (>= n)
+};
+
+// Device-side accumulators of one sampling call.
+struct DevStats {
+    unsigned long long samples, reachable, sum_I, sum_I2, overflow, first_overflow;
+    unsigned long long edges, sigma_adds, vexp, vdisc;
+};
+
+struct SampleLaunch {
+    uint64_t first, count, seed, phase;
+    uint32_t* hits;                  // [n]
+    DevStats* stats;
+    unsigned long long* work;        // next unclaimed sample offset
+    int slots;                       // grid size
+};
+
+// Debug request: one (s, t, r) path; output written to `out`.
+struct DebugOut {
+    int32_t L;
+    int32_t overflow;
+    uint64_t sigma;
+    int32_t path[1];   // flexible: L+1 entries
+};
+
+hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t count, hipStream_t stream);
+hipError_t launch_fill_u8(void* p, int64_t bytes, hipStream_t stream);
+hipError_t launch_init_stats(DevStats* st, unsigned long long* work, hipStream_t stream);
+hipError_t launch_sampler(const DevGraph& g, const DevCdf& cdf, const DevSlots& slots, const SampleLaunch& a,
+                          hipStream_t stream);
+hipError_t launch_debug_path(const DevGraph& g, const DevSlots& slots, int32_t s, int32_t t, uint64_t r,
+                             DebugOut* out, int32_t cap, hipStream_t stream);
+int sampler_block_size();
+
+}  // namespace percis

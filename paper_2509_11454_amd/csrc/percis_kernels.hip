@@ -1,0 +1,597 @@
+// PercIS sampler kernels for gfx950 (MI355X).
+//
+// One persistent workgroup per slot. A slot owns per-node scratch (levels and
+// shortest-path counts from both ends, three queues) that is all-zero between
+// samples; every sample clears exactly what it touched. Workgroups claim
+// sample indices from a global counter, so the grid can be smaller or larger
+// than the number of samples and results never depend on the launch shape:
+// every sample's randomness is keyed on its index (Philox4x64-10, counter
+// (index, variate, attempt, 0), key (seed, phase)), and all accumulation is
+// integer.
+//
+// Per sample (Algorithm 2 of the paper's appendix, then RandomSP of
+// Section III-B):
+//   1. pair: U_s uniform in [0, C) picks rank s = min{d : U_s < P[d]};
+//      U_t uniform in [0, c_s) picks t = min{d > s : U_t < F_s(d)} with
+//      F_s(d) = (d - s + 1) k_s - (W_s - W_{d+1}); both bounded draws use
+//      Lemire's multiply-and-reject.
+//   2. balanced bidirectional BFS with shortest-path counting: the side whose
+//      frontier has the smaller degree sum expands one full level, edge-
+//      balanced across the workgroup; the first level that reaches the other
+//      ball fixes d(s,t) = L and the meeting layer M, and
+//      sigma_st = sum_{w in M} sigma_s(w) sigma_t(w).
+//   3. shortest-path counts from s are pushed from M through the part of the
+//      shortest-path DAG inside the t-ball, so that every DAG node knows
+//      sigma_s.
+//   4. r uniform in [0, sigma_st); the canonical backward walk from t takes,
+//      among the in-neighbours one level closer to s (ascending id), the
+//      first whose cumulative sigma_s exceeds r (a 64-lane prefix scan per
+//      chunk of the in-row); every node passed on the way is an internal node
+//      of the chosen path and gets one hit.
+// A sigma that reaches 2^64 anywhere on the way to t is caught by a flag that
+// is set on a wrapping add and propagated along DAG arcs; the sample then adds
+// no hits and is counted as overflowed.
+#include "percis_internal.h"
+
+namespace percis {
+
+constexpr int BS = 256;
+constexpr int NWAVE = BS / 64;
+constexpr uint32_t LVMASK = 0x0FFFFFFFu;
+constexpr uint32_t DAGBIT = 0x20000000u;
+constexpr uint32_t OVFBIT = 0x40000000u;
+
+int sampler_block_size() { return BS; }
+
+// Scratch is shared by the waves of a workgroup and updated with L2 atomics;
+// reads go to L2 as well so that a stale L1 line is never observed.
+__device__ __forceinline__ uint32_t ld32(uint32_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint64_t ld64(uint64_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ int32_t ldq(int32_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// ---------------------------------------------------------------- Philox
+__device__ __forceinline__ uint64_t philox_word0(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3,
+                                                 uint64_t k0, uint64_t k1) {
+#pragma unroll
+    for (int i = 0; i < 10; i++) {
+        const uint64_t m0 = 0xD2E7470EE14C6C93ull, m1 = 0xCA5A826395121157ull;
+        uint64_t hi0 = __umul64hi(m0, c0), lo0 = m0 * c0;
+        uint64_t hi1 = __umul64hi(m1, c2), lo1 = m1 * c2;
+        uint64_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+        c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
+        k0 += 0x9E3779B97F4A7C15ull;
+        k1 += 0xBB67AE8584CAA73Bull;
+    }
+    return c0;
+}
+
+// Uniform integer in [0, N), N >= 1, exactly (Lemire 2019).
+__device__ uint64_t draw_bounded(uint64_t seed, uint64_t phase, uint64_t idx, uint64_t variate, uint64_t N) {
+    for (uint64_t attempt = 0;; attempt++) {
+        uint64_t x = philox_word0(idx, variate, attempt, 0, seed, phase);
+        uint64_t lo = x * N;
+        if (lo < N) {
+            uint64_t thr = (0 - N) % N;
+            if (lo < thr) continue;
+        }
+        return __umul64hi(x, N);
+    }
+}
+
+__device__ int32_t search_s(const DevCdf& c, uint64_t U) {
+    int32_t lo = 1, hi = c.n;
+    while (lo < hi) {
+        int32_t mid = lo + ((hi - lo) >> 1);
+        if (U < c.P[mid]) hi = mid; else lo = mid + 1;
+    }
+    return lo;
+}
+
+__device__ int32_t search_t(const DevCdf& c, int32_t s, uint64_t U) {
+    const uint64_t ks = c.kr[s], Ws = c.W[s];
+    int32_t lo = s + 1, hi = c.n;
+    while (lo < hi) {
+        int32_t mid = lo + ((hi - lo) >> 1);
+        uint64_t F = (uint64_t)(mid - s + 1) * ks - (Ws - c.W[mid + 1]);
+        if (U < F) hi = mid; else lo = mid + 1;
+    }
+    return lo;
+}
+
+// ------------------------------------------------------------ workgroup state
+struct SampleShared {
+    int32_t beg[BS];
+    int32_t off[BS];
+    uint64_t sig[BS];
+    uint32_t of[BS];
+    int32_t wsum[NWAVE];
+    unsigned long long idx;
+    int32_t s, t;
+    int32_t lo_s, hi_s, lo_t, hi_t;
+    int32_t a, b;
+    unsigned long long deg_s, deg_t, deg_next;
+    int32_t tail, tail_s, tail_t, tail_d;
+    int32_t nmeet;
+    int32_t status;   // 0 running, 1 met, 2 unreachable
+    int32_t ovf;
+    int32_t walk_err;
+    uint64_t sigma;
+    unsigned long long n_samples, n_reach, sum_I, sum_I2, n_ovf, first_ovf;
+};
+
+struct Counters {
+    unsigned long long E, A, V, Vd;
+};
+
+__device__ __forceinline__ int block_excl_scan(int v, int32_t* wsum, int& total) {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    int x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        int y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) wsum[wid] = x;
+    __syncthreads();
+    int pre = 0, tot = 0;
+#pragma unroll
+    for (int i = 0; i < NWAVE; i++) {
+        int s = wsum[i];
+        if (i < wid) pre += s;
+        tot += s;
+    }
+    total = tot;
+    return pre + x - v;
+}
+
+__device__ __forceinline__ uint64_t wave_incl_scan_u64(uint64_t v) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        uint64_t y = __shfl_up(v, o, 64);
+        if (lane >= o) v += y;
+    }
+    return v;
+}
+
+// One level of work over the frontier q[lo, hi), edge-balanced: the rows of up
+// to BS frontier nodes are concatenated (prefix sum of degrees) and the
+// workgroup strides over the concatenation.
+//   MODE 0: s-side BFS level (out-arcs); new nodes get s-level value nl.
+//   MODE 1: t-side BFS level (in-arcs);  new nodes get t-level value nl.
+//   MODE 2: DAG sweep inside the t-ball (out-arcs): nodes of t-level value nl
+//           receive sigma_s from the frontier and join the DAG queue.
+// New nodes whose other-side level is set form the meeting layer, which is
+// written to the head of q_d.
+template <int MODE>
+__device__ void expand(const DevGraph& g, const DevSlots& sl, int64_t so, int lo, int hi, uint32_t nl,
+                       SampleShared& sh, Counters& cn) {
+    const int tid = threadIdx.x;
+    const int32_t* rp = (MODE == 1) ? g.irp : g.rp;
+    const int32_t* col = (MODE == 1) ? g.icol : g.col;
+    const int32_t* drp = (MODE == 0) ? g.rp : g.irp;
+    int32_t* q = (MODE == 0 ? sl.q_s : MODE == 1 ? sl.q_t : sl.q_d) + so;
+    uint32_t* lv_mine = (MODE == 0 ? sl.lv_s : sl.lv_t) + so;
+    uint32_t* lv_other = (MODE == 0 ? sl.lv_t : sl.lv_s) + so;
+    uint64_t* sg = (MODE == 1 ? sl.sg_t : sl.sg_s) + so;
+
+    for (int base = lo; base < hi; base += BS) {
+        const int cnt = min(BS, hi - base);
+        int deg = 0, beg = 0;
+        uint64_t su = 0;
+        uint32_t of = 0;
+        if (tid < cnt) {
+            int32_t u = ldq(q + base + tid);
+            beg = rp[u];
+            deg = rp[u + 1] - beg;
+            su = ld64(sg + u);
+            if (MODE != 2) of = ld32(lv_mine + u) & OVFBIT;
+            cn.V++;
+        }
+        int total;
+        int ex = block_excl_scan(deg, sh.wsum, total);
+        sh.beg[tid] = beg;
+        sh.off[tid] = ex;
+        sh.sig[tid] = su;
+        sh.of[tid] = of;
+        __syncthreads();
+        for (int e = tid; e < total; e += BS) {
+            int l2 = 0, h2 = cnt - 1;
+            while (l2 < h2) {
+                int mid = (l2 + h2 + 1) >> 1;
+                if (sh.off[mid] <= e) l2 = mid; else h2 = mid - 1;
+            }
+            const int j = l2;
+            const int32_t w = col[sh.beg[j] + (e - sh.off[j])];
+            cn.E++;
+            if (MODE == 2) {
+                uint32_t lt = ld32(lv_mine + w);
+                if ((lt & LVMASK) == nl) {
+                    atomicAdd((unsigned long long*)(sg + w), (unsigned long long)sh.sig[j]);
+                    cn.A++;
+                    if (!(lt & DAGBIT)) {
+                        uint32_t old = atomicOr(lv_mine + w, DAGBIT);
+                        if (!(old & DAGBIT)) {
+                            int pos = atomicAdd(&sh.tail, 1);
+                            q[pos] = w;
+                            cn.Vd++;
+                        }
+                    }
+                }
+            } else {
+                uint32_t lw = ld32(lv_mine + w);
+                bool fresh = false;
+                if (lw == 0) {
+                    uint32_t old = atomicCAS(lv_mine + w, 0u, nl);
+                    if (old == 0) { fresh = true; lw = nl; } else { lw = old; }
+                }
+                if ((lw & LVMASK) == nl) {
+                    const uint64_t add = sh.sig[j];
+                    unsigned long long old = atomicAdd((unsigned long long*)(sg + w), (unsigned long long)add);
+                    if (old + add < old || sh.of[j]) atomicOr(lv_mine + w, OVFBIT);
+                    cn.A++;
+                }
+                if (fresh) {
+                    int pos = atomicAdd(&sh.tail, 1);
+                    q[pos] = w;
+                    cn.Vd++;
+                    atomicAdd(&sh.deg_next, (unsigned long long)(drp[w + 1] - drp[w]));
+                    if (ld32(lv_other + w) != 0) {
+                        int mp = atomicAdd(&sh.nmeet, 1);
+                        sl.q_d[so + mp] = w;
+                    }
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+__device__ __forceinline__ void level_barrier() {
+    __threadfence();
+    __syncthreads();
+}
+
+// One sample on this workgroup's slot. In debug mode (dbg != nullptr) the pair
+// and the path index are given instead of drawn, hits are not touched and the
+// path is written to dbg.
+__device__ void run_sample(const DevGraph& g, const DevCdf& cdf, const DevSlots& sl, int64_t so,
+                           uint64_t idx, const SampleLaunch& a, SampleShared& sh, Counters& cn,
+                           DebugOut* dbg, int32_t dbg_s, int32_t dbg_t, uint64_t dbg_r, int32_t dbg_cap) {
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    uint32_t* lv_s = sl.lv_s + so;
+    uint32_t* lv_t = sl.lv_t + so;
+    uint64_t* sg_s = sl.sg_s + so;
+    uint64_t* sg_t = sl.sg_t + so;
+    int32_t* q_s = sl.q_s + so;
+    int32_t* q_t = sl.q_t + so;
+    int32_t* q_d = sl.q_d + so;
+
+    if (tid == 0) {
+        int32_t s, t;
+        if (!dbg) {
+            uint64_t Us = draw_bounded(a.seed, a.phase, idx, 0, cdf.C);
+            int32_t sr = search_s(cdf, Us);
+            uint64_t cs = cdf.P[sr] - cdf.P[sr - 1];
+            uint64_t Ut = draw_bounded(a.seed, a.phase, idx, 1, cs);
+            int32_t tr = search_t(cdf, sr, Ut);
+            s = cdf.perm[sr];
+            t = cdf.perm[tr];
+        } else {
+            s = dbg_s;
+            t = dbg_t;
+        }
+        sh.s = s;
+        sh.t = t;
+        lv_s[s] = 1; sg_s[s] = 1; q_s[0] = s;
+        lv_t[t] = 1; sg_t[t] = 1; q_t[0] = t;
+        sh.lo_s = 0; sh.hi_s = 1; sh.lo_t = 0; sh.hi_t = 1;
+        sh.a = 0; sh.b = 0;
+        sh.deg_s = (unsigned long long)(g.rp[s + 1] - g.rp[s]);
+        sh.deg_t = (unsigned long long)(g.irp[t + 1] - g.irp[t]);
+        sh.tail_s = 1; sh.tail_t = 1; sh.tail_d = 0;
+        sh.nmeet = 0; sh.status = 0; sh.ovf = 0; sh.walk_err = 0;
+        sh.sigma = 0;
+        cn.V += 0;
+    }
+    level_barrier();
+
+    // ---- balanced bidirectional BFS
+    for (;;) {
+        const int side = (sh.deg_s <= sh.deg_t) ? 0 : 1;
+        __syncthreads();
+        if (tid == 0) {
+            sh.tail = side == 0 ? sh.tail_s : sh.tail_t;
+            sh.deg_next = 0;
+        }
+        __syncthreads();
+        if (side == 0) expand<0>(g, sl, so, sh.lo_s, sh.hi_s, (uint32_t)sh.a + 2, sh, cn);
+        else expand<1>(g, sl, so, sh.lo_t, sh.hi_t, (uint32_t)sh.b + 2, sh, cn);
+        level_barrier();
+        if (tid == 0) {
+            int grown;
+            if (side == 0) {
+                sh.lo_s = sh.hi_s; sh.hi_s = sh.tail; sh.tail_s = sh.tail; sh.a++; sh.deg_s = sh.deg_next;
+                grown = sh.hi_s - sh.lo_s;
+            } else {
+                sh.lo_t = sh.hi_t; sh.hi_t = sh.tail; sh.tail_t = sh.tail; sh.b++; sh.deg_t = sh.deg_next;
+                grown = sh.hi_t - sh.lo_t;
+            }
+            if (sh.nmeet > 0) sh.status = 1;
+            else if (grown == 0) sh.status = 2;
+        }
+        __syncthreads();
+        if (sh.status != 0) break;
+    }
+
+    // ---- meeting layer: sigma_st with overflow detection
+    // After the last level, the meeting layer lies at s-level a and t-level b
+    // (whichever side moved), so d(s,t) = a + b.
+    const int32_t L = sh.a + sh.b;
+    if (sh.status == 1) {
+        if (wid == 0) {
+            uint64_t acc = 0;
+            int of = 0;
+            for (int i = lane; i < sh.nmeet; i += 64) {
+                int32_t w = ldq(q_d + i);
+                uint32_t ls = ld32(lv_s + w), lt = ld32(lv_t + w);
+                of |= ((ls | lt) & OVFBIT) ? 1 : 0;
+                uint64_t x = ld64(sg_s + w), y = ld64(sg_t + w);
+                if (__umul64hi(x, y) != 0) of = 1;
+                uint64_t p = x * y;
+                uint64_t na = acc + p;
+                if (na < acc) of = 1;
+                acc = na;
+                atomicOr(lv_t + w, DAGBIT);
+            }
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) {
+                uint64_t oa = __shfl_xor(acc, o, 64);
+                int oo = __shfl_xor(of, o, 64);
+                uint64_t na = acc + oa;
+                of |= oo | (na < acc ? 1 : 0);
+                acc = na;
+            }
+            if (lane == 0) {
+                sh.sigma = acc;
+                sh.ovf = of;
+                sh.tail = sh.nmeet;
+            }
+        }
+        level_barrier();
+
+        // ---- sigma_s through the t-ball part of the DAG, level by level
+        if (!sh.ovf && sh.b > 0) {
+            int lo = 0, hi = sh.nmeet;
+            for (int j = sh.b; j >= 1; j--) {
+                expand<2>(g, sl, so, lo, hi, (uint32_t)j, sh, cn);
+                level_barrier();
+                lo = hi;
+                hi = sh.tail;
+                __syncthreads();
+            }
+        }
+        if (tid == 0) sh.tail_d = sh.tail;
+
+        // ---- canonical backward walk by wave 0
+        if (!sh.ovf && wid == 0) {
+            const int32_t aM = sh.a;
+            uint64_t r = dbg ? dbg_r : draw_bounded(a.seed, a.phase, idx, 2, sh.sigma);
+            int32_t w = sh.t;
+            int err = 0;
+            for (int32_t p = L - 1; p >= 1; p--) {
+                const int32_t beg = g.irp[w], end = g.irp[w + 1];
+                int32_t sel = -1;
+                for (int32_t base = beg; base < end; base += 64) {
+                    const int32_t i = base + lane;
+                    int32_t u = -1;
+                    uint64_t wt = 0;
+                    if (i < end) {
+                        u = g.icol[i];
+                        if (p <= aM) {
+                            if ((ld32(lv_s + u) & LVMASK) == (uint32_t)p + 1) wt = ld64(sg_s + u);
+                        } else {
+                            if ((ld32(lv_t + u) & LVMASK) == (uint32_t)(L - p) + 1) wt = ld64(sg_s + u);
+                        }
+                        cn.E++;
+                    }
+                    const uint64_t incl = wave_incl_scan_u64(wt);
+                    const uint64_t tot = __shfl(incl, 63, 64);
+                    if (r < tot) {
+                        const unsigned long long m = __ballot(incl > r);
+                        const int l = __ffsll((long long)m) - 1;
+                        const uint64_t ex = __shfl(incl - wt, l, 64);
+                        sel = __shfl(u, l, 64);
+                        r -= ex;
+                        break;
+                    }
+                    r -= tot;
+                }
+                if (sel < 0) { err = 1; break; }
+                w = sel;
+                if (lane == 0) {
+                    if (dbg) {
+                        if (p < dbg_cap) dbg->path[p] = w;
+                    } else {
+                        atomicAdd(a.hits + w, 1u);
+                    }
+                    cn.V++;
+                }
+            }
+            if (lane == 0) sh.walk_err = err;
+        }
+    } else {
+        if (tid == 0) sh.tail_d = 0;
+    }
+    __syncthreads();
+
+    // ---- per-sample statistics
+    if (tid == 0) {
+        sh.n_samples++;
+        if (sh.status == 1) {
+            if (sh.ovf || sh.walk_err) {
+                sh.n_ovf++;
+                if (idx < sh.first_ovf) sh.first_ovf = idx;
+            } else {
+                const unsigned long long I = (unsigned long long)(L - 1);
+                sh.n_reach++;
+                sh.sum_I += I;
+                sh.sum_I2 += I * I;
+            }
+        }
+        if (dbg) {
+            dbg->L = sh.status == 1 ? L : -1;
+            dbg->overflow = (sh.status == 1 && (sh.ovf || sh.walk_err)) ? (sh.walk_err ? 2 : 1) : 0;
+            dbg->sigma = sh.status == 1 ? (sh.ovf ? ~0ull : sh.sigma) : 0;
+            if (sh.status == 1 && L < dbg_cap) {
+                dbg->path[0] = sh.s;
+                dbg->path[L] = sh.t;
+            }
+        }
+    }
+
+    // ---- clear what this sample touched
+    const int ts = sh.tail_s, tt = sh.tail_t, td = sh.tail_d;
+    for (int i = tid; i < ts; i += BS) {
+        int32_t w = ldq(q_s + i);
+        lv_s[w] = 0;
+        sg_s[w] = 0;
+    }
+    for (int i = tid; i < tt; i += BS) {
+        int32_t w = ldq(q_t + i);
+        lv_t[w] = 0;
+        sg_t[w] = 0;
+    }
+    for (int i = tid; i < td; i += BS) {
+        int32_t w = ldq(q_d + i);
+        sg_s[w] = 0;
+    }
+    level_barrier();
+}
+
+__device__ void flush_counters(const Counters& cn, DevStats* st) {
+    unsigned long long E = cn.E, A = cn.A, V = cn.V, Vd = cn.Vd;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        E += __shfl_xor(E, o, 64);
+        A += __shfl_xor(A, o, 64);
+        V += __shfl_xor(V, o, 64);
+        Vd += __shfl_xor(Vd, o, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        atomicAdd(&st->edges, E);
+        atomicAdd(&st->sigma_adds, A);
+        atomicAdd(&st->vexp, V);
+        atomicAdd(&st->vdisc, Vd);
+    }
+}
+
+__global__ __launch_bounds__(BS) void sampler_kernel(DevGraph g, DevCdf cdf, DevSlots sl, SampleLaunch a) {
+    __shared__ SampleShared sh;
+    const int tid = threadIdx.x;
+    const int64_t so = (int64_t)blockIdx.x * sl.stride;
+    Counters cn = {0, 0, 0, 0};
+    if (tid == 0) {
+        sh.n_samples = sh.n_reach = sh.sum_I = sh.sum_I2 = sh.n_ovf = 0;
+        sh.first_ovf = ~0ull;
+    }
+    for (;;) {
+        if (tid == 0) sh.idx = atomicAdd(a.work, 1ull);
+        __syncthreads();
+        const unsigned long long q = sh.idx;
+        if (q >= a.count) break;
+        run_sample(g, cdf, sl, so, a.first + q, a, sh, cn, nullptr, 0, 0, 0, 0);
+    }
+    flush_counters(cn, a.stats);
+    if (tid == 0) {
+        atomicAdd(&a.stats->samples, sh.n_samples);
+        atomicAdd(&a.stats->reachable, sh.n_reach);
+        atomicAdd(&a.stats->sum_I, sh.sum_I);
+        atomicAdd(&a.stats->sum_I2, sh.sum_I2);
+        atomicAdd(&a.stats->overflow, sh.n_ovf);
+        atomicMin(&a.stats->first_overflow, sh.first_ovf);
+    }
+}
+
+__global__ __launch_bounds__(BS) void debug_path_kernel(DevGraph g, DevSlots sl, int32_t s, int32_t t, uint64_t r,
+                                                        DebugOut* out, int32_t cap) {
+    __shared__ SampleShared sh;
+    Counters cn = {0, 0, 0, 0};
+    if (threadIdx.x == 0) {
+        sh.n_samples = sh.n_reach = sh.sum_I = sh.sum_I2 = sh.n_ovf = 0;
+        sh.first_ovf = ~0ull;
+    }
+    __syncthreads();
+    DevCdf none = {};
+    SampleLaunch a = {};
+    run_sample(g, none, sl, 0, 0, a, sh, cn, out, s, t, r, cap);
+}
+
+__global__ void fill_u32_kernel(uint32_t* p, uint32_t v, int64_t count) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+__global__ void fill_u8_kernel(uint8_t* p, int64_t bytes) {
+    const int64_t words = bytes / 16;
+    uint4* p4 = (uint4*)p;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < words; i += (int64_t)gridDim.x * blockDim.x)
+        p4[i] = make_uint4(0, 0, 0, 0);
+    for (int64_t i = words * 16 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < bytes;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0;
+}
+
+__global__ void init_stats_kernel(DevStats* st, unsigned long long* work) {
+    if (threadIdx.x == 0) {
+        st->samples = st->reachable = st->sum_I = st->sum_I2 = st->overflow = 0;
+        st->first_overflow = ~0ull;
+        st->edges = st->sigma_adds = st->vexp = st->vdisc = 0;
+        *work = 0;
+    }
+}
+
+static int fill_grid(int64_t n) {
+    int64_t b = (n + 255) / 256;
+    if (b < 1) b = 1;
+    if (b > 4096) b = 4096;
+    return (int)b;
+}
+
+hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t count, hipStream_t stream) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(fill_u32_kernel, dim3(fill_grid(count)), dim3(256), 0, stream, p, v, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_u8(void* p, int64_t bytes, hipStream_t stream) {
+    if (bytes <= 0) return hipSuccess;
+    hipLaunchKernelGGL(fill_u8_kernel, dim3(fill_grid(bytes / 16 + 1)), dim3(256), 0, stream, (uint8_t*)p, bytes);
+    return hipGetLastError();
+}
+
+hipError_t launch_init_stats(DevStats* st, unsigned long long* work, hipStream_t stream) {
+    hipLaunchKernelGGL(init_stats_kernel, dim3(1), dim3(64), 0, stream, st, work);
+    return hipGetLastError();
+}
+
+hipError_t launch_sampler(const DevGraph& g, const DevCdf& cdf, const DevSlots& slots, const SampleLaunch& a,
+                          hipStream_t stream) {
+    if (a.count == 0 || a.slots <= 0) return hipSuccess;
+    hipLaunchKernelGGL(sampler_kernel, dim3(a.slots), dim3(BS), 0, stream, g, cdf, slots, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_debug_path(const DevGraph& g, const DevSlots& slots, int32_t s, int32_t t, uint64_t r,
+                             DebugOut* out, int32_t cap, hipStream_t stream) {
+    hipLaunchKernelGGL(debug_path_kernel, dim3(1), dim3(BS), 0, stream, g, slots, s, t, r, out, cap);
+    return hipGetLastError();
+}
+
+}  // namespace percis

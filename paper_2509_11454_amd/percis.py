@@ -1,0 +1,208 @@
+"""Python binding of libpercis (the C ABI in include/percis.h).
+
+Argument marshalling only: every step of the sampler runs in the HIP
+library. torch provides device memory (tensors whose data pointers are
+passed with PERCIS_DEVICE_PTRS) and the stream (torch's current stream).
+Importing this module fails loudly if the library has not been built.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+import torch  # loaded first: libpercis then binds to the same HIP runtime
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "lib", "libpercis.so")
+
+HOST_ONLY = -1
+OK, E_INVAL, E_STATE, E_NOMEM, E_DEVICE, E_DEGENERATE, E_TOO_LARGE, E_SIGMA_OVERFLOW = 0, -1, -2, -3, -4, -5, -6, -7
+DIRECTED, DEVICE_PTRS, ACCUMULATE = 0x1, 0x2, 0x4
+OPT_SLOTS, OPT_SCRATCH_MB = 1, 2
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError("libpercis.so is not built (%s); run __graft_entry__.build() or "
+                      "python -m paper_2509_11454_amd.build" % LIB_PATH)
+
+_lib = C.CDLL(LIB_PATH)
+
+
+class Stats(C.Structure):
+    _fields_ = [("samples", C.c_uint64), ("reachable", C.c_uint64), ("sum_I", C.c_uint64),
+                ("sum_I2", C.c_uint64), ("overflow", C.c_uint64), ("first_overflow", C.c_uint64),
+                ("edges", C.c_uint64), ("sigma_adds", C.c_uint64), ("vertices_expanded", C.c_uint64),
+                ("vertices_discovered", C.c_uint64), ("kernel_ms", C.c_double)]
+
+    def to_dict(self):
+        return {k: (float(getattr(self, k)) if t is C.c_double else int(getattr(self, k)))
+                for k, t in self._fields_}
+
+
+class EstimateInfo(C.Structure):
+    _fields_ = [("l1", C.c_uint64), ("l", C.c_uint64), ("D", C.c_int64), ("d_hat", C.c_double),
+                ("rho_tilde", C.c_double), ("Lambda", C.c_double), ("rho_hat", C.c_double),
+                ("v_hat", C.c_double), ("x_hat", C.c_double), ("phase1_ms", C.c_double),
+                ("bounds_ms", C.c_double), ("phase2_ms", C.c_double), ("total_ms", C.c_double),
+                ("overflow", C.c_uint64)]
+
+    def to_dict(self):
+        return {k: (float(getattr(self, k)) if t is C.c_double else int(getattr(self, k)))
+                for k, t in self._fields_}
+
+
+_P = C.c_void_p
+_SIGS = {
+    "percis_create": (C.c_int, [C.c_int, _P, C.POINTER(_P)]),
+    "percis_destroy": (None, [_P]),
+    "percis_set_stream": (C.c_int, [_P, _P]),
+    "percis_load_csr": (C.c_int, [_P, C.c_int32, C.c_int64, _P, _P, C.c_uint32]),
+    "percis_set_states": (C.c_int, [_P, _P, C.c_uint32]),
+    "percis_sample_range": (C.c_int, [_P, C.c_uint64, C.c_uint64, C.c_uint64, C.c_uint32, _P, C.c_uint32,
+                                      C.POINTER(Stats)]),
+    "percis_sample": (C.c_int, [_P, C.c_uint64, C.c_uint64, _P, C.c_uint32, C.POINTER(Stats)]),
+    "percis_estimate": (C.c_int, [_P, C.c_double, C.c_double, C.c_uint64, _P, C.POINTER(EstimateInfo)]),
+    "percis_set_vertex_diameter": (C.c_int, [_P, C.c_int64]),
+    "percis_debug_path": (C.c_int, [_P, C.c_int32, C.c_int32, C.c_uint64, _P, C.c_int32,
+                                    C.POINTER(C.c_int32), C.POINTER(C.c_uint64), C.POINTER(C.c_int32)]),
+    "percis_set_option": (C.c_int, [_P, C.c_int, C.c_int64]),
+    "percis_get_option": (C.c_int, [_P, C.c_int, C.POINTER(C.c_int64)]),
+    "percis_status_str": (C.c_char_p, [C.c_int]),
+    "percis_last_error": (C.c_char_p, [_P]),
+}
+for _name, (_res, _args) in _SIGS.items():
+    _f = getattr(_lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+EXPORTED = tuple(_SIGS)
+
+
+class PercisError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__("%s (%d): %s" % (_lib.percis_status_str(status).decode(), status, message))
+        self.status = status
+
+
+def _np_ptr(a):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+class Context:
+    """One library context on one device; owns the device copies of a graph,
+    its states and the sampler scratch."""
+
+    def __init__(self, device=0, stream=None):
+        """device = HOST_ONLY gives a context that validates inputs and builds
+        host-side structures but never touches a GPU."""
+        self.device = int(device)
+        h = C.c_void_p()
+        if self.device == HOST_ONLY:
+            self._stream = None
+            rc = _lib.percis_create(HOST_ONLY, None, C.byref(h))
+        else:
+            if not torch.cuda.is_available():
+                raise RuntimeError("no HIP device visible: the PercIS sampler runs on the GPU only")
+            torch.cuda.set_device(self.device)
+            if stream is None:
+                stream = torch.cuda.current_stream(self.device)
+            self._stream = stream
+            rc = _lib.percis_create(self.device, C.c_void_p(stream.cuda_stream), C.byref(h))
+        if rc != OK:
+            raise PercisError(rc, "percis_create failed")
+        self._h = h
+        self.n = 0
+        self.directed = False
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.percis_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc, allow=()):
+        if rc != OK and rc not in allow:
+            raise PercisError(rc, _lib.percis_last_error(self._h).decode())
+        return rc
+
+    def set_stream(self, stream):
+        self._stream = stream
+        return self._check(_lib.percis_set_stream(self._h, C.c_void_p(stream.cuda_stream)))
+
+    def load_csr(self, n, row_ptr, col, directed=False):
+        """row_ptr/col: numpy arrays (host) or int32 torch tensors on this device."""
+        flags = DIRECTED if directed else 0
+        if isinstance(row_ptr, torch.Tensor):
+            assert row_ptr.is_cuda and col.is_cuda and row_ptr.dtype == torch.int32 and col.dtype == torch.int32
+            rc = _lib.percis_load_csr(self._h, int(n), int(col.numel()), C.c_void_p(row_ptr.data_ptr()),
+                                      C.c_void_p(col.data_ptr()), flags | DEVICE_PTRS)
+        else:
+            rp = np.ascontiguousarray(row_ptr, dtype=np.int32)
+            cl = np.ascontiguousarray(col, dtype=np.int32)
+            rc = _lib.percis_load_csr(self._h, int(n), int(cl.size), _np_ptr(rp), _np_ptr(cl), flags)
+        self._check(rc)
+        self.n = int(n)
+        self.directed = bool(directed)
+
+    def set_states(self, k):
+        if isinstance(k, torch.Tensor):
+            assert k.is_cuda and k.dtype in (torch.int16, torch.uint16)
+            return self._check(_lib.percis_set_states(self._h, C.c_void_p(k.data_ptr()), DEVICE_PTRS))
+        kk = np.ascontiguousarray(k, dtype=np.uint16)
+        return self._check(_lib.percis_set_states(self._h, _np_ptr(kk), 0))
+
+    def sample_range(self, first, count, seed, phase=0, hits=None, accumulate=False, allow_overflow=False):
+        """Returns (hits, stats dict). hits: None (a new int32 device tensor is
+        returned, holding the uint32 counts), a torch int32 device tensor, or a
+        numpy uint32 array (host)."""
+        st = Stats()
+        flags = ACCUMULATE if accumulate else 0
+        if hits is None:
+            hits = torch.zeros(self.n, dtype=torch.int32, device="cuda:%d" % self.device)
+        if isinstance(hits, torch.Tensor):
+            assert hits.is_cuda and hits.dtype == torch.int32 and hits.numel() >= self.n
+            rc = _lib.percis_sample_range(self._h, int(first), int(count), int(seed), int(phase),
+                                          C.c_void_p(hits.data_ptr()), flags | DEVICE_PTRS, C.byref(st))
+        else:
+            assert hits.dtype == np.uint32 and hits.size >= self.n and hits.flags.c_contiguous
+            rc = _lib.percis_sample_range(self._h, int(first), int(count), int(seed), int(phase),
+                                          _np_ptr(hits), flags, C.byref(st))
+        self._check(rc, allow=(E_SIGMA_OVERFLOW,) if allow_overflow else ())
+        return hits, st.to_dict()
+
+    def sample(self, n_samples, seed, hits=None):
+        return self.sample_range(0, n_samples, seed, 0, hits)
+
+    def estimate(self, eps, delta, seed):
+        p = np.zeros(self.n, np.float64)
+        info = EstimateInfo()
+        self._check(_lib.percis_estimate(self._h, float(eps), float(delta), int(seed), _np_ptr(p), C.byref(info)))
+        return p, info.to_dict()
+
+    def set_vertex_diameter(self, D):
+        return self._check(_lib.percis_set_vertex_diameter(self._h, int(D)))
+
+    def debug_path(self, s, t, r, cap=None):
+        cap = self.n + 1 if cap is None else cap
+        buf = np.zeros(max(cap, 1), np.int32)
+        L, sig, ovf = C.c_int32(), C.c_uint64(), C.c_int32()
+        self._check(_lib.percis_debug_path(self._h, int(s), int(t), int(r), _np_ptr(buf), int(cap),
+                                           C.byref(L), C.byref(sig), C.byref(ovf)))
+        L, sig, ovf = int(L.value), int(sig.value), int(ovf.value)
+        path = [int(v) for v in buf[:L + 1]] if (L >= 0 and not ovf and r < sig and L + 1 <= cap) else None
+        return L, sig, ovf, path
+
+    def set_option(self, opt, value):
+        return self._check(_lib.percis_set_option(self._h, int(opt), int(value)))
+
+    def get_option(self, opt):
+        v = C.c_int64()
+        self._check(_lib.percis_get_option(self._h, int(opt), C.byref(v)))
+        return int(v.value)
+
+
+def raw_library():
+    return _lib

@@ -1,0 +1,123 @@
+"""CPU-only checks of the C ABI: the library loads and exports every symbol
+that include/percis.h declares, and the host-side logic (validation, call
+order, degenerate states, size limits) behaves as the header documents,
+through a host-only context that makes no HIP call."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "percis.h")
+LIB = os.path.join(ROOT, "paper_2509_11454_amd", "lib", "libpercis.so")
+
+pytestmark = pytest.mark.skipif(not os.path.exists(LIB), reason="libpercis.so not built")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(percis_[a-z_]+)\s*\(", text)))
+
+
+def test_exports_every_declared_symbol():
+    lib = C.CDLL(LIB)
+    names = declared_functions()
+    assert len(names) >= 14
+    for name in names:
+        assert hasattr(lib, name), name
+    out = os.popen("nm -D --defined-only %s" % LIB).read()
+    for name in names:
+        assert re.search(r"\bT %s\b" % name, out), name
+
+
+@pytest.fixture(scope="module")
+def P():
+    from paper_2509_11454_amd import percis
+    return percis
+
+
+def ctx(P):
+    return P.Context(P.HOST_ONLY)
+
+
+def test_binding_names_match_header(P):
+    assert set(P.EXPORTED) == set(declared_functions())
+
+
+def test_host_only_valid_graph_and_states(P):
+    c = ctx(P)
+    g, k = W.workload_er1000()
+    c.load_csr(g.n, g.row_ptr, g.col)
+    c.set_states(k)
+    with pytest.raises(P.PercisError) as e:
+        c.sample(10, 1, hits=np.zeros(g.n, np.uint32))
+    assert e.value.status == P.E_STATE
+
+
+@pytest.mark.parametrize("case", ["nonmonotone", "range", "selfloop", "dup", "asym", "rp0", "rpn"])
+def test_csr_validation(P, case):
+    c = ctx(P)
+    n = 4
+    rp = np.array([0, 1, 2, 3, 4], np.int32)
+    col = np.array([1, 0, 3, 2], np.int32)
+    c.load_csr(n, rp, col)  # valid: two edges
+    if case == "nonmonotone":
+        rp = np.array([0, 2, 1, 3, 4], np.int32)
+    elif case == "range":
+        col = np.array([1, 0, 3, 7], np.int32)
+    elif case == "selfloop":
+        col = np.array([0, 0, 3, 2], np.int32)
+    elif case == "dup":
+        rp = np.array([0, 2, 3, 4, 5], np.int32)
+        col = np.array([1, 1, 0, 3, 2], np.int32)
+    elif case == "asym":
+        col = np.array([1, 0, 3, 1], np.int32)
+    elif case == "rp0":
+        rp = np.array([1, 1, 2, 3, 4], np.int32)
+    elif case == "rpn":
+        rp = np.array([0, 1, 2, 3, 3], np.int32)
+    with pytest.raises(P.PercisError) as e:
+        c.load_csr(n, rp, col)
+    assert e.value.status == P.E_INVAL
+
+
+def test_directed_asymmetric_ok_and_unsorted_rows(P):
+    c = ctx(P)
+    rp = np.array([0, 2, 2, 3], np.int32)
+    col = np.array([2, 1, 0], np.int32)   # row 0 unsorted
+    c.load_csr(3, rp, col, directed=True)
+    with pytest.raises(P.PercisError):
+        c.load_csr(3, rp, col, directed=False)
+
+
+def test_call_order_and_degenerate(P):
+    c = ctx(P)
+    with pytest.raises(P.PercisError) as e:
+        c.set_states(np.zeros(3, np.uint16))
+    assert e.value.status == P.E_STATE
+    g = W.path_graph(5)
+    c.load_csr(g.n, g.row_ptr, g.col)
+    with pytest.raises(P.PercisError) as e:
+        c.set_states(np.full(5, 777, np.uint16))
+    assert e.value.status == P.E_DEGENERATE
+    c.set_states(np.array([1, 0, 0, 0, 0], np.uint16))
+
+
+def test_too_large(P):
+    c = ctx(P)
+    rp = np.zeros(2, np.int32)
+    lib = P.raw_library()
+    rc = lib.percis_load_csr(c._h, (1 << 25) + 1, 0, rp.ctypes.data_as(C.c_void_p), None, 0)
+    assert rc == P.E_TOO_LARGE
+
+
+def test_status_strings(P):
+    lib = P.raw_library()
+    for code in range(0, -8, -1):
+        assert lib.percis_status_str(code)
+    assert lib.percis_status_str(-99) == b"unknown status"
