@@ -102,7 +102,13 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-estimate", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB (reference for HBM counters)")
     args = ap.parse_args()
+
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
 
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (samples would be sharded by index "
@@ -196,6 +202,24 @@ def main():
         print("[bench] cpu baseline: %.1f samples/s" % out["cpu_baseline"]["value"], file=sys.stderr, flush=True)
 
     print(json.dumps(out), flush=True)
+
+
+def copy_calibration(mib):
+    """A plain copy kernel of known size: reads and writes mib MiB once. Its
+    FETCH_SIZE / WRITE_SIZE readings calibrate the counters of the sampler."""
+    import torch
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.int32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    print(json.dumps({"copy_mib": mib, "read_bytes": n * 4, "write_bytes": n * 4, "seconds": dt,
+                      "gbs": 2 * n * 4 / dt / 1e9}), flush=True)
 
 
 def host_cpu_model():
