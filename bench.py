@@ -99,6 +99,8 @@ def main():
     ap.add_argument("--samples", type=int, default=0, help="samples per step (default: the workload's)")
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--slots", type=int, default=0)
+    ap.add_argument("--block", type=int, default=0)
+    ap.add_argument("--bitmaps", type=int, default=0, help="0 auto, 1 device memory, 2 LDS")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-estimate", action="store_true")
@@ -129,8 +131,9 @@ def main():
           file=sys.stderr, flush=True)
 
     c = P.Context(0)
-    if args.slots:
-        c.set_option(P.OPT_SLOTS, args.slots)
+    c.set_option(P.OPT_SLOTS, args.slots)
+    c.set_option(P.OPT_BLOCK, args.block)
+    c.set_option(P.OPT_BITMAPS, args.bitmaps)
     c.load_csr(g.n, g.row_ptr, g.col, directed=g.directed)
     c.set_states(k)
     hits = torch.zeros(g.n, dtype=torch.int32, device="cuda")
@@ -158,6 +161,8 @@ def main():
     achieved = b_alg / avg_kernel_s / 1e9
     traffic = measured_traffic(args.workload, samples)
     slots = c.get_option(P.OPT_SLOTS)
+    block = c.get_option(P.OPT_BLOCK)
+    bitmaps = "lds" if c.get_option(P.OPT_BITMAPS) == 2 else "device"
 
     out = {
         "metric": METRIC,
@@ -173,7 +178,8 @@ def main():
         "dtype": "u64",
         "data": "synthetic",
         "config": {"workload": "%s: %s" % (args.workload, desc), "n": g.n, "m_arcs": g.m,
-                   "samples_per_step": samples, "seed": args.seed, "slots": slots},
+                   "samples_per_step": samples, "seed": args.seed, "slots": slots,
+                   "threads_per_sample": block, "bitmaps": bitmaps},
         "gteps": totals["edges"] / elapsed / 1e9,
         "edges_per_sample": totals["edges"] / (samples * args.steps),
         "reachable_fraction": totals["reachable"] / (samples * args.steps),

@@ -165,9 +165,16 @@ int percis_debug_path(percis_ctx* ctx, int32_t s, int32_t t, uint64_t r, int32_t
 
 /* Tuning knobs (launch shape only; results never depend on them).
  * PERCIS_OPT_SLOTS: concurrent samples (resident workgroups), 0 = auto.
- * PERCIS_OPT_SCRATCH_MB: cap on per-slot scratch memory, 0 = auto. */
+ * PERCIS_OPT_SCRATCH_MB: cap on the sampler's scratch memory, 0 = auto.
+ * PERCIS_OPT_BLOCK: threads per sample (256, 512 or 1024), 0 = auto.
+ * PERCIS_OPT_BITMAPS: where the visited bitmaps live: 0 = auto (LDS when
+ * they fit), 1 = device memory, 2 = LDS (PERCIS_E_INVAL if they do not fit).
+ * Reading PERCIS_OPT_SLOTS, _BLOCK or _BITMAPS after a graph is loaded gives
+ * the shape in use (BITMAPS then reads 1 or 2). */
 #define PERCIS_OPT_SLOTS       1
 #define PERCIS_OPT_SCRATCH_MB  2
+#define PERCIS_OPT_BLOCK       3
+#define PERCIS_OPT_BITMAPS     4
 int percis_set_option(percis_ctx* ctx, int option, int64_t value);
 int percis_get_option(percis_ctx* ctx, int option, int64_t* value);
 

@@ -33,8 +33,11 @@ struct percis_ctx {
     bool has_graph = false, directed = false;
     int32_t n = 0;
     int64_t m = 0;
-    std::vector<int32_t> h_rp, h_col;      // sorted host copy
+    int32_t n_act = 0;                     // nodes with at least one arc (internal ids 0..n_act-1)
+    std::vector<int32_t> h_rp, h_col;      // out-adjacency in internal ids, rows sorted
     std::vector<int32_t> h_irp, h_icol;    // in-adjacency (directed graphs only)
+    std::vector<int32_t> h_orig, h_newid;  // internal id -> caller id, and back
+    int32_t* d_orig = nullptr;
     bool graph_on_device = false;
     int32_t *d_rp = nullptr, *d_col = nullptr, *d_irp = nullptr, *d_icol = nullptr;
 
@@ -66,7 +69,8 @@ struct percis_ctx {
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
 
     int64_t D_override = -1;
-    int64_t opt_slots = 0, opt_scratch_mb = 0;
+    int64_t opt_slots = 0, opt_scratch_mb = 0, opt_block = 0, opt_bitmaps = 0;
+    SamplerShape shape{};
 };
 
 namespace {
@@ -138,6 +142,9 @@ void free_graph(percis_ctx* c) {
     dfree(c->d_rp);
     dfree(c->d_col);
     dfree(c->d_hits);
+    dfree(c->d_orig);
+    c->h_orig.clear();
+    c->h_newid.clear();
     c->h_rp.clear();
     c->h_col.clear();
     c->h_irp.clear();
@@ -172,6 +179,8 @@ int ensure_graph_device(percis_ctx* c) {
             c->d_icol = c->d_col;
         }
         if ((rc = dalloc(c, c->d_hits, (size_t)n))) return rc;
+        if ((rc = dalloc(c, c->d_orig, (size_t)n))) return rc;
+        HIPCHK(c, hipMemcpy(c->d_orig, c->h_orig.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice));
         c->graph_on_device = true;
     }
     return PERCIS_OK;
@@ -197,22 +206,32 @@ int ensure_device(percis_ctx* c) {
 }
 
 constexpr int64_t kSlotBytesPerNode = 4 + 4 + 8 + 8 + 4 + 4 + 4;
+constexpr int64_t kLdsPerCu = 160 * 1024;
 
-// Allocates (once per graph) the per-slot scratch: enough resident
-// workgroups to fill every CU, capped by a memory budget.
+// Picks the launch shape and allocates (once per graph) the per-slot
+// scratch: one slot per resident workgroup, capped by a memory budget.
 int ensure_slots(percis_ctx* c) {
     if (c->slot_mem) return PERCIS_OK;
-    const int64_t stride = ((int64_t)c->n + 63) / 64 * 64;
-    const int64_t per_slot = stride * kSlotBytesPerNode;
+    const int64_t act = std::max<int32_t>(c->n_act, 1);
+    const int64_t stride = (act + 63) / 64 * 64;
+    const int64_t words = ((act + 31) / 32 + 63) / 64 * 64;
+    SamplerShape sh{};
+    sh.block = c->opt_block ? (int)c->opt_block : 1024;
+    const int64_t lds_need = 3 * words * 4;
+    const bool fits = lds_need + sampler_static_lds() <= kLdsPerCu;
+    if (c->opt_bitmaps == 2 && !fits) return fail(c, PERCIS_E_INVAL, "bitmaps of %lld nodes do not fit in LDS", (long long)act);
+    sh.lds_bitmaps = c->opt_bitmaps == 2 || (c->opt_bitmaps == 0 && fits);
+    sh.lds_bytes = sh.lds_bitmaps ? lds_need : 0;
+    const int occ = sampler_occupancy(sh);
+    if (occ <= 0) return fail(c, PERCIS_E_DEVICE, "sampler shape (block %d, %s bitmaps) cannot launch", sh.block,
+                              sh.lds_bitmaps ? "LDS" : "global");
+    const int64_t per_slot = stride * kSlotBytesPerNode + (sh.lds_bitmaps ? 0 : 3 * words * 4);
     size_t free_b = 0, total_b = 0;
     HIPCHK(c, hipMemGetInfo(&free_b, &total_b));
-    int64_t budget = c->opt_scratch_mb > 0 ? c->opt_scratch_mb * (1ll << 20)
-                                           : std::min<int64_t>((int64_t)free_b / 2, 48ll << 30);
-    int64_t want = c->opt_slots > 0 ? c->opt_slots : (int64_t)std::max(c->cu_count, 1) * 8;
-    int64_t fit = budget / per_slot;
-    int64_t ns = std::max<int64_t>(1, std::min(want, fit));
-    if (c->opt_slots > 0 && ns < c->opt_slots && fit < c->opt_slots)
-        ns = std::max<int64_t>(1, fit);
+    const int64_t budget = c->opt_scratch_mb > 0 ? c->opt_scratch_mb * (1ll << 20)
+                                                 : std::min<int64_t>((int64_t)free_b / 2, 48ll << 30);
+    const int64_t want = c->opt_slots > 0 ? c->opt_slots : (int64_t)std::max(c->cu_count, 1) * occ;
+    int64_t ns = std::max<int64_t>(1, std::min(want, budget / per_slot));
     void* mem = nullptr;
     hipError_t e = hipErrorOutOfMemory;
     while (ns >= 1) {
@@ -222,14 +241,14 @@ int ensure_slots(percis_ctx* c) {
         ns /= 2;
     }
     if (e != hipSuccess || !mem) return fail(c, PERCIS_E_NOMEM, "cannot allocate sampler scratch");
-    int rc_fill = launch_fill_u8(mem, ns * per_slot, c->stream) == hipSuccess ? 0 : 1;
-    if (rc_fill) {
+    if (launch_fill_u8(mem, ns * per_slot, c->stream) != hipSuccess) {
         (void)hipFree(mem);
         return fail(c, PERCIS_E_DEVICE, "scratch clear failed");
     }
     char* p = (char*)mem;
     DevSlots s{};
     s.stride = stride;
+    s.words = words;
     const int64_t cnt = ns * stride;
     s.lv_s = (uint32_t*)p; p += cnt * 4;
     s.lv_t = (uint32_t*)p; p += cnt * 4;
@@ -238,16 +257,20 @@ int ensure_slots(percis_ctx* c) {
     s.q_s = (int32_t*)p; p += cnt * 4;
     s.q_t = (int32_t*)p; p += cnt * 4;
     s.q_d = (int32_t*)p; p += cnt * 4;
+    s.bm = sh.lds_bitmaps ? nullptr : (uint32_t*)p;
     c->slot_mem = mem;
     c->slots = s;
     c->nslots = (int)ns;
     c->slot_stride = stride;
+    c->shape = sh;
     return PERCIS_OK;
 }
 
 DevGraph dev_graph(const percis_ctx* c) {
     DevGraph g;
     g.n = c->n;
+    g.n_act = c->n_act;
+    g.orig = c->d_orig;
     g.rp = c->d_rp;
     g.col = c->d_col;
     g.irp = c->d_irp;
@@ -371,7 +394,7 @@ int run_sampler(percis_ctx* c, uint64_t first, uint64_t count, uint64_t seed, ui
     a.work = c->d_work;
     a.slots = (int)std::min<uint64_t>((uint64_t)c->nslots, std::max<uint64_t>(count, 1));
     HIPCHK(c, hipEventRecord(c->ev0, c->stream));
-    HIPCHK(c, launch_sampler(dev_graph(c), dev_cdf(c), c->slots, a, c->stream));
+    HIPCHK(c, launch_sampler(dev_graph(c), dev_cdf(c), c->slots, a, c->shape, c->stream));
     HIPCHK(c, hipEventRecord(c->ev1, c->stream));
     DevStats hs{};
     HIPCHK(c, hipMemcpyAsync(&hs, c->d_stats, sizeof hs, hipMemcpyDeviceToHost, c->stream));
@@ -516,7 +539,31 @@ int percis_load_csr(percis_ctx* c, int32_t n, int64_t m, const int32_t* row_ptr,
                 if (!std::binary_search(cl.data() + rp[v], cl.data() + rp[v + 1], u))
                     return fail(c, PERCIS_E_INVAL, "undirected graph lacks arc %d -> %d (reverse of %d -> %d)", v, u, u, v);
             }
-    } else {
+    }
+    // internal ids: nodes with an arc first (in caller order), then the rest
+    std::vector<uint8_t> has_arc(n, 0);
+    for (int32_t u = 0; u < n; u++)
+        if (rp[u + 1] > rp[u]) has_arc[u] = 1;
+    for (int64_t e = 0; e < m; e++) has_arc[cl[e]] = 1;
+    std::vector<int32_t> newid(n), orig(n);
+    int32_t next = 0;
+    for (int32_t v = 0; v < n; v++)
+        if (has_arc[v]) { newid[v] = next; orig[next] = v; next++; }
+    const int32_t n_act = next;
+    for (int32_t v = 0; v < n; v++)
+        if (!has_arc[v]) { newid[v] = next; orig[next] = v; next++; }
+    std::vector<int32_t> irp2(n + 1, 0), icl2((size_t)m);
+    irp2[0] = 0;
+    for (int32_t i = 0; i < n; i++) {
+        const int32_t v = orig[i];
+        irp2[i + 1] = irp2[i] + (rp[v + 1] - rp[v]);
+        int32_t o = irp2[i];
+        for (int32_t e = rp[v]; e < rp[v + 1]; e++) icl2[o++] = newid[cl[e]];
+        // the relabelling keeps the order of nodes with arcs, so rows stay sorted
+    }
+    rp.swap(irp2);
+    cl.swap(icl2);
+    if (directed) {
         // in-adjacency by a counting sort on the head; scanning tails in
         // increasing order keeps every in-row sorted
         std::vector<int32_t> irp(n + 1, 0), icl((size_t)m);
@@ -530,7 +577,10 @@ int percis_load_csr(percis_ctx* c, int32_t n, int64_t m, const int32_t* row_ptr,
     }
     c->h_rp.swap(rp);
     c->h_col.swap(cl);
+    c->h_orig.swap(orig);
+    c->h_newid.swap(newid);
     c->n = n;
+    c->n_act = n_act;
     c->m = m;
     c->directed = directed;
     c->has_graph = true;
@@ -567,6 +617,7 @@ int percis_set_states(percis_ctx* c, const uint16_t* k_in, uint32_t flags) {
     for (int32_t v = 0; v < n; v++) perm[1 + start[65535 - k[v]]++] = v;
     std::vector<uint32_t> kr(n + 2, 0);
     for (int32_t i = 1; i <= n; i++) kr[i] = k[perm[i]];
+    for (int32_t i = 1; i <= n; i++) perm[i] = c->h_newid[perm[i]];  // the device works in internal ids
     std::vector<uint64_t> W(n + 2, 0), P(n + 1, 0);
     for (int32_t i = n; i >= 1; i--) W[i] = W[i + 1] + kr[i];
     for (int32_t i = 1; i <= n; i++) {
@@ -712,7 +763,8 @@ int percis_debug_path(percis_ctx* c, int32_t s, int32_t t, uint64_t r, int32_t* 
         c->dbg_cap = need;
     }
     HIPCHK(c, launch_fill_u8(c->d_dbg, sizeof(DebugOut) + sizeof(int32_t) * need, c->stream));
-    HIPCHK(c, launch_debug_path(dev_graph(c), c->slots, s, t, r, c->d_dbg, cap, c->stream));
+    HIPCHK(c, launch_debug_path(dev_graph(c), c->slots, c->h_newid[s], c->h_newid[t], r, c->d_dbg, cap, c->shape,
+                                c->stream));
     std::vector<char> buf(sizeof(DebugOut) + sizeof(int32_t) * need);
     HIPCHK(c, hipMemcpyAsync(buf.data(), c->d_dbg, buf.size(), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -722,7 +774,7 @@ int percis_debug_path(percis_ctx* c, int32_t s, int32_t t, uint64_t r, int32_t* 
     if (overflow) *overflow = o->overflow;
     if (o->overflow == 2) return fail(c, PERCIS_E_DEVICE, "canonical walk found no predecessor");
     if (path && o->L >= 0 && !o->overflow && r < o->sigma && o->L + 1 <= cap)
-        std::memcpy(path, o->path, sizeof(int32_t) * (o->L + 1));
+        for (int32_t i = 0; i <= o->L; i++) path[i] = c->h_orig[o->path[i]];
     return PERCIS_OK;
 }
 
@@ -732,6 +784,15 @@ int percis_set_option(percis_ctx* c, int option, int64_t value) {
     switch (option) {
         case PERCIS_OPT_SLOTS: c->opt_slots = value; break;
         case PERCIS_OPT_SCRATCH_MB: c->opt_scratch_mb = value; break;
+        case PERCIS_OPT_BLOCK:
+            if (value != 0 && value != 256 && value != 512 && value != 1024)
+                return fail(c, PERCIS_E_INVAL, "block must be 256, 512 or 1024");
+            c->opt_block = value;
+            break;
+        case PERCIS_OPT_BITMAPS:
+            if (value > 2) return fail(c, PERCIS_E_INVAL, "bitmaps option is 0 (auto), 1 (global) or 2 (LDS)");
+            c->opt_bitmaps = value;
+            break;
         default: return fail(c, PERCIS_E_INVAL, "unknown option %d", option);
     }
     if (!c->host_only && set_device(c) == PERCIS_OK) {
@@ -753,6 +814,18 @@ int percis_get_option(percis_ctx* c, int option, int64_t* value) {
             return PERCIS_OK;
         }
         case PERCIS_OPT_SCRATCH_MB: *value = c->opt_scratch_mb; return PERCIS_OK;
+        case PERCIS_OPT_BLOCK:
+        case PERCIS_OPT_BITMAPS: {
+            if (c->host_only || !c->has_graph) {
+                *value = option == PERCIS_OPT_BLOCK ? c->opt_block : c->opt_bitmaps;
+                return PERCIS_OK;
+            }
+            int rc = set_device(c);
+            if (rc) return rc;
+            if ((rc = ensure_slots(c))) return rc;
+            *value = option == PERCIS_OPT_BLOCK ? c->shape.block : (c->shape.lds_bitmaps ? 2 : 1);
+            return PERCIS_OK;
+        }
         default: return fail(c, PERCIS_E_INVAL, "unknown option %d", option);
     }
 }

@@ -6,29 +6,35 @@
 
 namespace percis {
 
-// Device view of the graph: out-adjacency and in-adjacency (the same arrays
-// for an undirected graph), rows sorted by increasing node id.
+// Device view of the graph in internal node ids: nodes with at least one
+// arc get ids 0..n_act-1 in increasing order of the caller's ids, nodes
+// without arcs follow. Relative order among nodes with arcs is kept, so the
+// ascending-id order of predecessors (which fixes the canonical path) is the
+// caller's order. Rows are sorted by increasing id.
 struct DevGraph {
     int32_t n;
-    const int32_t* rp;    // [n+1]
+    int32_t n_act;
+    const int32_t* rp;    // [n+1] out-adjacency
     const int32_t* col;   // [m]
-    const int32_t* irp;   // [n+1]
+    const int32_t* irp;   // [n+1] in-adjacency (same arrays if undirected)
     const int32_t* icol;  // [m]
+    const int32_t* orig;  // [n] internal id -> caller's id
 };
 
 // Device view of the exact integer pair distribution (Algorithm 2 in units
-// of 1/65535): ranks i = 1..n sorted by (k non-increasing, id increasing).
+// of 1/65535): ranks i = 1..n sorted by (k non-increasing, caller id
+// increasing).
 struct DevCdf {
     int32_t n;
     uint64_t C;            // total weight, sum over ordered pairs of R(k_u - k_w)
-    const int32_t* perm;   // [n+1]  perm[i] = node of rank i
+    const int32_t* perm;   // [n+1]  perm[i] = internal id of rank i
     const uint32_t* kr;    // [n+2]  k of rank i
     const uint64_t* W;     // [n+2]  W[i] = sum_{j >= i} kr[j], W[n+1] = 0
     const uint64_t* P;     // [n+1]  P[i] = sum_{j <= i} c_j, c_j = (n-j+1) kr[j] - W[j]
 };
 
-// Per-slot scratch; every array is [slots][stride] and is all-zero between
-// samples (each sample clears what it touched).
+// Per-slot scratch; every array is [slots][stride] (stride >= n_act) and is
+// all-zero between samples (each sample clears what it touched).
 struct DevSlots {
     uint32_t* lv_s;   // s-side level + 1 (0 = unreached), plus flag bits
     uint32_t* lv_t;   // t-side level + 1, plus flag bits
@@ -37,7 +43,9 @@ struct DevSlots {
     int32_t* q_s;     // s-side BFS queue (levels are contiguous segments)
     int32_t* q_t;     // t-side BFS queue
     int32_t* q_d;     // t-side shortest-path DAG, level by level
-    int64_t stride;   // elements per slot (>= n)
+    int64_t stride;   // elements per slot
+    uint32_t* bm;     // visited bitmaps when they do not live in LDS: [slots][3][words]
+    int64_t words;    // 32-bit words per bitmap
 };
 
 // Device-side accumulators of one sampling call.
@@ -48,7 +56,7 @@ struct DevStats {
 
 struct SampleLaunch {
     uint64_t first, count, seed, phase;
-    uint32_t* hits;                  // [n]
+    uint32_t* hits;                  // [n] by caller id
     DevStats* stats;
     unsigned long long* work;        // next unclaimed sample offset
     int slots;                       // grid size
@@ -59,16 +67,26 @@ struct DebugOut {
     int32_t L;
     int32_t overflow;
     uint64_t sigma;
-    int32_t path[1];   // flexible: L+1 entries
+    int32_t path[1];   // flexible: L+1 entries (internal ids)
+};
+
+// Launch shape of the sampler: threads per workgroup and whether the
+// visited bitmaps live in LDS.
+struct SamplerShape {
+    int block;        // 256, 512 or 1024
+    bool lds_bitmaps;
+    int64_t lds_bytes;  // dynamic LDS per workgroup (3 bitmaps) when lds_bitmaps
 };
 
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t count, hipStream_t stream);
 hipError_t launch_fill_u8(void* p, int64_t bytes, hipStream_t stream);
 hipError_t launch_init_stats(DevStats* st, unsigned long long* work, hipStream_t stream);
 hipError_t launch_sampler(const DevGraph& g, const DevCdf& cdf, const DevSlots& slots, const SampleLaunch& a,
-                          hipStream_t stream);
+                          const SamplerShape& shape, hipStream_t stream);
 hipError_t launch_debug_path(const DevGraph& g, const DevSlots& slots, int32_t s, int32_t t, uint64_t r,
-                             DebugOut* out, int32_t cap, hipStream_t stream);
-int sampler_block_size();
+                             DebugOut* out, int32_t cap, const SamplerShape& shape, hipStream_t stream);
+// Resident workgroups per CU for a shape (0 if it cannot launch).
+int sampler_occupancy(const SamplerShape& shape);
+int64_t sampler_static_lds();
 
 }  // namespace percis

@@ -2,19 +2,21 @@
 //
 // One persistent workgroup per slot. A slot owns per-node scratch (levels and
 // shortest-path counts from both ends, three queues) that is all-zero between
-// samples; every sample clears exactly what it touched. Workgroups claim
-// sample indices from a global counter, so the grid can be smaller or larger
-// than the number of samples and results never depend on the launch shape:
-// every sample's randomness is keyed on its index (Philox4x64-10, counter
-// (index, variate, attempt, 0), key (seed, phase)), and all accumulation is
-// integer.
+// samples; every sample clears exactly what it touched. Visited sets are
+// bitmaps -- in LDS when they fit, otherwise in the slot's global scratch --
+// so that the per-edge test touches one bit instead of a level word.
+// Workgroups claim sample indices from a global counter, so the grid can be
+// smaller or larger than the number of samples and results never depend on
+// the launch shape: every sample's randomness is keyed on its index
+// (Philox4x64-10, counter (index, variate, attempt, 0), key (seed, phase)),
+// and all accumulation is integer.
 //
 // Per sample (Algorithm 2 of the paper's appendix, then RandomSP of
 // Section III-B):
 //   1. pair: U_s uniform in [0, C) picks rank s = min{d : U_s < P[d]};
 //      U_t uniform in [0, c_s) picks t = min{d > s : U_t < F_s(d)} with
 //      F_s(d) = (d - s + 1) k_s - (W_s - W_{d+1}); both bounded draws use
-//      Lemire's multiply-and-reject.
+//      Lemire's multiply-and-reject, both searches are 64-way (one wave).
 //   2. balanced bidirectional BFS with shortest-path counting: the side whose
 //      frontier has the smaller degree sum expands one full level, edge-
 //      balanced across the workgroup; the first level that reaches the other
@@ -35,16 +37,13 @@
 
 namespace percis {
 
-constexpr int BS = 256;
-constexpr int NWAVE = BS / 64;
+constexpr int CH = 256;  // frontier nodes staged per chunk
 constexpr uint32_t LVMASK = 0x0FFFFFFFu;
 constexpr uint32_t DAGBIT = 0x20000000u;
 constexpr uint32_t OVFBIT = 0x40000000u;
 
-int sampler_block_size() { return BS; }
-
-// Scratch is shared by the waves of a workgroup and updated with L2 atomics;
-// reads go to L2 as well so that a stale L1 line is never observed.
+// Slot scratch is shared by the waves of a workgroup and updated with L2
+// atomics; reads go to L2 as well so that a stale L1 line is never observed.
 __device__ __forceinline__ uint32_t ld32(uint32_t* p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -54,6 +53,33 @@ __device__ __forceinline__ uint64_t ld64(uint64_t* p) {
 __device__ __forceinline__ int32_t ldq(int32_t* p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+
+// Visited bitmaps: three planes per slot -- s-side visited, t-side visited,
+// and "reached in the level being built" (shared by both sides, since only
+// one side grows at a time).
+template <bool LDS>
+struct Bits {
+    uint32_t* vs;
+    uint32_t* vt;
+    uint32_t* nw;
+    static constexpr int SCOPE = LDS ? __HIP_MEMORY_SCOPE_WORKGROUP : __HIP_MEMORY_SCOPE_AGENT;
+    __device__ __forceinline__ static uint32_t rd(uint32_t* p, int32_t w) {
+        return __hip_atomic_load(p + (w >> 5), __ATOMIC_RELAXED, SCOPE);
+    }
+    __device__ __forceinline__ static uint32_t rd_acq(uint32_t* p, int32_t w) {
+        return __hip_atomic_load(p + (w >> 5), __ATOMIC_ACQUIRE, SCOPE);
+    }
+    __device__ __forceinline__ static uint32_t set(uint32_t* p, int32_t w) {
+        return __hip_atomic_fetch_or(p + (w >> 5), 1u << (w & 31), __ATOMIC_RELAXED, SCOPE);
+    }
+    __device__ __forceinline__ static uint32_t set_rel(uint32_t* p, int32_t w) {
+        return __hip_atomic_fetch_or(p + (w >> 5), 1u << (w & 31), __ATOMIC_ACQ_REL, SCOPE);
+    }
+    __device__ __forceinline__ static bool test(uint32_t word, int32_t w) { return (word >> (w & 31)) & 1u; }
+    __device__ __forceinline__ static void clear_word(uint32_t* p, int32_t w) {
+        __hip_atomic_store(p + (w >> 5), 0u, __ATOMIC_RELAXED, SCOPE);
+    }
+};
 
 // ---------------------------------------------------------------- Philox
 __device__ __forceinline__ uint64_t philox_word0(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3,
@@ -84,33 +110,34 @@ __device__ uint64_t draw_bounded(uint64_t seed, uint64_t phase, uint64_t idx, ui
     }
 }
 
-__device__ int32_t search_s(const DevCdf& c, uint64_t U) {
-    int32_t lo = 1, hi = c.n;
-    while (lo < hi) {
-        int32_t mid = lo + ((hi - lo) >> 1);
-        if (U < c.P[mid]) hi = mid; else lo = mid + 1;
+// Smallest d in [lo, hi] with pred(d), for a monotone pred with pred(hi)
+// true; one wave probes 64 points per step. Wave-uniform arguments.
+template <class Pred>
+__device__ __forceinline__ int32_t wave_search(int32_t lo, int32_t hi, Pred pred) {
+    const int lane = threadIdx.x & 63;
+    while (hi - lo + 1 > 64) {
+        const int64_t len = (int64_t)hi - lo + 1;
+        const int32_t x = lo + (int32_t)(((int64_t)(lane + 1) * len) >> 6) - 1;
+        const unsigned long long m = __ballot(pred(x));
+        const int i = __ffsll((long long)m) - 1;
+        const int32_t nhi = __shfl(x, i, 64);
+        const int32_t prev = __shfl(x, i > 0 ? i - 1 : 0, 64);
+        lo = i > 0 ? prev + 1 : lo;
+        hi = nhi;
     }
-    return lo;
-}
-
-__device__ int32_t search_t(const DevCdf& c, int32_t s, uint64_t U) {
-    const uint64_t ks = c.kr[s], Ws = c.W[s];
-    int32_t lo = s + 1, hi = c.n;
-    while (lo < hi) {
-        int32_t mid = lo + ((hi - lo) >> 1);
-        uint64_t F = (uint64_t)(mid - s + 1) * ks - (Ws - c.W[mid + 1]);
-        if (U < F) hi = mid; else lo = mid + 1;
-    }
-    return lo;
+    const int32_t x = lo + lane;
+    const bool p = (x > hi) || pred(x);
+    const unsigned long long m = __ballot(p);
+    return lo + __ffsll((long long)m) - 1;
 }
 
 // ------------------------------------------------------------ workgroup state
 struct SampleShared {
-    int32_t beg[BS];
-    int32_t off[BS];
-    uint64_t sig[BS];
-    uint32_t of[BS];
-    int32_t wsum[NWAVE];
+    int32_t beg[CH];
+    int32_t off[CH];
+    uint64_t sig[CH];
+    uint8_t of[CH];
+    int32_t wsum[16];
     unsigned long long idx;
     int32_t s, t;
     int32_t lo_s, hi_s, lo_t, hi_t;
@@ -129,19 +156,23 @@ struct Counters {
     unsigned long long E, A, V, Vd;
 };
 
-__device__ __forceinline__ int block_excl_scan(int v, int32_t* wsum, int& total) {
+// Exclusive scan over the first CH threads (the chunk); every thread of the
+// block must call it.
+template <int BSZ>
+__device__ __forceinline__ int chunk_excl_scan(int v, int32_t* wsum, int& total) {
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    constexpr int NW = CH / 64;
     int x = v;
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) {
         int y = __shfl_up(x, o, 64);
         if (lane >= o) x += y;
     }
-    if (lane == 63) wsum[wid] = x;
+    if (lane == 63 && wid < NW) wsum[wid] = x;
     __syncthreads();
     int pre = 0, tot = 0;
 #pragma unroll
-    for (int i = 0; i < NWAVE; i++) {
+    for (int i = 0; i < NW; i++) {
         int s = wsum[i];
         if (i < wid) pre += s;
         tot += s;
@@ -161,28 +192,34 @@ __device__ __forceinline__ uint64_t wave_incl_scan_u64(uint64_t v) {
 }
 
 // One level of work over the frontier q[lo, hi), edge-balanced: the rows of up
-// to BS frontier nodes are concatenated (prefix sum of degrees) and the
+// to CH frontier nodes are concatenated (prefix sum of degrees) and the
 // workgroup strides over the concatenation.
 //   MODE 0: s-side BFS level (out-arcs); new nodes get s-level value nl.
 //   MODE 1: t-side BFS level (in-arcs);  new nodes get t-level value nl.
 //   MODE 2: DAG sweep inside the t-ball (out-arcs): nodes of t-level value nl
 //           receive sigma_s from the frontier and join the DAG queue.
-// New nodes whose other-side level is set form the meeting layer, which is
-// written to the head of q_d.
-template <int MODE>
-__device__ void expand(const DevGraph& g, const DevSlots& sl, int64_t so, int lo, int hi, uint32_t nl,
-                       SampleShared& sh, Counters& cn) {
+// In MODE 0/1 an arc (u, w) adds sigma(u) to w iff w is reached in this level:
+// either this arc reaches it first, or the "new" bit says another arc of this
+// level did. The new bit is set before the visited bit (release), and read
+// after it (acquire), so a visited node with a clear new bit is an old one.
+// New nodes that the other side has reached form the meeting layer, written
+// to the head of q_d.
+template <int MODE, int BSZ, bool LDS>
+__device__ void expand(const DevGraph& g, const DevSlots& sl, int64_t so, const Bits<LDS>& bits, int lo, int hi,
+                       uint32_t nl, SampleShared& sh, Counters& cn) {
+    using B = Bits<LDS>;
     const int tid = threadIdx.x;
     const int32_t* rp = (MODE == 1) ? g.irp : g.rp;
     const int32_t* col = (MODE == 1) ? g.icol : g.col;
     const int32_t* drp = (MODE == 0) ? g.rp : g.irp;
     int32_t* q = (MODE == 0 ? sl.q_s : MODE == 1 ? sl.q_t : sl.q_d) + so;
     uint32_t* lv_mine = (MODE == 0 ? sl.lv_s : sl.lv_t) + so;
-    uint32_t* lv_other = (MODE == 0 ? sl.lv_t : sl.lv_s) + so;
     uint64_t* sg = (MODE == 1 ? sl.sg_t : sl.sg_s) + so;
+    uint32_t* vis_mine = MODE == 0 ? bits.vs : bits.vt;
+    uint32_t* vis_other = MODE == 0 ? bits.vt : bits.vs;
 
-    for (int base = lo; base < hi; base += BS) {
-        const int cnt = min(BS, hi - base);
+    for (int base = lo; base < hi; base += CH) {
+        const int cnt = min(CH, hi - base);
         int deg = 0, beg = 0;
         uint64_t su = 0;
         uint32_t of = 0;
@@ -191,17 +228,19 @@ __device__ void expand(const DevGraph& g, const DevSlots& sl, int64_t so, int lo
             beg = rp[u];
             deg = rp[u + 1] - beg;
             su = ld64(sg + u);
-            if (MODE != 2) of = ld32(lv_mine + u) & OVFBIT;
+            if (MODE != 2) of = (ld32(lv_mine + u) & OVFBIT) ? 1 : 0;
             cn.V++;
         }
         int total;
-        int ex = block_excl_scan(deg, sh.wsum, total);
-        sh.beg[tid] = beg;
-        sh.off[tid] = ex;
-        sh.sig[tid] = su;
-        sh.of[tid] = of;
+        const int ex = chunk_excl_scan<BSZ>(deg, sh.wsum, total);
+        if (tid < CH) {
+            sh.beg[tid] = beg;
+            sh.off[tid] = ex;
+            sh.sig[tid] = su;
+            sh.of[tid] = (uint8_t)of;
+        }
         __syncthreads();
-        for (int e = tid; e < total; e += BS) {
+        for (int e = tid; e < total; e += BSZ) {
             int l2 = 0, h2 = cnt - 1;
             while (l2 < h2) {
                 int mid = (l2 + h2 + 1) >> 1;
@@ -211,6 +250,7 @@ __device__ void expand(const DevGraph& g, const DevSlots& sl, int64_t so, int lo
             const int32_t w = col[sh.beg[j] + (e - sh.off[j])];
             cn.E++;
             if (MODE == 2) {
+                if (!B::test(B::rd(bits.vt, w), w)) continue;
                 uint32_t lt = ld32(lv_mine + w);
                 if ((lt & LVMASK) == nl) {
                     atomicAdd((unsigned long long*)(sg + w), (unsigned long long)sh.sig[j]);
@@ -225,24 +265,27 @@ __device__ void expand(const DevGraph& g, const DevSlots& sl, int64_t so, int lo
                     }
                 }
             } else {
-                uint32_t lw = ld32(lv_mine + w);
-                bool fresh = false;
-                if (lw == 0) {
-                    uint32_t old = atomicCAS(lv_mine + w, 0u, nl);
-                    if (old == 0) { fresh = true; lw = nl; } else { lw = old; }
+                bool add, fresh = false;
+                if (!B::test(B::rd_acq(vis_mine, w), w)) {
+                    B::set(bits.nw, w);
+                    fresh = !B::test(B::set_rel(vis_mine, w), w);
+                    add = true;
+                } else {
+                    add = B::test(B::rd(bits.nw, w), w);
                 }
-                if ((lw & LVMASK) == nl) {
-                    const uint64_t add = sh.sig[j];
-                    unsigned long long old = atomicAdd((unsigned long long*)(sg + w), (unsigned long long)add);
-                    if (old + add < old || sh.of[j]) atomicOr(lv_mine + w, OVFBIT);
+                if (add) {
+                    const uint64_t addv = sh.sig[j];
+                    unsigned long long old = atomicAdd((unsigned long long*)(sg + w), (unsigned long long)addv);
+                    if (old + addv < old || sh.of[j]) atomicOr(lv_mine + w, OVFBIT);
                     cn.A++;
                 }
                 if (fresh) {
+                    atomicOr(lv_mine + w, nl);
                     int pos = atomicAdd(&sh.tail, 1);
                     q[pos] = w;
                     cn.Vd++;
                     atomicAdd(&sh.deg_next, (unsigned long long)(drp[w + 1] - drp[w]));
-                    if (ld32(lv_other + w) != 0) {
+                    if (B::test(B::rd(vis_other, w), w)) {
                         int mp = atomicAdd(&sh.nmeet, 1);
                         sl.q_d[so + mp] = w;
                     }
@@ -258,12 +301,22 @@ __device__ __forceinline__ void level_barrier() {
     __syncthreads();
 }
 
+// Clears the "new" bits of the nodes q[lo, hi) (all of them belong to the
+// level just built).
+template <int BSZ, bool LDS>
+__device__ void clear_new(const Bits<LDS>& bits, int32_t* q, int lo, int hi) {
+    for (int i = lo + (int)threadIdx.x; i < hi; i += BSZ) Bits<LDS>::clear_word(bits.nw, ldq(q + i));
+}
+
 // One sample on this workgroup's slot. In debug mode (dbg != nullptr) the pair
 // and the path index are given instead of drawn, hits are not touched and the
-// path is written to dbg.
+// path is written to dbg (internal ids).
+template <int BSZ, bool LDS>
 __device__ void run_sample(const DevGraph& g, const DevCdf& cdf, const DevSlots& sl, int64_t so,
-                           uint64_t idx, const SampleLaunch& a, SampleShared& sh, Counters& cn,
-                           DebugOut* dbg, int32_t dbg_s, int32_t dbg_t, uint64_t dbg_r, int32_t dbg_cap) {
+                           const Bits<LDS>& bits, int64_t words, uint64_t idx, const SampleLaunch& a,
+                           SampleShared& sh, Counters& cn, DebugOut* dbg, int32_t dbg_s, int32_t dbg_t,
+                           uint64_t dbg_r, int32_t dbg_cap) {
+    using B = Bits<LDS>;
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     uint32_t* lv_s = sl.lv_s + so;
     uint32_t* lv_t = sl.lv_t + so;
@@ -273,37 +326,53 @@ __device__ void run_sample(const DevGraph& g, const DevCdf& cdf, const DevSlots&
     int32_t* q_t = sl.q_t + so;
     int32_t* q_d = sl.q_d + so;
 
-    if (tid == 0) {
+    // ---- the pair (wave 0)
+    if (wid == 0) {
         int32_t s, t;
         if (!dbg) {
-            uint64_t Us = draw_bounded(a.seed, a.phase, idx, 0, cdf.C);
-            int32_t sr = search_s(cdf, Us);
-            uint64_t cs = cdf.P[sr] - cdf.P[sr - 1];
-            uint64_t Ut = draw_bounded(a.seed, a.phase, idx, 1, cs);
-            int32_t tr = search_t(cdf, sr, Ut);
+            const uint64_t Us = draw_bounded(a.seed, a.phase, idx, 0, cdf.C);
+            const uint64_t* P = cdf.P;
+            const int32_t sr = wave_search(1, cdf.n, [&](int32_t d) { return Us < P[d]; });
+            const uint64_t cs = P[sr] - P[sr - 1];
+            const uint64_t Ut = draw_bounded(a.seed, a.phase, idx, 1, cs);
+            const uint64_t ks = cdf.kr[sr], Ws = cdf.W[sr];
+            const uint64_t* W = cdf.W;
+            const int32_t tr = wave_search(sr + 1, cdf.n, [&](int32_t d) {
+                return Ut < (uint64_t)(d - sr + 1) * ks - (Ws - W[d + 1]);
+            });
             s = cdf.perm[sr];
             t = cdf.perm[tr];
         } else {
             s = dbg_s;
             t = dbg_t;
         }
-        sh.s = s;
-        sh.t = t;
-        lv_s[s] = 1; sg_s[s] = 1; q_s[0] = s;
-        lv_t[t] = 1; sg_t[t] = 1; q_t[0] = t;
-        sh.lo_s = 0; sh.hi_s = 1; sh.lo_t = 0; sh.hi_t = 1;
-        sh.a = 0; sh.b = 0;
-        sh.deg_s = (unsigned long long)(g.rp[s + 1] - g.rp[s]);
-        sh.deg_t = (unsigned long long)(g.irp[t + 1] - g.irp[t]);
-        sh.tail_s = 1; sh.tail_t = 1; sh.tail_d = 0;
-        sh.nmeet = 0; sh.status = 0; sh.ovf = 0; sh.walk_err = 0;
-        sh.sigma = 0;
-        cn.V += 0;
+        if (lane == 0) {
+            sh.s = s;
+            sh.t = t;
+            sh.nmeet = 0; sh.ovf = 0; sh.walk_err = 0; sh.sigma = 0;
+            sh.tail_d = 0;
+            sh.a = 0; sh.b = 0;
+            if (s >= g.n_act || t >= g.n_act) {
+                // a node without arcs reaches nothing and is reached by nothing
+                sh.status = 2;
+                sh.tail_s = 0; sh.tail_t = 0;
+            } else {
+                sh.status = 0;
+                B::set(bits.vs, s);
+                B::set(bits.vt, t);
+                atomicOr(lv_s + s, 1u); sg_s[s] = 1; q_s[0] = s;
+                atomicOr(lv_t + t, 1u); sg_t[t] = 1; q_t[0] = t;
+                sh.lo_s = 0; sh.hi_s = 1; sh.lo_t = 0; sh.hi_t = 1;
+                sh.deg_s = (unsigned long long)(g.rp[s + 1] - g.rp[s]);
+                sh.deg_t = (unsigned long long)(g.irp[t + 1] - g.irp[t]);
+                sh.tail_s = 1; sh.tail_t = 1;
+            }
+        }
     }
     level_barrier();
 
     // ---- balanced bidirectional BFS
-    for (;;) {
+    while (sh.status == 0) {
         const int side = (sh.deg_s <= sh.deg_t) ? 0 : 1;
         __syncthreads();
         if (tid == 0) {
@@ -311,23 +380,27 @@ __device__ void run_sample(const DevGraph& g, const DevCdf& cdf, const DevSlots&
             sh.deg_next = 0;
         }
         __syncthreads();
-        if (side == 0) expand<0>(g, sl, so, sh.lo_s, sh.hi_s, (uint32_t)sh.a + 2, sh, cn);
-        else expand<1>(g, sl, so, sh.lo_t, sh.hi_t, (uint32_t)sh.b + 2, sh, cn);
+        int nlo, nhi;
+        if (side == 0) {
+            nlo = sh.hi_s;
+            expand<0, BSZ, LDS>(g, sl, so, bits, sh.lo_s, sh.hi_s, (uint32_t)sh.a + 2, sh, cn);
+        } else {
+            nlo = sh.hi_t;
+            expand<1, BSZ, LDS>(g, sl, so, bits, sh.lo_t, sh.hi_t, (uint32_t)sh.b + 2, sh, cn);
+        }
         level_barrier();
+        nhi = sh.tail;
+        clear_new<BSZ, LDS>(bits, side == 0 ? q_s : q_t, nlo, nhi);
         if (tid == 0) {
-            int grown;
             if (side == 0) {
                 sh.lo_s = sh.hi_s; sh.hi_s = sh.tail; sh.tail_s = sh.tail; sh.a++; sh.deg_s = sh.deg_next;
-                grown = sh.hi_s - sh.lo_s;
             } else {
                 sh.lo_t = sh.hi_t; sh.hi_t = sh.tail; sh.tail_t = sh.tail; sh.b++; sh.deg_t = sh.deg_next;
-                grown = sh.hi_t - sh.lo_t;
             }
             if (sh.nmeet > 0) sh.status = 1;
-            else if (grown == 0) sh.status = 2;
+            else if (nhi == nlo) sh.status = 2;
         }
-        __syncthreads();
-        if (sh.status != 0) break;
+        level_barrier();
     }
 
     // ---- meeting layer: sigma_st with overflow detection
@@ -370,7 +443,7 @@ __device__ void run_sample(const DevGraph& g, const DevCdf& cdf, const DevSlots&
         if (!sh.ovf && sh.b > 0) {
             int lo = 0, hi = sh.nmeet;
             for (int j = sh.b; j >= 1; j--) {
-                expand<2>(g, sl, so, lo, hi, (uint32_t)j, sh, cn);
+                expand<2, BSZ, LDS>(g, sl, so, bits, lo, hi, (uint32_t)j, sh, cn);
                 level_barrier();
                 lo = hi;
                 hi = sh.tail;
@@ -395,9 +468,11 @@ __device__ void run_sample(const DevGraph& g, const DevCdf& cdf, const DevSlots&
                     if (i < end) {
                         u = g.icol[i];
                         if (p <= aM) {
-                            if ((ld32(lv_s + u) & LVMASK) == (uint32_t)p + 1) wt = ld64(sg_s + u);
+                            if (B::test(B::rd(bits.vs, u), u) && (ld32(lv_s + u) & LVMASK) == (uint32_t)p + 1)
+                                wt = ld64(sg_s + u);
                         } else {
-                            if ((ld32(lv_t + u) & LVMASK) == (uint32_t)(L - p) + 1) wt = ld64(sg_s + u);
+                            if (B::test(B::rd(bits.vt, u), u) && (ld32(lv_t + u) & LVMASK) == (uint32_t)(L - p) + 1)
+                                wt = ld64(sg_s + u);
                         }
                         cn.E++;
                     }
@@ -419,15 +494,13 @@ __device__ void run_sample(const DevGraph& g, const DevCdf& cdf, const DevSlots&
                     if (dbg) {
                         if (p < dbg_cap) dbg->path[p] = w;
                     } else {
-                        atomicAdd(a.hits + w, 1u);
+                        atomicAdd(a.hits + g.orig[w], 1u);
                     }
                     cn.V++;
                 }
             }
             if (lane == 0) sh.walk_err = err;
         }
-    } else {
-        if (tid == 0) sh.tail_d = 0;
     }
     __syncthreads();
 
@@ -458,17 +531,19 @@ __device__ void run_sample(const DevGraph& g, const DevCdf& cdf, const DevSlots&
 
     // ---- clear what this sample touched
     const int ts = sh.tail_s, tt = sh.tail_t, td = sh.tail_d;
-    for (int i = tid; i < ts; i += BS) {
+    for (int i = tid; i < ts; i += BSZ) {
         int32_t w = ldq(q_s + i);
         lv_s[w] = 0;
         sg_s[w] = 0;
+        B::clear_word(bits.vs, w);
     }
-    for (int i = tid; i < tt; i += BS) {
+    for (int i = tid; i < tt; i += BSZ) {
         int32_t w = ldq(q_t + i);
         lv_t[w] = 0;
         sg_t[w] = 0;
+        B::clear_word(bits.vt, w);
     }
-    for (int i = tid; i < td; i += BS) {
+    for (int i = tid; i < td; i += BSZ) {
         int32_t w = ldq(q_d + i);
         sg_s[w] = 0;
     }
@@ -492,11 +567,34 @@ __device__ void flush_counters(const Counters& cn, DevStats* st) {
     }
 }
 
-__global__ __launch_bounds__(BS) void sampler_kernel(DevGraph g, DevCdf cdf, DevSlots sl, SampleLaunch a) {
+extern __shared__ uint32_t dyn_lds[];
+
+template <int BSZ, bool LDS>
+__device__ __forceinline__ Bits<LDS> slot_bits(const DevSlots& sl, int slot) {
+    Bits<LDS> b;
+    if (LDS) {
+        b.vs = dyn_lds;
+        b.vt = dyn_lds + sl.words;
+        b.nw = dyn_lds + 2 * sl.words;
+    } else {
+        uint32_t* base = sl.bm + (int64_t)slot * 3 * sl.words;
+        b.vs = base;
+        b.vt = base + sl.words;
+        b.nw = base + 2 * sl.words;
+    }
+    return b;
+}
+
+template <int BSZ, bool LDS>
+__global__ __launch_bounds__(BSZ) void sampler_kernel(DevGraph g, DevCdf cdf, DevSlots sl, SampleLaunch a) {
     __shared__ SampleShared sh;
     const int tid = threadIdx.x;
     const int64_t so = (int64_t)blockIdx.x * sl.stride;
+    const Bits<LDS> bits = slot_bits<BSZ, LDS>(sl, blockIdx.x);
     Counters cn = {0, 0, 0, 0};
+    if (LDS) {
+        for (int64_t i = tid; i < 3 * sl.words; i += BSZ) dyn_lds[i] = 0;
+    }
     if (tid == 0) {
         sh.n_samples = sh.n_reach = sh.sum_I = sh.sum_I2 = sh.n_ovf = 0;
         sh.first_ovf = ~0ull;
@@ -506,7 +604,7 @@ __global__ __launch_bounds__(BS) void sampler_kernel(DevGraph g, DevCdf cdf, Dev
         __syncthreads();
         const unsigned long long q = sh.idx;
         if (q >= a.count) break;
-        run_sample(g, cdf, sl, so, a.first + q, a, sh, cn, nullptr, 0, 0, 0, 0);
+        run_sample<BSZ, LDS>(g, cdf, sl, so, bits, sl.words, a.first + q, a, sh, cn, nullptr, 0, 0, 0, 0);
     }
     flush_counters(cn, a.stats);
     if (tid == 0) {
@@ -519,10 +617,15 @@ __global__ __launch_bounds__(BS) void sampler_kernel(DevGraph g, DevCdf cdf, Dev
     }
 }
 
-__global__ __launch_bounds__(BS) void debug_path_kernel(DevGraph g, DevSlots sl, int32_t s, int32_t t, uint64_t r,
-                                                        DebugOut* out, int32_t cap) {
+template <int BSZ, bool LDS>
+__global__ __launch_bounds__(BSZ) void debug_path_kernel(DevGraph g, DevSlots sl, int32_t s, int32_t t, uint64_t r,
+                                                         DebugOut* out, int32_t cap) {
     __shared__ SampleShared sh;
+    const Bits<LDS> bits = slot_bits<BSZ, LDS>(sl, 0);
     Counters cn = {0, 0, 0, 0};
+    if (LDS) {
+        for (int64_t i = threadIdx.x; i < 3 * sl.words; i += BSZ) dyn_lds[i] = 0;
+    }
     if (threadIdx.x == 0) {
         sh.n_samples = sh.n_reach = sh.sum_I = sh.sum_I2 = sh.n_ovf = 0;
         sh.first_ovf = ~0ull;
@@ -530,7 +633,7 @@ __global__ __launch_bounds__(BS) void debug_path_kernel(DevGraph g, DevSlots sl,
     __syncthreads();
     DevCdf none = {};
     SampleLaunch a = {};
-    run_sample(g, none, sl, 0, 0, a, sh, cn, out, s, t, r, cap);
+    run_sample<BSZ, LDS>(g, none, sl, 0, bits, sl.words, 0, a, sh, cn, out, s, t, r, cap);
 }
 
 __global__ void fill_u32_kernel(uint32_t* p, uint32_t v, int64_t count) {
@@ -581,17 +684,59 @@ hipError_t launch_init_stats(DevStats* st, unsigned long long* work, hipStream_t
     return hipGetLastError();
 }
 
+int64_t sampler_static_lds() { return (int64_t)sizeof(SampleShared); }
+
+template <int BSZ, bool LDS>
+static const void* sampler_fn() {
+    return reinterpret_cast<const void*>(&sampler_kernel<BSZ, LDS>);
+}
+
+static const void* pick_sampler(const SamplerShape& s) {
+    switch (s.block) {
+        case 256: return s.lds_bitmaps ? sampler_fn<256, true>() : sampler_fn<256, false>();
+        case 512: return s.lds_bitmaps ? sampler_fn<512, true>() : sampler_fn<512, false>();
+        case 1024: return s.lds_bitmaps ? sampler_fn<1024, true>() : sampler_fn<1024, false>();
+        default: return nullptr;
+    }
+}
+
+int sampler_occupancy(const SamplerShape& s) {
+    const void* fn = pick_sampler(s);
+    if (!fn) return 0;
+    int blocks = 0;
+    const size_t dyn = s.lds_bitmaps ? (size_t)s.lds_bytes : 0;
+    if (dyn > 0) (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn);
+    (void)hipGetLastError();
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, fn, s.block, dyn) != hipSuccess) return 0;
+    return blocks;
+}
+
 hipError_t launch_sampler(const DevGraph& g, const DevCdf& cdf, const DevSlots& slots, const SampleLaunch& a,
-                          hipStream_t stream) {
+                          const SamplerShape& shape, hipStream_t stream) {
     if (a.count == 0 || a.slots <= 0) return hipSuccess;
-    hipLaunchKernelGGL(sampler_kernel, dim3(a.slots), dim3(BS), 0, stream, g, cdf, slots, a);
-    return hipGetLastError();
+    const void* fn = pick_sampler(shape);
+    if (!fn) return hipErrorInvalidValue;
+    const size_t dyn = shape.lds_bitmaps ? (size_t)shape.lds_bytes : 0;
+    if (dyn > 0) (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn);
+    (void)hipGetLastError();
+    void* args[] = {(void*)&g, (void*)&cdf, (void*)&slots, (void*)&a};
+    return hipLaunchKernel(fn, dim3(a.slots), dim3(shape.block), args, dyn, stream);
 }
 
 hipError_t launch_debug_path(const DevGraph& g, const DevSlots& slots, int32_t s, int32_t t, uint64_t r,
-                             DebugOut* out, int32_t cap, hipStream_t stream) {
-    hipLaunchKernelGGL(debug_path_kernel, dim3(1), dim3(BS), 0, stream, g, slots, s, t, r, out, cap);
-    return hipGetLastError();
+                             DebugOut* out, int32_t cap, const SamplerShape& shape, hipStream_t stream) {
+    const void* fn = nullptr;
+    switch (shape.block) {
+        case 256: fn = shape.lds_bitmaps ? (const void*)&debug_path_kernel<256, true> : (const void*)&debug_path_kernel<256, false>; break;
+        case 512: fn = shape.lds_bitmaps ? (const void*)&debug_path_kernel<512, true> : (const void*)&debug_path_kernel<512, false>; break;
+        case 1024: fn = shape.lds_bitmaps ? (const void*)&debug_path_kernel<1024, true> : (const void*)&debug_path_kernel<1024, false>; break;
+        default: return hipErrorInvalidValue;
+    }
+    const size_t dyn = shape.lds_bitmaps ? (size_t)shape.lds_bytes : 0;
+    if (dyn > 0) (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn);
+    (void)hipGetLastError();
+    void* args[] = {(void*)&g, (void*)&slots, (void*)&s, (void*)&t, (void*)&r, (void*)&out, (void*)&cap};
+    return hipLaunchKernel(fn, dim3(1), dim3(shape.block), args, dyn, stream);
 }
 
 }  // namespace percis

@@ -91,15 +91,49 @@ def test_er1000_parity():
     assert int(hg.sum()) == sg["sum_I"]
 
 
-@pytest.mark.parametrize("slots", [1, 3, 37])
-def test_launch_shape_invariance(slots):
+@pytest.mark.parametrize("slots,block,bitmaps", [(1, 0, 0), (3, 256, 1), (37, 512, 2), (0, 1024, 1),
+                                                  (0, 256, 2), (5, 1024, 2)])
+def test_launch_shape_invariance(slots, block, bitmaps):
+    """Hit counts and statistics do not depend on the number of slots, the
+    threads per sample or where the visited bitmaps live."""
+    from paper_2509_11454_amd import percis as P
     g, k = W.workload_er1000()
     c0 = gpu_context(g, k)
     h0, s0 = gpu_hits(c0, 0, 3000, 7)
-    c = gpu_context(g, k, slots=slots)
+    c = P.Context(0)
+    c.set_option(P.OPT_SLOTS, slots)
+    c.set_option(P.OPT_BLOCK, block)
+    c.set_option(P.OPT_BITMAPS, bitmaps)
+    c.load_csr(g.n, g.row_ptr, g.col)
+    c.set_states(k)
     h, s = gpu_hits(c, 0, 3000, 7)
     assert np.array_equal(h0, h)
     same_stats(s0, s)
+    if block:
+        assert c.get_option(P.OPT_BLOCK) == block
+    if bitmaps:
+        assert c.get_option(P.OPT_BITMAPS) == bitmaps
+
+
+def test_rmat18_shapes_agree():
+    """On the benchmark graph, LDS and device-memory bitmaps and different
+    block sizes give identical hits on a window of samples."""
+    from paper_2509_11454_amd import percis as P
+    g, k = W.workload_rmat18()
+    ref = None
+    for block, bitmaps in [(1024, 2), (512, 1), (256, 2)]:
+        c = P.Context(0)
+        c.set_option(P.OPT_BLOCK, block)
+        c.set_option(P.OPT_BITMAPS, bitmaps)
+        c.load_csr(g.n, g.row_ptr, g.col)
+        c.set_states(k)
+        h, s = gpu_hits(c, 5000, 20000, 3)
+        if ref is None:
+            ref = (h, s)
+        else:
+            assert np.array_equal(ref[0], h)
+            same_stats(ref[1], s)
+        c.close()
 
 
 def test_ranges_add_up_and_accumulate():
