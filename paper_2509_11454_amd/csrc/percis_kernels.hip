@@ -42,16 +42,18 @@ constexpr uint32_t LVMASK = 0x0FFFFFFFu;
 constexpr uint32_t DAGBIT = 0x20000000u;
 constexpr uint32_t OVFBIT = 0x40000000u;
 
-// Slot scratch is shared by the waves of a workgroup and updated with L2
-// atomics; reads go to L2 as well so that a stale L1 line is never observed.
-__device__ __forceinline__ uint32_t ld32(uint32_t* p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+// Slot scratch is private to one workgroup (one CU), so every access to it is
+// a workgroup-scope atomic: coherent among the workgroup's waves without the
+// device-wide cache maintenance that agent scope costs on a multi-XCD part.
+#define WGS __HIP_MEMORY_SCOPE_WORKGROUP
+__device__ __forceinline__ uint32_t ld32(uint32_t* p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, WGS); }
+__device__ __forceinline__ uint64_t ld64(uint64_t* p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, WGS); }
+__device__ __forceinline__ int32_t ldq(int32_t* p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, WGS); }
+__device__ __forceinline__ uint32_t or32(uint32_t* p, uint32_t v) {
+    return __hip_atomic_fetch_or(p, v, __ATOMIC_RELAXED, WGS);
 }
-__device__ __forceinline__ uint64_t ld64(uint64_t* p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ int32_t ldq(int32_t* p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+__device__ __forceinline__ uint64_t add64(uint64_t* p, uint64_t v) {
+    return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, WGS);
 }
 
 // Visited bitmaps: three planes per slot -- s-side visited, t-side visited,
@@ -62,7 +64,7 @@ struct Bits {
     uint32_t* vs;
     uint32_t* vt;
     uint32_t* nw;
-    static constexpr int SCOPE = LDS ? __HIP_MEMORY_SCOPE_WORKGROUP : __HIP_MEMORY_SCOPE_AGENT;
+    static constexpr int SCOPE = __HIP_MEMORY_SCOPE_WORKGROUP;
     __device__ __forceinline__ static uint32_t rd(uint32_t* p, int32_t w) {
         return __hip_atomic_load(p + (w >> 5), __ATOMIC_RELAXED, SCOPE);
     }
@@ -253,10 +255,10 @@ __device__ void expand(const DevGraph& g, const DevSlots& sl, int64_t so, const 
                 if (!B::test(B::rd(bits.vt, w), w)) continue;
                 uint32_t lt = ld32(lv_mine + w);
                 if ((lt & LVMASK) == nl) {
-                    atomicAdd((unsigned long long*)(sg + w), (unsigned long long)sh.sig[j]);
+                    add64(sg + w, sh.sig[j]);
                     cn.A++;
                     if (!(lt & DAGBIT)) {
-                        uint32_t old = atomicOr(lv_mine + w, DAGBIT);
+                        uint32_t old = or32(lv_mine + w, DAGBIT);
                         if (!(old & DAGBIT)) {
                             int pos = atomicAdd(&sh.tail, 1);
                             q[pos] = w;
@@ -275,12 +277,12 @@ __device__ void expand(const DevGraph& g, const DevSlots& sl, int64_t so, const 
                 }
                 if (add) {
                     const uint64_t addv = sh.sig[j];
-                    unsigned long long old = atomicAdd((unsigned long long*)(sg + w), (unsigned long long)addv);
-                    if (old + addv < old || sh.of[j]) atomicOr(lv_mine + w, OVFBIT);
+                    const uint64_t old = add64(sg + w, addv);
+                    if (old + addv < old || sh.of[j]) or32(lv_mine + w, OVFBIT);
                     cn.A++;
                 }
                 if (fresh) {
-                    atomicOr(lv_mine + w, nl);
+                    or32(lv_mine + w, nl);
                     int pos = atomicAdd(&sh.tail, 1);
                     q[pos] = w;
                     cn.Vd++;
@@ -296,10 +298,9 @@ __device__ void expand(const DevGraph& g, const DevSlots& sl, int64_t so, const 
     }
 }
 
-__device__ __forceinline__ void level_barrier() {
-    __threadfence();
-    __syncthreads();
-}
+// __syncthreads orders the workgroup's scratch accesses (workgroup-scope
+// release/acquire around the barrier).
+__device__ __forceinline__ void level_barrier() { __syncthreads(); }
 
 // Clears the "new" bits of the nodes q[lo, hi) (all of them belong to the
 // level just built).
@@ -360,8 +361,8 @@ __device__ void run_sample(const DevGraph& g, const DevCdf& cdf, const DevSlots&
                 sh.status = 0;
                 B::set(bits.vs, s);
                 B::set(bits.vt, t);
-                atomicOr(lv_s + s, 1u); sg_s[s] = 1; q_s[0] = s;
-                atomicOr(lv_t + t, 1u); sg_t[t] = 1; q_t[0] = t;
+                or32(lv_s + s, 1u); sg_s[s] = 1; q_s[0] = s;
+                or32(lv_t + t, 1u); sg_t[t] = 1; q_t[0] = t;
                 sh.lo_s = 0; sh.hi_s = 1; sh.lo_t = 0; sh.hi_t = 1;
                 sh.deg_s = (unsigned long long)(g.rp[s + 1] - g.rp[s]);
                 sh.deg_t = (unsigned long long)(g.irp[t + 1] - g.irp[t]);
@@ -421,7 +422,7 @@ __device__ void run_sample(const DevGraph& g, const DevCdf& cdf, const DevSlots&
                 uint64_t na = acc + p;
                 if (na < acc) of = 1;
                 acc = na;
-                atomicOr(lv_t + w, DAGBIT);
+                or32(lv_t + w, DAGBIT);
             }
 #pragma unroll
             for (int o = 32; o > 0; o >>= 1) {
