@@ -144,7 +144,9 @@ struct SampleShared {
     int32_t s, t;
     int32_t lo_s, hi_s, lo_t, hi_t;
     int32_t a, b;
-    unsigned long long deg_s, deg_t, deg_next;
+    unsigned long long deg_s, deg_t, deg_next;       // frontier degree sums
+    unsigned long long max_s, max_t, max_next;       // largest count in each frontier
+    uint32_t ovf_s, ovf_t, ovf_next;                 // a frontier count overflowed
     int32_t tail, tail_s, tail_t, tail_d;
     int32_t nmeet;
     int32_t status;   // 0 running, 1 met, 2 unreachable
@@ -193,103 +195,120 @@ __device__ __forceinline__ uint64_t wave_incl_scan_u64(uint64_t v) {
     return v;
 }
 
-// One level of work over the frontier q[lo, hi), edge-balanced: the rows of up
-// to CH frontier nodes are concatenated (prefix sum of degrees) and the
-// workgroup strides over the concatenation.
-//   MODE 0: s-side BFS level (out-arcs); new nodes get s-level value nl.
-//   MODE 1: t-side BFS level (in-arcs);  new nodes get t-level value nl.
-//   MODE 2: DAG sweep inside the t-ball (out-arcs): nodes of t-level value nl
-//           receive sigma_s from the frontier and join the DAG queue.
-// In MODE 0/1 an arc (u, w) adds sigma(u) to w iff w is reached in this level:
-// either this arc reaches it first, or the "new" bit says another arc of this
-// level did. The new bit is set before the visited bit (release), and read
-// after it (acquire), so a visited node with a clear new bit is an old one.
-// New nodes that the other side has reached form the meeting layer, written
-// to the head of q_d.
-template <int MODE, int BSZ, bool LDS>
-__device__ void expand(const DevGraph& g, const DevSlots& sl, int64_t so, const Bits<LDS>& bits, int lo, int hi,
-                       uint32_t nl, SampleShared& sh, Counters& cn) {
+// Stages up to CH frontier nodes q[base, base+cnt) in LDS: row start, degree
+// prefix sum, shortest-path count and overflow flag of each; returns the
+// number of adjacency entries of the chunk. Every thread must call it.
+template <int BSZ>
+__device__ __forceinline__ int stage_chunk(int32_t* q, int base, int cnt, const int32_t* rp, uint64_t* sg,
+                                           uint32_t* lv, bool read_ovf, SampleShared& sh, Counters& cn) {
+    const int tid = threadIdx.x;
+    int deg = 0, beg = 0;
+    uint64_t su = 0;
+    uint32_t of = 0;
+    if (tid < cnt) {
+        const int32_t u = ldq(q + base + tid);
+        beg = rp[u];
+        deg = rp[u + 1] - beg;
+        su = ld64(sg + u);
+        if (read_ovf) of = (ld32(lv + u) & OVFBIT) ? 1 : 0;
+        cn.V++;
+    }
+    int total;
+    const int ex = chunk_excl_scan<BSZ>(deg, sh.wsum, total);
+    if (tid < CH) {
+        sh.beg[tid] = beg;
+        sh.off[tid] = ex;
+        sh.sig[tid] = su;
+        sh.of[tid] = (uint8_t)of;
+    }
+    __syncthreads();
+    return total;
+}
+
+// Index j of the staged node whose row holds the e-th entry of the chunk.
+__device__ __forceinline__ int chunk_owner(const SampleShared& sh, int cnt, int e) {
+    int l2 = 0, h2 = cnt - 1;
+    while (l2 < h2) {
+        const int mid = (l2 + h2 + 1) >> 1;
+        if (sh.off[mid] <= e) l2 = mid; else h2 = mid - 1;
+    }
+    return l2;
+}
+
+constexpr int UNROLL = 4;
+
+// One BFS level over the frontier q[lo, hi) of one side (SIDE 0: s, out-arcs;
+// SIDE 1: t, in-arcs), edge-balanced: the rows of up to CH frontier nodes are
+// concatenated and the workgroup strides over the concatenation, UNROLL
+// entries per thread at a time so that their loads overlap. An arc (u, w)
+// adds sigma(u) to w iff w is reached in this level: either this arc reaches
+// it first, or the "new" bit says another arc of this level did. The new bit
+// is set before the visited bit (release) and read after it (acquire), so a
+// visited node with a clear new bit is an old one. New nodes that the other
+// side has reached form the meeting layer, written to the head of q_d.
+// `careful` is set when a count of this level could reach 2^64 (or a
+// frontier count already did): only then are the adds checked for wrapping.
+template <int SIDE, int BSZ, bool LDS>
+__device__ void expand_bfs(const DevGraph& g, const DevSlots& sl, int64_t so, const Bits<LDS>& bits, int lo, int hi,
+                           uint32_t nl, bool careful, SampleShared& sh, Counters& cn) {
     using B = Bits<LDS>;
     const int tid = threadIdx.x;
-    const int32_t* rp = (MODE == 1) ? g.irp : g.rp;
-    const int32_t* col = (MODE == 1) ? g.icol : g.col;
-    const int32_t* drp = (MODE == 0) ? g.rp : g.irp;
-    int32_t* q = (MODE == 0 ? sl.q_s : MODE == 1 ? sl.q_t : sl.q_d) + so;
-    uint32_t* lv_mine = (MODE == 0 ? sl.lv_s : sl.lv_t) + so;
-    uint64_t* sg = (MODE == 1 ? sl.sg_t : sl.sg_s) + so;
-    uint32_t* vis_mine = MODE == 0 ? bits.vs : bits.vt;
-    uint32_t* vis_other = MODE == 0 ? bits.vt : bits.vs;
+    const int32_t* rp = SIDE ? g.irp : g.rp;
+    const int32_t* col = SIDE ? g.icol : g.col;
+    int32_t* q = (SIDE ? sl.q_t : sl.q_s) + so;
+    uint32_t* lv = (SIDE ? sl.lv_t : sl.lv_s) + so;
+    uint64_t* sg = (SIDE ? sl.sg_t : sl.sg_s) + so;
+    uint32_t* vis_mine = SIDE ? bits.vt : bits.vs;
+    uint32_t* vis_other = SIDE ? bits.vs : bits.vt;
 
     for (int base = lo; base < hi; base += CH) {
         const int cnt = min(CH, hi - base);
-        int deg = 0, beg = 0;
-        uint64_t su = 0;
-        uint32_t of = 0;
-        if (tid < cnt) {
-            int32_t u = ldq(q + base + tid);
-            beg = rp[u];
-            deg = rp[u + 1] - beg;
-            su = ld64(sg + u);
-            if (MODE != 2) of = (ld32(lv_mine + u) & OVFBIT) ? 1 : 0;
-            cn.V++;
-        }
-        int total;
-        const int ex = chunk_excl_scan<BSZ>(deg, sh.wsum, total);
-        if (tid < CH) {
-            sh.beg[tid] = beg;
-            sh.off[tid] = ex;
-            sh.sig[tid] = su;
-            sh.of[tid] = (uint8_t)of;
-        }
-        __syncthreads();
-        for (int e = tid; e < total; e += BSZ) {
-            int l2 = 0, h2 = cnt - 1;
-            while (l2 < h2) {
-                int mid = (l2 + h2 + 1) >> 1;
-                if (sh.off[mid] <= e) l2 = mid; else h2 = mid - 1;
-            }
-            const int j = l2;
-            const int32_t w = col[sh.beg[j] + (e - sh.off[j])];
-            cn.E++;
-            if (MODE == 2) {
-                if (!B::test(B::rd(bits.vt, w), w)) continue;
-                uint32_t lt = ld32(lv_mine + w);
-                if ((lt & LVMASK) == nl) {
-                    add64(sg + w, sh.sig[j]);
-                    cn.A++;
-                    if (!(lt & DAGBIT)) {
-                        uint32_t old = or32(lv_mine + w, DAGBIT);
-                        if (!(old & DAGBIT)) {
-                            int pos = atomicAdd(&sh.tail, 1);
-                            q[pos] = w;
-                            cn.Vd++;
-                        }
-                    }
+        const int total = stage_chunk<BSZ>(q, base, cnt, rp, sg, lv, careful, sh, cn);
+        for (int e0 = tid; e0 < total; e0 += BSZ * UNROLL) {
+            int32_t w[UNROLL];
+            int jj[UNROLL];
+#pragma unroll
+            for (int k = 0; k < UNROLL; k++) {
+                const int e = e0 + k * BSZ;
+                jj[k] = -1;
+                w[k] = 0;
+                if (e < total) {
+                    jj[k] = chunk_owner(sh, cnt, e);
+                    w[k] = col[sh.beg[jj[k]] + (e - sh.off[jj[k]])];
                 }
-            } else {
+            }
+#pragma unroll
+            for (int k = 0; k < UNROLL; k++) {
+                if (jj[k] < 0) continue;
+                const int32_t x = w[k];
+                const int j = jj[k];
+                cn.E++;
                 bool add, fresh = false;
-                if (!B::test(B::rd_acq(vis_mine, w), w)) {
-                    B::set(bits.nw, w);
-                    fresh = !B::test(B::set_rel(vis_mine, w), w);
+                if (!B::test(B::rd_acq(vis_mine, x), x)) {
+                    B::set(bits.nw, x);
+                    fresh = !B::test(B::set_rel(vis_mine, x), x);
                     add = true;
                 } else {
-                    add = B::test(B::rd(bits.nw, w), w);
+                    add = B::test(B::rd(bits.nw, x), x);
                 }
                 if (add) {
                     const uint64_t addv = sh.sig[j];
-                    const uint64_t old = add64(sg + w, addv);
-                    if (old + addv < old || sh.of[j]) or32(lv_mine + w, OVFBIT);
+                    if (careful) {
+                        const uint64_t old = add64(sg + x, addv);
+                        if (old + addv < old || sh.of[j]) or32(lv + x, OVFBIT);
+                    } else {
+                        (void)add64(sg + x, addv);
+                    }
                     cn.A++;
                 }
                 if (fresh) {
-                    or32(lv_mine + w, nl);
-                    int pos = atomicAdd(&sh.tail, 1);
-                    q[pos] = w;
+                    or32(lv + x, nl);
+                    const int pos = atomicAdd(&sh.tail, 1);
+                    q[pos] = x;
                     cn.Vd++;
-                    atomicAdd(&sh.deg_next, (unsigned long long)(drp[w + 1] - drp[w]));
-                    if (B::test(B::rd(vis_other, w), w)) {
-                        int mp = atomicAdd(&sh.nmeet, 1);
-                        sl.q_d[so + mp] = w;
+                    if (B::test(B::rd(vis_other, x), x)) {
+                        const int mp = atomicAdd(&sh.nmeet, 1);
+                        sl.q_d[so + mp] = x;
                     }
                 }
             }
@@ -298,16 +317,81 @@ __device__ void expand(const DevGraph& g, const DevSlots& sl, int64_t so, const 
     }
 }
 
+// One level of the DAG sweep inside the t-ball (out-arcs): frontier nodes
+// q_d[lo, hi) have t-level value nl + 1; out-neighbours with t-level value nl
+// lie on the DAG, receive sigma_s and join q_d. No count here exceeds
+// sigma_st, which is known to be below 2^64.
+template <int BSZ, bool LDS>
+__device__ void expand_sweep(const DevGraph& g, const DevSlots& sl, int64_t so, const Bits<LDS>& bits, int lo, int hi,
+                             uint32_t nl, SampleShared& sh, Counters& cn) {
+    using B = Bits<LDS>;
+    const int tid = threadIdx.x;
+    int32_t* q = sl.q_d + so;
+    uint32_t* lv_t = sl.lv_t + so;
+    uint64_t* sg_s = sl.sg_s + so;
+    for (int base = lo; base < hi; base += CH) {
+        const int cnt = min(CH, hi - base);
+        const int total = stage_chunk<BSZ>(q, base, cnt, g.rp, sg_s, lv_t, false, sh, cn);
+        for (int e = tid; e < total; e += BSZ) {
+            const int j = chunk_owner(sh, cnt, e);
+            const int32_t w = g.col[sh.beg[j] + (e - sh.off[j])];
+            cn.E++;
+            if (!B::test(B::rd(bits.vt, w), w)) continue;
+            const uint32_t lt = ld32(lv_t + w);
+            if ((lt & LVMASK) != nl) continue;
+            (void)add64(sg_s + w, sh.sig[j]);
+            cn.A++;
+            if (!(lt & DAGBIT)) {
+                const uint32_t old = or32(lv_t + w, DAGBIT);
+                if (!(old & DAGBIT)) {
+                    const int pos = atomicAdd(&sh.tail, 1);
+                    q[pos] = w;
+                    cn.Vd++;
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// After a level of one side: clears the "new" bits of its nodes q[lo, hi)
+// and gathers, for the next expansion of that side, the degree sum of the
+// new frontier, its largest shortest-path count and whether any count
+// overflowed.
+template <int BSZ, bool LDS>
+__device__ void finish_level(const Bits<LDS>& bits, int32_t* q, uint64_t* sg, uint32_t* lv, const int32_t* drp,
+                             int lo, int hi, SampleShared& sh) {
+    unsigned long long dsum = 0, smax = 0;
+    uint32_t of = 0;
+    for (int i = lo + (int)threadIdx.x; i < hi; i += BSZ) {
+        const int32_t w = ldq(q + i);
+        Bits<LDS>::clear_word(bits.nw, w);
+        dsum += (unsigned long long)(drp[w + 1] - drp[w]);
+        const uint64_t sv = ld64(sg + w);
+        smax = sv > smax ? sv : smax;
+        of |= ld32(lv + w) & OVFBIT;
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        dsum += __shfl_xor(dsum, o, 64);
+        const unsigned long long om = __shfl_xor(smax, o, 64);
+        smax = om > smax ? om : smax;
+        of |= __shfl_xor(of, o, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        if (dsum) atomicAdd(&sh.deg_next, dsum);
+        if (smax) atomicMax(&sh.max_next, smax);
+        if (of) atomicOr(&sh.ovf_next, 1u);
+    }
+}
+
+__device__ __forceinline__ bool may_wrap(unsigned long long deg, unsigned long long smax, uint32_t ovf) {
+    return ovf || (smax > 0 && deg > ~0ull / smax);
+}
+
 // __syncthreads orders the workgroup's scratch accesses (workgroup-scope
 // release/acquire around the barrier).
 __device__ __forceinline__ void level_barrier() { __syncthreads(); }
-
-// Clears the "new" bits of the nodes q[lo, hi) (all of them belong to the
-// level just built).
-template <int BSZ, bool LDS>
-__device__ void clear_new(const Bits<LDS>& bits, int32_t* q, int lo, int hi) {
-    for (int i = lo + (int)threadIdx.x; i < hi; i += BSZ) Bits<LDS>::clear_word(bits.nw, ldq(q + i));
-}
 
 // One sample on this workgroup's slot. In debug mode (dbg != nullptr) the pair
 // and the path index are given instead of drawn, hits are not touched and the
@@ -366,6 +450,7 @@ __device__ void run_sample(const DevGraph& g, const DevCdf& cdf, const DevSlots&
                 sh.lo_s = 0; sh.hi_s = 1; sh.lo_t = 0; sh.hi_t = 1;
                 sh.deg_s = (unsigned long long)(g.rp[s + 1] - g.rp[s]);
                 sh.deg_t = (unsigned long long)(g.irp[t + 1] - g.irp[t]);
+                sh.max_s = 1; sh.max_t = 1; sh.ovf_s = 0; sh.ovf_t = 0;
                 sh.tail_s = 1; sh.tail_t = 1;
             }
         }
@@ -375,28 +460,30 @@ __device__ void run_sample(const DevGraph& g, const DevCdf& cdf, const DevSlots&
     // ---- balanced bidirectional BFS
     while (sh.status == 0) {
         const int side = (sh.deg_s <= sh.deg_t) ? 0 : 1;
+        const int nlo = side == 0 ? sh.hi_s : sh.hi_t;
+        const bool careful = side == 0 ? may_wrap(sh.deg_s, sh.max_s, sh.ovf_s) : may_wrap(sh.deg_t, sh.max_t, sh.ovf_t);
         __syncthreads();
         if (tid == 0) {
-            sh.tail = side == 0 ? sh.tail_s : sh.tail_t;
+            sh.tail = nlo;
             sh.deg_next = 0;
+            sh.max_next = 0;
+            sh.ovf_next = 0;
         }
         __syncthreads();
-        int nlo, nhi;
-        if (side == 0) {
-            nlo = sh.hi_s;
-            expand<0, BSZ, LDS>(g, sl, so, bits, sh.lo_s, sh.hi_s, (uint32_t)sh.a + 2, sh, cn);
-        } else {
-            nlo = sh.hi_t;
-            expand<1, BSZ, LDS>(g, sl, so, bits, sh.lo_t, sh.hi_t, (uint32_t)sh.b + 2, sh, cn);
-        }
+        if (side == 0) expand_bfs<0, BSZ, LDS>(g, sl, so, bits, sh.lo_s, sh.hi_s, (uint32_t)sh.a + 2, careful, sh, cn);
+        else expand_bfs<1, BSZ, LDS>(g, sl, so, bits, sh.lo_t, sh.hi_t, (uint32_t)sh.b + 2, careful, sh, cn);
         level_barrier();
-        nhi = sh.tail;
-        clear_new<BSZ, LDS>(bits, side == 0 ? q_s : q_t, nlo, nhi);
+        const int nhi = sh.tail;
+        if (side == 0) finish_level<BSZ, LDS>(bits, q_s, sg_s, lv_s, g.rp, nlo, nhi, sh);
+        else finish_level<BSZ, LDS>(bits, q_t, sg_t, lv_t, g.irp, nlo, nhi, sh);
+        level_barrier();
         if (tid == 0) {
             if (side == 0) {
-                sh.lo_s = sh.hi_s; sh.hi_s = sh.tail; sh.tail_s = sh.tail; sh.a++; sh.deg_s = sh.deg_next;
+                sh.lo_s = nlo; sh.hi_s = nhi; sh.tail_s = nhi; sh.a++;
+                sh.deg_s = sh.deg_next; sh.max_s = sh.max_next; sh.ovf_s = sh.ovf_next;
             } else {
-                sh.lo_t = sh.hi_t; sh.hi_t = sh.tail; sh.tail_t = sh.tail; sh.b++; sh.deg_t = sh.deg_next;
+                sh.lo_t = nlo; sh.hi_t = nhi; sh.tail_t = nhi; sh.b++;
+                sh.deg_t = sh.deg_next; sh.max_t = sh.max_next; sh.ovf_t = sh.ovf_next;
             }
             if (sh.nmeet > 0) sh.status = 1;
             else if (nhi == nlo) sh.status = 2;
@@ -444,7 +531,7 @@ __device__ void run_sample(const DevGraph& g, const DevCdf& cdf, const DevSlots&
         if (!sh.ovf && sh.b > 0) {
             int lo = 0, hi = sh.nmeet;
             for (int j = sh.b; j >= 1; j--) {
-                expand<2, BSZ, LDS>(g, sl, so, bits, lo, hi, (uint32_t)j, sh, cn);
+                expand_sweep<BSZ, LDS>(g, sl, so, bits, lo, hi, (uint32_t)j, sh, cn);
                 level_barrier();
                 lo = hi;
                 hi = sh.tail;
