@@ -104,6 +104,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-estimate", action="store_true")
+    ap.add_argument("--one-per-launch", type=int, default=2000, metavar="N",
+                    help="also time N samples drawn one per launch (0 = skip)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (reference for HBM counters)")
     args = ap.parse_args()
@@ -143,12 +145,15 @@ def main():
 
     torch.cuda.synchronize()
     totals = dict(edges=0, sigma_adds=0, vertices_expanded=0, vertices_discovered=0, sum_I=0, reachable=0)
+    phases = {}
     kernel_ms = []
     t_start = time.perf_counter()
     for i in range(args.steps):
         _, st = c.sample_range(0, samples, args.seed, 0, hits=hits)
         for key in totals:
             totals[key] += st[key]
+        for key, v in st["phase_ms"].items():
+            phases[key] = phases.get(key, 0.0) + v
         kernel_ms.append(st["kernel_ms"])
         print("[bench] step %d: kernel %.1f ms" % (i, st["kernel_ms"]), file=sys.stderr, flush=True)
     torch.cuda.synchronize()
@@ -191,6 +196,26 @@ def main():
     }
     if traffic:
         out["hbm_frac_measured"] = out["hbm_gbs_measured"] / HBM_PEAK_GBS
+
+    ptot = sum(phases.values())
+    if ptot > 0:
+        out["phase_split"] = {key: v / ptot for key, v in phases.items()}
+
+    if args.one_per_launch:
+        h1 = torch.zeros(g.n, dtype=torch.int32, device="cuda")
+        c.sample_range(0, 1, args.seed, 0, hits=h1)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for i in range(args.one_per_launch):
+            c.sample_range(i, 1, args.seed, 0, hits=h1, accumulate=i > 0)
+        torch.cuda.synchronize()
+        dt1 = time.perf_counter() - t1
+        out["one_sample_per_launch"] = {"value": args.one_per_launch / dt1, "unit": "samples/s",
+                                        "samples": args.one_per_launch,
+                                        "form": "one percis_sample_range call (one kernel launch) per sample"}
+        out["speedup_vs_one_per_launch"] = value / out["one_sample_per_launch"]["value"]
+        print("[bench] one sample per launch: %.1f samples/s" % out["one_sample_per_launch"]["value"],
+              file=sys.stderr, flush=True)
 
     if not args.no_estimate:
         p, info = c.estimate(0.01, 0.1, args.seed)

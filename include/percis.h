@@ -76,6 +76,12 @@ typedef struct {
     uint64_t vertices_expanded;
     uint64_t vertices_discovered;
     double   kernel_ms;         /* device time of the sampling kernel */
+    /* Time spent per sample phase, summed over the concurrently running
+     * samples (slot-milliseconds): drawing the pair (Algorithm 2), the
+     * bidirectional BFS, the meeting layer and DAG sweep, the path walk, and
+     * clearing the slot. Their ratios give the split between pair sampling
+     * and traversal that the paper reports (Section IV-B). */
+    double   phase_ms[5];
 } percis_stats;
 
 /* Result summary of percis_estimate (Algorithm 1). */

@@ -28,6 +28,7 @@ struct percis_ctx {
     hipStream_t stream = nullptr;
     std::string err;
     int cu_count = 0;
+    double wall_hz = 0.0;                  // device wall-clock rate
 
     // graph
     bool has_graph = false, directed = false;
@@ -413,6 +414,7 @@ int run_sampler(percis_ctx* c, uint64_t first, uint64_t count, uint64_t seed, ui
     st.vertices_expanded = hs.vexp;
     st.vertices_discovered = hs.vdisc;
     st.kernel_ms = ms;
+    for (int i = 0; i < 5; i++) st.phase_ms[i] = c->wall_hz > 0 ? (double)hs.phase_ticks[i] / c->wall_hz * 1e3 : 0.0;
     if (st_out) *st_out = st;
     if (st.samples != count)
         return fail(c, PERCIS_E_DEVICE, "sampler processed %llu of %llu samples", (unsigned long long)st.samples,
@@ -465,6 +467,8 @@ int percis_create(int device, void* hip_stream, percis_ctx** out) {
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, device) != hipSuccess) { delete c; return PERCIS_E_DEVICE; }
     c->cu_count = prop.multiProcessorCount;
+    int wall_khz = 0;
+    if (hipDeviceGetAttribute(&wall_khz, hipDeviceAttributeWallClockRate, device) == hipSuccess) c->wall_hz = wall_khz * 1e3;
     if (hipMalloc((void**)&c->d_stats, sizeof(DevStats)) != hipSuccess ||
         hipMalloc((void**)&c->d_work, sizeof(unsigned long long)) != hipSuccess ||
         hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess) {

@@ -52,6 +52,7 @@ struct DevSlots {
 struct DevStats {
     unsigned long long samples, reachable, sum_I, sum_I2, overflow, first_overflow;
     unsigned long long edges, sigma_adds, vexp, vdisc;
+    unsigned long long phase_ticks[5];   // summed over workgroups, wall-clock ticks
 };
 
 struct SampleLaunch {

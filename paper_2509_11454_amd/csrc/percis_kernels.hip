@@ -154,6 +154,7 @@ struct SampleShared {
     int32_t walk_err;
     uint64_t sigma;
     unsigned long long n_samples, n_reach, sum_I, sum_I2, n_ovf, first_ovf;
+    unsigned long long phase_ticks[5];  // pair, BFS, meeting + DAG sweep, walk, clearing
 };
 
 struct Counters {
@@ -411,6 +412,17 @@ __device__ void run_sample(const DevGraph& g, const DevCdf& cdf, const DevSlots&
     int32_t* q_t = sl.q_t + so;
     int32_t* q_d = sl.q_d + so;
 
+    // phase timers (thread 0, constant-rate wall clock)
+    unsigned long long tm_prev = 0;
+    if (tid == 0) tm_prev = wall_clock64();
+    auto phase_mark = [&](int ph) {
+        if (tid == 0) {
+            const unsigned long long now = wall_clock64();
+            sh.phase_ticks[ph] += now - tm_prev;
+            tm_prev = now;
+        }
+    };
+
     // ---- the pair (wave 0)
     if (wid == 0) {
         int32_t s, t;
@@ -456,6 +468,7 @@ __device__ void run_sample(const DevGraph& g, const DevCdf& cdf, const DevSlots&
         }
     }
     level_barrier();
+    phase_mark(0);
 
     // ---- balanced bidirectional BFS
     while (sh.status == 0) {
@@ -490,6 +503,8 @@ __device__ void run_sample(const DevGraph& g, const DevCdf& cdf, const DevSlots&
         }
         level_barrier();
     }
+
+    phase_mark(1);
 
     // ---- meeting layer: sigma_st with overflow detection
     // After the last level, the meeting layer lies at s-level a and t-level b
@@ -539,6 +554,7 @@ __device__ void run_sample(const DevGraph& g, const DevCdf& cdf, const DevSlots&
             }
         }
         if (tid == 0) sh.tail_d = sh.tail;
+        phase_mark(2);
 
         // ---- canonical backward walk by wave 0
         if (!sh.ovf && wid == 0) {
@@ -591,6 +607,7 @@ __device__ void run_sample(const DevGraph& g, const DevCdf& cdf, const DevSlots&
         }
     }
     __syncthreads();
+    phase_mark(3);
 
     // ---- per-sample statistics
     if (tid == 0) {
@@ -636,6 +653,7 @@ __device__ void run_sample(const DevGraph& g, const DevCdf& cdf, const DevSlots&
         sg_s[w] = 0;
     }
     level_barrier();
+    phase_mark(4);
 }
 
 __device__ void flush_counters(const Counters& cn, DevStats* st) {
@@ -686,6 +704,7 @@ __global__ __launch_bounds__(BSZ) void sampler_kernel(DevGraph g, DevCdf cdf, De
     if (tid == 0) {
         sh.n_samples = sh.n_reach = sh.sum_I = sh.sum_I2 = sh.n_ovf = 0;
         sh.first_ovf = ~0ull;
+        for (int i = 0; i < 5; i++) sh.phase_ticks[i] = 0;
     }
     for (;;) {
         if (tid == 0) sh.idx = atomicAdd(a.work, 1ull);
@@ -702,6 +721,7 @@ __global__ __launch_bounds__(BSZ) void sampler_kernel(DevGraph g, DevCdf cdf, De
         atomicAdd(&a.stats->sum_I2, sh.sum_I2);
         atomicAdd(&a.stats->overflow, sh.n_ovf);
         atomicMin(&a.stats->first_overflow, sh.first_ovf);
+        for (int i = 0; i < 5; i++) atomicAdd(&a.stats->phase_ticks[i], sh.phase_ticks[i]);
     }
 }
 
@@ -717,6 +737,7 @@ __global__ __launch_bounds__(BSZ) void debug_path_kernel(DevGraph g, DevSlots sl
     if (threadIdx.x == 0) {
         sh.n_samples = sh.n_reach = sh.sum_I = sh.sum_I2 = sh.n_ovf = 0;
         sh.first_ovf = ~0ull;
+        for (int i = 0; i < 5; i++) sh.phase_ticks[i] = 0;
     }
     __syncthreads();
     DevCdf none = {};
@@ -744,6 +765,7 @@ __global__ void init_stats_kernel(DevStats* st, unsigned long long* work) {
         st->samples = st->reachable = st->sum_I = st->sum_I2 = st->overflow = 0;
         st->first_overflow = ~0ull;
         st->edges = st->sigma_adds = st->vexp = st->vdisc = 0;
+        for (int i = 0; i < 5; i++) st->phase_ticks[i] = 0;
         *work = 0;
     }
 }

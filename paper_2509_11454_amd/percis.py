@@ -30,11 +30,18 @@ class Stats(C.Structure):
     _fields_ = [("samples", C.c_uint64), ("reachable", C.c_uint64), ("sum_I", C.c_uint64),
                 ("sum_I2", C.c_uint64), ("overflow", C.c_uint64), ("first_overflow", C.c_uint64),
                 ("edges", C.c_uint64), ("sigma_adds", C.c_uint64), ("vertices_expanded", C.c_uint64),
-                ("vertices_discovered", C.c_uint64), ("kernel_ms", C.c_double)]
+                ("vertices_discovered", C.c_uint64), ("kernel_ms", C.c_double), ("phase_ms", C.c_double * 5)]
+
+    PHASES = ("pair", "bfs", "dag", "walk", "clear")
 
     def to_dict(self):
-        return {k: (float(getattr(self, k)) if t is C.c_double else int(getattr(self, k)))
-                for k, t in self._fields_}
+        d = {}
+        for k, t in self._fields_:
+            if k == "phase_ms":
+                d[k] = dict(zip(self.PHASES, [float(x) for x in self.phase_ms]))
+            else:
+                d[k] = float(getattr(self, k)) if t is C.c_double else int(getattr(self, k))
+        return d
 
 
 class EstimateInfo(C.Structure):
