@@ -156,6 +156,46 @@ int percis_sample(percis_ctx* ctx, uint64_t n_samples, uint64_t seed, uint32_t* 
 int percis_estimate(percis_ctx* ctx, double eps, double delta, uint64_t seed, double* p_out,
                     percis_estimate_info* info);
 
+/* ---- many graphs in one launch ----
+ * A context holds graph 0 (set by percis_load_csr / percis_set_states) and
+ * any number of further graphs added with percis_add_graph. A task is a
+ * sample range of one graph; percis_sample_tasks runs any set of tasks, on
+ * any mix of graphs, through one persistent launch (the samples of all tasks
+ * share the device's workgroups). Each task's hits and statistics equal what
+ * percis_sample_range would give for the same graph, range, seed and phase. */
+
+/* Adds a graph with its states (arguments as for percis_load_csr followed by
+ * percis_set_states; flags: PERCIS_DIRECTED, PERCIS_DEVICE_PTRS) and returns
+ * its id (>= 1) in *graph_id. */
+int percis_add_graph(percis_ctx* ctx, int32_t n, int64_t m, const int32_t* row_ptr, const int32_t* col,
+                     const uint16_t* k, uint32_t flags, int32_t* graph_id);
+
+/* Size of graph `graph`: nodes, arcs, and nodes with at least one arc. */
+int percis_graph_info(percis_ctx* ctx, int32_t graph, int32_t* n, int64_t* m, int32_t* n_active);
+
+typedef struct {
+    int32_t graph;        /* graph id (0 = the graph of percis_load_csr) */
+    uint32_t phase;       /* stream phase */
+    uint64_t first;       /* first sample index */
+    uint64_t count;       /* number of samples, < 2^32 */
+    uint64_t seed;
+    uint32_t* hits;       /* device memory, n entries of that graph, caller-owned */
+    uint32_t flags;       /* PERCIS_ACCUMULATE or 0 */
+    percis_stats* stats;  /* host, receives this task's sample statistics; may be NULL */
+} percis_task;
+
+/* Runs ntasks tasks in one launch on the context's stream and waits for it.
+ * Each task's stats receive its sample counts (samples, reachable, sum_I,
+ * sum_I2, overflow, first_overflow) and the kernel time; launch_stats (may be
+ * NULL) receives the sums over all tasks plus the launch-wide work counters
+ * and phase times. Returns PERCIS_E_SIGMA_OVERFLOW if any task overflowed. */
+int percis_sample_tasks(percis_ctx* ctx, int32_t ntasks, const percis_task* tasks, percis_stats* launch_stats);
+
+/* Algorithm 1 on graph `graph` (percis_estimate is this with graph 0). */
+int percis_graph_estimate(percis_ctx* ctx, int32_t graph, double eps, double delta, uint64_t seed, double* p_out,
+                          percis_estimate_info* info);
+int percis_graph_set_vertex_diameter(percis_ctx* ctx, int32_t graph, int64_t D);
+
 /* Overrides VertexDiamUB with a caller-known bound D >= the maximum number of
  * internal nodes of any shortest path (D < 0 restores the default: a BFS per
  * connected component for undirected graphs, the largest weakly connected
@@ -183,6 +223,21 @@ int percis_debug_path(percis_ctx* ctx, int32_t s, int32_t t, uint64_t r, int32_t
 #define PERCIS_OPT_BITMAPS     4
 int percis_set_option(percis_ctx* ctx, int option, int64_t value);
 int percis_get_option(percis_ctx* ctx, int option, int64_t* value);
+
+/* Autotuner: times probe_samples samples of graph `graph` (stream phase 3,
+ * seed `seed`) under every launch shape that can run (threads per sample
+ * 256/512/1024, bitmaps in LDS when they fit or in device memory, slots
+ * filling the device) and keeps the fastest as the context's shape. The
+ * chosen shape is reported in *result (may be NULL). Results of sampling
+ * calls never depend on the shape. */
+typedef struct {
+    int32_t block;          /* threads per sample */
+    int32_t bitmaps;        /* 1 = device memory, 2 = LDS */
+    int32_t slots;          /* concurrent samples */
+    int32_t candidates;     /* shapes timed */
+    double samples_per_s;   /* probe throughput of the chosen shape */
+} percis_tuning;
+int percis_autotune(percis_ctx* ctx, int32_t graph, uint64_t probe_samples, uint64_t seed, percis_tuning* result);
 
 const char* percis_status_str(int status);
 const char* percis_last_error(const percis_ctx* ctx);

@@ -1,0 +1,117 @@
+// Library-internal host-side state of the PercIS library (not part of the ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "percis.h"
+#include "percis_internal.h"
+
+namespace percis {
+
+// One graph with its states: host copies in internal ids (nodes with arcs
+// first, caller order kept) and their device copies.
+struct GraphData {
+    bool has_graph = false, directed = false;
+    int32_t n = 0, n_act = 0;
+    int64_t m = 0;
+    std::vector<int32_t> h_rp, h_col;      // out-adjacency, rows sorted
+    std::vector<int32_t> h_irp, h_icol;    // in-adjacency (directed graphs only)
+    std::vector<int32_t> h_orig, h_newid;  // internal id -> caller id, and back
+    bool graph_on_device = false;
+    int32_t *d_rp = nullptr, *d_col = nullptr, *d_irp = nullptr, *d_icol = nullptr, *d_orig = nullptr;
+    uint32_t* d_hits = nullptr;            // hits buffer owned by the library
+
+    bool has_states = false;
+    uint64_t C = 0;
+    std::vector<double> d_v;               // C / S_v by caller id, 0 where S_v = 0
+    double d_hat = 1.0;
+    std::vector<int32_t> h_perm;           // rank -> internal id
+    std::vector<uint32_t> h_kr;
+    std::vector<uint64_t> h_W, h_P;
+    bool states_on_device = false;
+    int32_t* d_perm = nullptr;
+    uint32_t* d_kr = nullptr;
+    uint64_t *d_W = nullptr, *d_P = nullptr;
+
+    int64_t D_override = -1;
+};
+
+// A task as the host sees it: a sample range of one graph into device hits.
+struct TaskSpec {
+    int32_t graph;
+    uint32_t phase;
+    uint64_t first, count, seed;
+    uint32_t* d_hits;
+    bool accumulate;
+};
+
+}  // namespace percis
+
+struct percis_ctx {
+    int device = 0;
+    bool host_only = false;                // created with PERCIS_HOST_ONLY: validation and host math only
+    hipStream_t stream = nullptr;
+    std::string err;
+    int cu_count = 0;
+    double wall_hz = 0.0;                  // device wall-clock rate
+
+    std::vector<percis::GraphData*> graphs;  // [0] is the graph of percis_load_csr
+
+    void* slot_mem = nullptr;
+    int nslots = 0;
+    int64_t slot_act = 0;                  // largest graph (nodes with arcs) the slots fit
+    percis::DevSlots slots{};
+    percis::SamplerShape shape{};
+
+    percis::DevStats* d_stats = nullptr;   // launch-wide counters
+    unsigned long long* d_work = nullptr;
+    percis::DevTask* d_tasks = nullptr;
+    percis::DevStats* d_task_stats = nullptr;
+    int task_cap = 0;
+    percis::DebugOut* d_dbg = nullptr;
+    int32_t dbg_cap = 0;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+
+    int64_t opt_slots = 0, opt_scratch_mb = 0, opt_block = 0, opt_bitmaps = 0;
+};
+
+namespace percis {
+
+int fail(percis_ctx* c, int code, const char* fmt, ...);
+
+#define HIPCHK(c, expr)                                                                            \
+    do {                                                                                           \
+        hipError_t e_ = (expr);                                                                    \
+        if (e_ != hipSuccess)                                                                      \
+            return ::percis::fail((c), e_ == hipErrorOutOfMemory ? PERCIS_E_NOMEM : PERCIS_E_DEVICE, \
+                                  "%s: %s", #expr, hipGetErrorString(e_));                         \
+    } while (0)
+
+template <class T>
+void dfree(T*& p) {
+    if (p) (void)hipFree((void*)p);
+    p = nullptr;
+}
+
+template <class T>
+int dalloc(percis_ctx* c, T*& p, size_t count) {
+    dfree(p);
+    void* q = nullptr;
+    hipError_t e = hipMalloc(&q, sizeof(T) * (count ? count : 1));
+    if (e != hipSuccess)
+        return fail(c, PERCIS_E_NOMEM, "hipMalloc(%zu bytes): %s", sizeof(T) * count, hipGetErrorString(e));
+    p = (T*)q;
+    return PERCIS_OK;
+}
+
+int set_device(percis_ctx* c);
+int graph_upload(percis_ctx* c, GraphData& G, bool states);
+GraphData* get_graph(percis_ctx* c, int32_t id);
+int run_tasks(percis_ctx* c, const std::vector<TaskSpec>& tasks, std::vector<percis_stats>* out, percis_stats* launch);
+void bounds_from_phase1(const GraphData& G, uint64_t l1, uint64_t sum_I, uint64_t sum_I2, const uint32_t* h1,
+                        double eps, double delta, percis_estimate_info* I);
+int64_t vertex_diam_ub(const GraphData& G);
+
+}  // namespace percis

@@ -55,11 +55,27 @@ struct DevStats {
     unsigned long long phase_ticks[5];   // summed over workgroups, wall-clock ticks
 };
 
-struct SampleLaunch {
+// One task of a launch: samples first .. first+count-1 of stream
+// (seed, phase) on one graph. A launch runs many tasks (possibly on different
+// graphs) through one persistent grid; the launch's sample index space is the
+// concatenation of the tasks' ranges.
+struct DevTask {
+    DevGraph g;
+    DevCdf cdf;
     uint64_t first, count, seed, phase;
-    uint32_t* hits;                  // [n] by caller id
-    DevStats* stats;
-    unsigned long long* work;        // next unclaimed sample offset
+    uint32_t* hits;                  // [g.n] by caller id
+    DevStats* stats;                 // this task's sample statistics
+    unsigned long long offset;       // launch index of the task's first sample
+    uint32_t clear_hits;             // zero hits before sampling
+    uint32_t pad;
+};
+
+struct SampleLaunch {
+    const DevTask* tasks;            // device array
+    int ntasks;
+    unsigned long long total;        // sum of the tasks' counts
+    unsigned long long* work;        // next unclaimed launch index
+    DevStats* stats;                 // launch-wide work counters and phase times
     int slots;                       // grid size
 };
 
@@ -82,8 +98,10 @@ struct SamplerShape {
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t count, hipStream_t stream);
 hipError_t launch_fill_u8(void* p, int64_t bytes, hipStream_t stream);
 hipError_t launch_init_stats(DevStats* st, unsigned long long* work, hipStream_t stream);
-hipError_t launch_sampler(const DevGraph& g, const DevCdf& cdf, const DevSlots& slots, const SampleLaunch& a,
-                          const SamplerShape& shape, hipStream_t stream);
+// Zeroes every task's statistics and, where asked, its hits (one launch).
+hipError_t launch_clear_tasks(const DevTask* tasks, int ntasks, int64_t max_n, hipStream_t stream);
+hipError_t launch_sampler(const DevSlots& slots, const SampleLaunch& a, const SamplerShape& shape,
+                          hipStream_t stream);
 hipError_t launch_debug_path(const DevGraph& g, const DevSlots& slots, int32_t s, int32_t t, uint64_t r,
                              DebugOut* out, int32_t cap, const SamplerShape& shape, hipStream_t stream);
 // Resident workgroups per CU for a shape (0 if it cannot launch).

@@ -153,7 +153,7 @@ struct SampleShared {
     int32_t ovf;
     int32_t walk_err;
     uint64_t sigma;
-    unsigned long long n_samples, n_reach, sum_I, sum_I2, n_ovf, first_ovf;
+    int32_t task;
     unsigned long long phase_ticks[5];  // pair, BFS, meeting + DAG sweep, walk, clearing
 };
 
@@ -399,7 +399,7 @@ __device__ __forceinline__ void level_barrier() { __syncthreads(); }
 // path is written to dbg (internal ids).
 template <int BSZ, bool LDS>
 __device__ void run_sample(const DevGraph& g, const DevCdf& cdf, const DevSlots& sl, int64_t so,
-                           const Bits<LDS>& bits, int64_t words, uint64_t idx, const SampleLaunch& a,
+                           const Bits<LDS>& bits, uint64_t idx, const DevTask& T,
                            SampleShared& sh, Counters& cn, DebugOut* dbg, int32_t dbg_s, int32_t dbg_t,
                            uint64_t dbg_r, int32_t dbg_cap) {
     using B = Bits<LDS>;
@@ -427,11 +427,11 @@ __device__ void run_sample(const DevGraph& g, const DevCdf& cdf, const DevSlots&
     if (wid == 0) {
         int32_t s, t;
         if (!dbg) {
-            const uint64_t Us = draw_bounded(a.seed, a.phase, idx, 0, cdf.C);
+            const uint64_t Us = draw_bounded(T.seed, T.phase, idx, 0, cdf.C);
             const uint64_t* P = cdf.P;
             const int32_t sr = wave_search(1, cdf.n, [&](int32_t d) { return Us < P[d]; });
             const uint64_t cs = P[sr] - P[sr - 1];
-            const uint64_t Ut = draw_bounded(a.seed, a.phase, idx, 1, cs);
+            const uint64_t Ut = draw_bounded(T.seed, T.phase, idx, 1, cs);
             const uint64_t ks = cdf.kr[sr], Ws = cdf.W[sr];
             const uint64_t* W = cdf.W;
             const int32_t tr = wave_search(sr + 1, cdf.n, [&](int32_t d) {
@@ -559,7 +559,7 @@ __device__ void run_sample(const DevGraph& g, const DevCdf& cdf, const DevSlots&
         // ---- canonical backward walk by wave 0
         if (!sh.ovf && wid == 0) {
             const int32_t aM = sh.a;
-            uint64_t r = dbg ? dbg_r : draw_bounded(a.seed, a.phase, idx, 2, sh.sigma);
+            uint64_t r = dbg ? dbg_r : draw_bounded(T.seed, T.phase, idx, 2, sh.sigma);
             int32_t w = sh.t;
             int err = 0;
             for (int32_t p = L - 1; p >= 1; p--) {
@@ -598,7 +598,7 @@ __device__ void run_sample(const DevGraph& g, const DevCdf& cdf, const DevSlots&
                     if (dbg) {
                         if (p < dbg_cap) dbg->path[p] = w;
                     } else {
-                        atomicAdd(a.hits + g.orig[w], 1u);
+                        atomicAdd(T.hits + g.orig[w], 1u);
                     }
                     cn.V++;
                 }
@@ -611,19 +611,23 @@ __device__ void run_sample(const DevGraph& g, const DevCdf& cdf, const DevSlots&
 
     // ---- per-sample statistics
     if (tid == 0) {
-        sh.n_samples++;
-        if (sh.status == 1) {
-            if (sh.ovf || sh.walk_err) {
-                sh.n_ovf++;
-                if (idx < sh.first_ovf) sh.first_ovf = idx;
-            } else {
-                const unsigned long long I = (unsigned long long)(L - 1);
-                sh.n_reach++;
-                sh.sum_I += I;
-                sh.sum_I2 += I * I;
+        if (!dbg) {
+            DevStats* st = T.stats;
+            atomicAdd(&st->samples, 1ull);
+            if (sh.status == 1) {
+                if (sh.ovf || sh.walk_err) {
+                    atomicAdd(&st->overflow, 1ull);
+                    atomicMin(&st->first_overflow, (unsigned long long)idx);
+                } else {
+                    const unsigned long long I = (unsigned long long)(L - 1);
+                    atomicAdd(&st->reachable, 1ull);
+                    if (I) {
+                        atomicAdd(&st->sum_I, I);
+                        atomicAdd(&st->sum_I2, I * I);
+                    }
+                }
             }
-        }
-        if (dbg) {
+        } else {
             dbg->L = sh.status == 1 ? L : -1;
             dbg->overflow = (sh.status == 1 && (sh.ovf || sh.walk_err)) ? (sh.walk_err ? 2 : 1) : 0;
             dbg->sigma = sh.status == 1 ? (sh.ovf ? ~0ull : sh.sigma) : 0;
@@ -692,7 +696,7 @@ __device__ __forceinline__ Bits<LDS> slot_bits(const DevSlots& sl, int slot) {
 }
 
 template <int BSZ, bool LDS>
-__global__ __launch_bounds__(BSZ) void sampler_kernel(DevGraph g, DevCdf cdf, DevSlots sl, SampleLaunch a) {
+__global__ __launch_bounds__(BSZ) void sampler_kernel(DevSlots sl, SampleLaunch L) {
     __shared__ SampleShared sh;
     const int tid = threadIdx.x;
     const int64_t so = (int64_t)blockIdx.x * sl.stride;
@@ -702,26 +706,32 @@ __global__ __launch_bounds__(BSZ) void sampler_kernel(DevGraph g, DevCdf cdf, De
         for (int64_t i = tid; i < 3 * sl.words; i += BSZ) dyn_lds[i] = 0;
     }
     if (tid == 0) {
-        sh.n_samples = sh.n_reach = sh.sum_I = sh.sum_I2 = sh.n_ovf = 0;
-        sh.first_ovf = ~0ull;
         for (int i = 0; i < 5; i++) sh.phase_ticks[i] = 0;
     }
     for (;;) {
-        if (tid == 0) sh.idx = atomicAdd(a.work, 1ull);
+        if (tid == 0) {
+            const unsigned long long q = atomicAdd(L.work, 1ull);
+            sh.idx = q;
+            if (q < L.total) {
+                // the task holding launch index q: last task with offset <= q
+                int lo = 0, hi = L.ntasks - 1;
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (L.tasks[mid].offset <= q) lo = mid; else hi = mid - 1;
+                }
+                sh.task = lo;
+            }
+        }
         __syncthreads();
         const unsigned long long q = sh.idx;
-        if (q >= a.count) break;
-        run_sample<BSZ, LDS>(g, cdf, sl, so, bits, sl.words, a.first + q, a, sh, cn, nullptr, 0, 0, 0, 0);
+        if (q >= L.total) break;
+        const int k = __builtin_amdgcn_readfirstlane(sh.task);
+        const DevTask& T = L.tasks[k];
+        run_sample<BSZ, LDS>(T.g, T.cdf, sl, so, bits, T.first + (q - T.offset), T, sh, cn, nullptr, 0, 0, 0, 0);
     }
-    flush_counters(cn, a.stats);
+    flush_counters(cn, L.stats);
     if (tid == 0) {
-        atomicAdd(&a.stats->samples, sh.n_samples);
-        atomicAdd(&a.stats->reachable, sh.n_reach);
-        atomicAdd(&a.stats->sum_I, sh.sum_I);
-        atomicAdd(&a.stats->sum_I2, sh.sum_I2);
-        atomicAdd(&a.stats->overflow, sh.n_ovf);
-        atomicMin(&a.stats->first_overflow, sh.first_ovf);
-        for (int i = 0; i < 5; i++) atomicAdd(&a.stats->phase_ticks[i], sh.phase_ticks[i]);
+        for (int i = 0; i < 5; i++) atomicAdd(&L.stats->phase_ticks[i], sh.phase_ticks[i]);
     }
 }
 
@@ -735,14 +745,12 @@ __global__ __launch_bounds__(BSZ) void debug_path_kernel(DevGraph g, DevSlots sl
         for (int64_t i = threadIdx.x; i < 3 * sl.words; i += BSZ) dyn_lds[i] = 0;
     }
     if (threadIdx.x == 0) {
-        sh.n_samples = sh.n_reach = sh.sum_I = sh.sum_I2 = sh.n_ovf = 0;
-        sh.first_ovf = ~0ull;
         for (int i = 0; i < 5; i++) sh.phase_ticks[i] = 0;
     }
     __syncthreads();
     DevCdf none = {};
-    SampleLaunch a = {};
-    run_sample<BSZ, LDS>(g, none, sl, 0, bits, sl.words, 0, a, sh, cn, out, s, t, r, cap);
+    DevTask T = {};
+    run_sample<BSZ, LDS>(g, none, sl, 0, bits, 0, T, sh, cn, out, s, t, r, cap);
 }
 
 __global__ void fill_u32_kernel(uint32_t* p, uint32_t v, int64_t count) {
@@ -770,6 +778,23 @@ __global__ void init_stats_kernel(DevStats* st, unsigned long long* work) {
     }
 }
 
+__global__ void clear_tasks_kernel(const DevTask* tasks, int ntasks) {
+    const int k = blockIdx.y;
+    if (k >= ntasks) return;
+    const DevTask& T = tasks[k];
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        DevStats* st = T.stats;
+        st->samples = st->reachable = st->sum_I = st->sum_I2 = st->overflow = 0;
+        st->first_overflow = ~0ull;
+        st->edges = st->sigma_adds = st->vexp = st->vdisc = 0;
+        for (int i = 0; i < 5; i++) st->phase_ticks[i] = 0;
+    }
+    if (T.clear_hits) {
+        for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < T.g.n; i += (int64_t)gridDim.x * blockDim.x)
+            T.hits[i] = 0;
+    }
+}
+
 static int fill_grid(int64_t n) {
     int64_t b = (n + 255) / 256;
     if (b < 1) b = 1;
@@ -791,6 +816,14 @@ hipError_t launch_fill_u8(void* p, int64_t bytes, hipStream_t stream) {
 
 hipError_t launch_init_stats(DevStats* st, unsigned long long* work, hipStream_t stream) {
     hipLaunchKernelGGL(init_stats_kernel, dim3(1), dim3(64), 0, stream, st, work);
+    return hipGetLastError();
+}
+
+hipError_t launch_clear_tasks(const DevTask* tasks, int ntasks, int64_t max_n, hipStream_t stream) {
+    if (ntasks <= 0) return hipSuccess;
+    int64_t bx = (max_n + 255) / 256;
+    bx = bx < 1 ? 1 : (bx > 512 ? 512 : bx);
+    hipLaunchKernelGGL(clear_tasks_kernel, dim3((unsigned)bx, (unsigned)ntasks), dim3(256), 0, stream, tasks, ntasks);
     return hipGetLastError();
 }
 
@@ -821,15 +854,15 @@ int sampler_occupancy(const SamplerShape& s) {
     return blocks;
 }
 
-hipError_t launch_sampler(const DevGraph& g, const DevCdf& cdf, const DevSlots& slots, const SampleLaunch& a,
-                          const SamplerShape& shape, hipStream_t stream) {
-    if (a.count == 0 || a.slots <= 0) return hipSuccess;
+hipError_t launch_sampler(const DevSlots& slots, const SampleLaunch& a, const SamplerShape& shape,
+                          hipStream_t stream) {
+    if (a.total == 0 || a.slots <= 0) return hipSuccess;
     const void* fn = pick_sampler(shape);
     if (!fn) return hipErrorInvalidValue;
     const size_t dyn = shape.lds_bitmaps ? (size_t)shape.lds_bytes : 0;
     if (dyn > 0) (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn);
     (void)hipGetLastError();
-    void* args[] = {(void*)&g, (void*)&cdf, (void*)&slots, (void*)&a};
+    void* args[] = {(void*)&slots, (void*)&a};
     return hipLaunchKernel(fn, dim3(a.slots), dim3(shape.block), args, dyn, stream);
 }
 

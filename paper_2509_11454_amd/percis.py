@@ -56,6 +56,19 @@ class EstimateInfo(C.Structure):
                 for k, t in self._fields_}
 
 
+class Task(C.Structure):
+    _fields_ = [("graph", C.c_int32), ("phase", C.c_uint32), ("first", C.c_uint64), ("count", C.c_uint64),
+                ("seed", C.c_uint64), ("hits", C.c_void_p), ("flags", C.c_uint32), ("stats", C.POINTER(Stats))]
+
+
+class Tuning(C.Structure):
+    _fields_ = [("block", C.c_int32), ("bitmaps", C.c_int32), ("slots", C.c_int32), ("candidates", C.c_int32),
+                ("samples_per_s", C.c_double)]
+
+    def to_dict(self):
+        return {k: (float(getattr(self, k)) if t is C.c_double else int(getattr(self, k))) for k, t in self._fields_}
+
+
 _P = C.c_void_p
 _SIGS = {
     "percis_create": (C.c_int, [C.c_int, _P, C.POINTER(_P)]),
@@ -70,6 +83,14 @@ _SIGS = {
     "percis_set_vertex_diameter": (C.c_int, [_P, C.c_int64]),
     "percis_debug_path": (C.c_int, [_P, C.c_int32, C.c_int32, C.c_uint64, _P, C.c_int32,
                                     C.POINTER(C.c_int32), C.POINTER(C.c_uint64), C.POINTER(C.c_int32)]),
+    "percis_add_graph": (C.c_int, [_P, C.c_int32, C.c_int64, _P, _P, _P, C.c_uint32, C.POINTER(C.c_int32)]),
+    "percis_graph_info": (C.c_int, [_P, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int64),
+                                    C.POINTER(C.c_int32)]),
+    "percis_sample_tasks": (C.c_int, [_P, C.c_int32, C.POINTER(Task), C.POINTER(Stats)]),
+    "percis_graph_estimate": (C.c_int, [_P, C.c_int32, C.c_double, C.c_double, C.c_uint64, _P,
+                                        C.POINTER(EstimateInfo)]),
+    "percis_graph_set_vertex_diameter": (C.c_int, [_P, C.c_int32, C.c_int64]),
+    "percis_autotune": (C.c_int, [_P, C.c_int32, C.c_uint64, C.c_uint64, C.POINTER(Tuning)]),
     "percis_set_option": (C.c_int, [_P, C.c_int, C.c_int64]),
     "percis_get_option": (C.c_int, [_P, C.c_int, C.POINTER(C.c_int64)]),
     "percis_status_str": (C.c_char_p, [C.c_int]),
@@ -201,6 +222,53 @@ class Context:
         L, sig, ovf = int(L.value), int(sig.value), int(ovf.value)
         path = [int(v) for v in buf[:L + 1]] if (L >= 0 and not ovf and r < sig and L + 1 <= cap) else None
         return L, sig, ovf, path
+
+    def add_graph(self, n, row_ptr, col, k, directed=False):
+        """Adds a graph with its states; returns its id."""
+        rp = np.ascontiguousarray(row_ptr, dtype=np.int32)
+        cl = np.ascontiguousarray(col, dtype=np.int32)
+        kk = np.ascontiguousarray(k, dtype=np.uint16)
+        gid = C.c_int32()
+        self._check(_lib.percis_add_graph(self._h, int(n), int(cl.size), _np_ptr(rp), _np_ptr(cl), _np_ptr(kk),
+                                          DIRECTED if directed else 0, C.byref(gid)))
+        return int(gid.value)
+
+    def graph_info(self, graph):
+        n, m, na = C.c_int32(), C.c_int64(), C.c_int32()
+        self._check(_lib.percis_graph_info(self._h, int(graph), C.byref(n), C.byref(m), C.byref(na)))
+        return int(n.value), int(m.value), int(na.value)
+
+    def sample_tasks(self, tasks, allow_overflow=False):
+        """tasks: list of dicts with graph, first, count, seed, phase, hits
+        (int32 device tensor), accumulate. Returns (per-task stats, launch stats)."""
+        arr = (Task * len(tasks))()
+        sts = [Stats() for _ in tasks]
+        for i, t in enumerate(tasks):
+            h = t["hits"]
+            assert isinstance(h, torch.Tensor) and h.is_cuda and h.dtype == torch.int32
+            arr[i] = Task(int(t["graph"]), int(t.get("phase", 0)), int(t.get("first", 0)), int(t["count"]),
+                          int(t["seed"]), C.c_void_p(h.data_ptr()), ACCUMULATE if t.get("accumulate") else 0,
+                          C.pointer(sts[i]))
+        ls = Stats()
+        rc = _lib.percis_sample_tasks(self._h, len(tasks), arr, C.byref(ls))
+        self._check(rc, allow=(E_SIGMA_OVERFLOW,) if allow_overflow else ())
+        return [s.to_dict() for s in sts], ls.to_dict()
+
+    def graph_estimate(self, graph, eps, delta, seed):
+        n = self.graph_info(graph)[0]
+        p = np.zeros(n, np.float64)
+        info = EstimateInfo()
+        self._check(_lib.percis_graph_estimate(self._h, int(graph), float(eps), float(delta), int(seed), _np_ptr(p),
+                                               C.byref(info)))
+        return p, info.to_dict()
+
+    def graph_set_vertex_diameter(self, graph, D):
+        return self._check(_lib.percis_graph_set_vertex_diameter(self._h, int(graph), int(D)))
+
+    def autotune(self, graph=0, probe_samples=20000, seed=12345):
+        t = Tuning()
+        self._check(_lib.percis_autotune(self._h, int(graph), int(probe_samples), int(seed), C.byref(t)))
+        return t.to_dict()
 
     def set_option(self, opt, value):
         return self._check(_lib.percis_set_option(self._h, int(opt), int(value)))

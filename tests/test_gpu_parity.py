@@ -275,3 +275,51 @@ def test_directed_prop7_estimate():
     pe = O.exact(og, st)
     assert np.abs(p - pe).max() <= 0.05
     assert np.all(p[[0] + list(range(2, g.n))] == 0.0)
+
+
+def test_tasks_many_graphs_one_launch():
+    """Tasks on five graphs (undirected, directed, tiny, with isolated nodes)
+    in one launch: every task's hits and statistics equal the oracle's for
+    its own graph, range, seed and phase, whatever the mix."""
+    import torch
+    from paper_2509_11454_amd import percis as P
+    rng = np.random.default_rng(21)
+    graphs = [W.workload_er1000(), (W.ba_graph(3000, 4, 5), None), (W.random_small_graph(70, 0.05, 8, True), None),
+              (W.path_graph(30), None), W.with_isolated_component(W.er_graph(200, 500, 4), 30)]
+    graphs = [(g, k if k is not None else W.uniform_states(g.n, rng)) for g, k in graphs]
+    c = P.Context(0)
+    g0, k0 = graphs[0]
+    c.load_csr(g0.n, g0.row_ptr, g0.col)
+    c.set_states(k0)
+    ids = [0] + [c.add_graph(g.n, g.row_ptr, g.col, k, directed=g.directed) for g, k in graphs[1:]]
+    assert c.graph_info(ids[1])[0] == graphs[1][0].n
+    tasks = []
+    for i, (gid, (g, k)) in enumerate(zip(ids, graphs)):
+        for j, (first, count) in enumerate([(0, 700), (5000 + 13 * i, 300)]):
+            tasks.append(dict(graph=gid, first=first, count=count, seed=40 + i, phase=j,
+                              hits=torch.zeros(g.n, dtype=torch.int32, device="cuda")))
+    stats, launch = c.sample_tasks(tasks)
+    assert launch["samples"] == sum(t["count"] for t in tasks)
+    for t, st in zip(tasks, stats):
+        g, k = graphs[ids.index(t["graph"])]
+        og, sto = oracle_objects(g, k)
+        ho, so = O.sample_range(og, sto, t["first"], t["count"], t["seed"], t["phase"])
+        assert np.array_equal(t["hits"].cpu().numpy().view(np.uint32), ho), (g.name, t["first"])
+        same_stats(so, st)
+    # graph estimate on an added graph meets eps against the exact values
+    p, info = c.graph_estimate(ids[1], 0.05, 0.1, 9)
+    og, sto = oracle_objects(*graphs[1])
+    assert np.abs(p - O.exact(og, sto)).max() <= 0.05
+
+
+def test_autotune_keeps_results():
+    from paper_2509_11454_amd import percis as P
+    g, k = W.workload_er1000()
+    c = gpu_context(g, k)
+    h0, s0 = gpu_hits(c, 0, 4000, 17)
+    t = c.autotune(0, 5000)
+    assert t["candidates"] >= 3 and t["block"] in (256, 512, 1024) and t["bitmaps"] in (1, 2)
+    assert c.get_option(P.OPT_BLOCK) == t["block"]
+    h1, s1 = gpu_hits(c, 0, 4000, 17)
+    assert np.array_equal(h0, h1)
+    same_stats(s0, s1)
