@@ -239,6 +239,40 @@ typedef struct {
 } percis_tuning;
 int percis_autotune(percis_ctx* ctx, int32_t graph, uint64_t probe_samples, uint64_t seed, percis_tuning* result);
 
+/* ---- serving: continuous batching of centrality queries ----
+ * A server runs Algorithm 1 queries (graph, eps, delta, seed) over the graphs
+ * resident in its context. Queries wait in arrival order until their hit
+ * buffer (4 bytes per node, device memory owned by the server) fits in
+ * memory_budget_bytes; admitted queries advance in chunks of at most
+ * chunk_samples samples, and each percis_server_step is one launch that
+ * carries a chunk of every active query, up to step_samples samples in all,
+ * so queries of different graphs share the device and a query submitted
+ * while others run joins at the next step. A query's result is the same
+ * alone or in any mix, and equals percis_graph_estimate with the same
+ * arguments. The server is used from one host thread at a time. */
+typedef struct percis_server percis_server;
+int percis_server_create(percis_ctx* ctx, int64_t memory_budget_bytes, uint64_t chunk_samples,
+                         uint64_t step_samples, percis_server** out);
+void percis_server_destroy(percis_server* server);
+/* Queues a query; returns its id. */
+int percis_server_submit(percis_server* server, int32_t graph, double eps, double delta, uint64_t seed,
+                         int64_t* query_id);
+/* Admits what fits, runs one batched launch, advances the queries and
+ * retires finished ones; *completed (may be NULL) counts queries that
+ * finished a phase-2 or failed in this step. Does nothing if no query is
+ * active or queued. */
+int percis_server_step(percis_server* server, int32_t* completed);
+/* *done = 1 once the query has finished: its estimate is copied to p_out
+ * (host, n_cap >= n of its graph; may be NULL), its summary to info (may be
+ * NULL), the query is forgotten, and the query's own status is returned
+ * (PERCIS_OK, or the error that stopped it). *done = 0 while it runs. */
+int percis_server_result(percis_server* server, int64_t query_id, int32_t* done, double* p_out, int32_t n_cap,
+                         percis_estimate_info* info);
+/* Queue lengths, device bytes held by admitted queries (now and at peak),
+ * and samples drawn so far. Any pointer may be NULL. */
+int percis_server_status(percis_server* server, int32_t* queued, int32_t* active, int64_t* bytes_in_use,
+                         int64_t* peak_bytes, uint64_t* samples_done);
+
 const char* percis_status_str(int status);
 const char* percis_last_error(const percis_ctx* ctx);
 

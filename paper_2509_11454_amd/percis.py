@@ -91,6 +91,14 @@ _SIGS = {
                                         C.POINTER(EstimateInfo)]),
     "percis_graph_set_vertex_diameter": (C.c_int, [_P, C.c_int32, C.c_int64]),
     "percis_autotune": (C.c_int, [_P, C.c_int32, C.c_uint64, C.c_uint64, C.POINTER(Tuning)]),
+    "percis_server_create": (C.c_int, [_P, C.c_int64, C.c_uint64, C.c_uint64, C.POINTER(_P)]),
+    "percis_server_destroy": (None, [_P]),
+    "percis_server_submit": (C.c_int, [_P, C.c_int32, C.c_double, C.c_double, C.c_uint64, C.POINTER(C.c_int64)]),
+    "percis_server_step": (C.c_int, [_P, C.POINTER(C.c_int32)]),
+    "percis_server_result": (C.c_int, [_P, C.c_int64, C.POINTER(C.c_int32), _P, C.c_int32,
+                                       C.POINTER(EstimateInfo)]),
+    "percis_server_status": (C.c_int, [_P, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int64),
+                                       C.POINTER(C.c_int64), C.POINTER(C.c_uint64)]),
     "percis_set_option": (C.c_int, [_P, C.c_int, C.c_int64]),
     "percis_get_option": (C.c_int, [_P, C.c_int, C.POINTER(C.c_int64)]),
     "percis_status_str": (C.c_char_p, [C.c_int]),
@@ -277,6 +285,62 @@ class Context:
         v = C.c_int64()
         self._check(_lib.percis_get_option(self._h, int(opt), C.byref(v)))
         return int(v.value)
+
+
+class Server:
+    """Continuous-batching query server over the graphs of a Context."""
+
+    def __init__(self, ctx, memory_budget_bytes, chunk_samples=8192, step_samples=262144):
+        self.ctx = ctx
+        h = C.c_void_p()
+        ctx._check(_lib.percis_server_create(ctx._h, int(memory_budget_bytes), int(chunk_samples),
+                                             int(step_samples), C.byref(h)))
+        self._h = h
+        self._n = {}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.percis_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def submit(self, graph, eps, delta, seed):
+        qid = C.c_int64()
+        self.ctx._check(_lib.percis_server_submit(self._h, int(graph), float(eps), float(delta), int(seed),
+                                                  C.byref(qid)))
+        self._n[int(qid.value)] = self.ctx.graph_info(graph)[0]
+        return int(qid.value)
+
+    def step(self):
+        done = C.c_int32()
+        self.ctx._check(_lib.percis_server_step(self._h, C.byref(done)))
+        return int(done.value)
+
+    def result(self, qid):
+        """None while running; else (status, p or None, info dict)."""
+        n = self._n[qid]
+        p = np.zeros(n, np.float64)
+        done = C.c_int32()
+        info = EstimateInfo()
+        rc = _lib.percis_server_result(self._h, int(qid), C.byref(done), _np_ptr(p), n, C.byref(info))
+        if not done.value:
+            if rc != OK:
+                self.ctx._check(rc)
+            return None
+        del self._n[qid]
+        return rc, (p if rc == OK else None), info.to_dict()
+
+    def status(self):
+        q, a, b, pk, sd = C.c_int32(), C.c_int32(), C.c_int64(), C.c_int64(), C.c_uint64()
+        self.ctx._check(_lib.percis_server_status(self._h, C.byref(q), C.byref(a), C.byref(b), C.byref(pk),
+                                                  C.byref(sd)))
+        return dict(queued=int(q.value), active=int(a.value), bytes_in_use=int(b.value), peak_bytes=int(pk.value),
+                    samples_done=int(sd.value))
 
 
 def raw_library():
