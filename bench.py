@@ -106,12 +106,21 @@ def main():
     ap.add_argument("--no-estimate", action="store_true")
     ap.add_argument("--one-per-launch", type=int, default=2000, metavar="N",
                     help="also time N samples drawn one per launch (0 = skip)")
+    ap.add_argument("--mode", default="single", choices=["single", "batch", "serve"],
+                    help="single: one graph (default); batch: 64 BA graphs in one launch; serve: query stream")
+    ap.add_argument("--queries", type=int, default=120, help="serve: queries per load level")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (reference for HBM counters)")
     args = ap.parse_args()
 
     if args.copy_calibration:
         copy_calibration(args.copy_calibration)
+        return
+    if args.mode == "batch":
+        run_batch(args)
+        return
+    if args.mode == "serve":
+        run_serve(args)
         return
 
     if args.gpus != 1:
@@ -232,6 +241,183 @@ def main():
         out["cpu_baseline"]["host"] = host_cpu_model()
         print("[bench] cpu baseline: %.1f samples/s" % out["cpu_baseline"]["value"], file=sys.stderr, flush=True)
 
+    print(json.dumps(out), flush=True)
+
+
+def run_batch(args):
+    """64 Barabasi-Albert graphs (m = 4, n log-uniform in [1e4, 1e6], own
+    uniform states) with 1e5 samples each: one autotuned launch over all
+    graphs, against 64 per-graph launches and one sample per launch."""
+    import torch
+    import workloads as W
+    from paper_2509_11454_amd import percis as P
+
+    per_graph = args.samples or 100_000
+    t0 = time.perf_counter()
+    graphs = W.workload_ba_batch(64, 4, args.seed)
+    print("[bench] 64 BA graphs: %d nodes, %d arcs in %.1f s" % (sum(g.n for g, _ in graphs),
+                                                                    sum(g.m for g, _ in graphs),
+                                                                    time.perf_counter() - t0),
+          file=sys.stderr, flush=True)
+    c = P.Context(0)
+    g0, k0 = graphs[0]
+    c.load_csr(g0.n, g0.row_ptr, g0.col)
+    c.set_states(k0)
+    ids = [0] + [c.add_graph(g.n, g.row_ptr, g.col, k) for g, k in graphs[1:]]
+    big = max(range(64), key=lambda i: graphs[i][0].n)
+    tune = c.autotune(ids[big], 20000)
+    print("[bench] autotune: %s" % tune, file=sys.stderr, flush=True)
+    hits = [torch.zeros(g.n, dtype=torch.int32, device="cuda") for g, _ in graphs]
+    tasks = [dict(graph=ids[i], first=0, count=per_graph, seed=args.seed + i, phase=0, hits=hits[i])
+             for i in range(64)]
+    for _ in range(args.warmup):
+        c.sample_tasks(tasks)
+    torch.cuda.synchronize()
+    kern = []
+    launch = None
+    t1 = time.perf_counter()
+    for _ in range(args.steps):
+        _, launch = c.sample_tasks(tasks)
+        kern.append(launch["kernel_ms"])
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t1
+    total = per_graph * 64
+    value = total * args.steps / elapsed
+    # the same work as 64 separate launches, one graph each
+    t2 = time.perf_counter()
+    for i in range(64):
+        c.sample_tasks([tasks[i]])
+    torch.cuda.synchronize()
+    seq_rate = total / (time.perf_counter() - t2)
+    # one sample per launch, on the median-size graph
+    mid = sorted(range(64), key=lambda i: graphs[i][0].n)[32]
+    one = dict(graph=ids[mid], first=0, count=1, seed=args.seed, phase=0, hits=hits[mid])
+    t3 = time.perf_counter()
+    nops = 500
+    for j in range(nops):
+        one["first"] = j
+        c.sample_tasks([one])
+    torch.cuda.synchronize()
+    opl_rate = nops / (time.perf_counter() - t3)
+    avg_kernel_s = sum(kern) / len(kern) / 1e3
+    b_alg = algorithmic_bytes(launch)
+    achieved = b_alg / avg_kernel_s / 1e9
+    out = {
+        "metric": METRIC, "value": value, "unit": "samples/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": elapsed / args.steps * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+        "config": {"workload": "64 Barabasi-Albert graphs (m=4, n log-uniform in [1e4, 1e6], uniform states), "
+                               "%d samples per graph in one launch" % per_graph,
+                   "nodes": sum(g.n for g, _ in graphs), "arcs": sum(g.m for g, _ in graphs), "tuning": tune},
+        "gteps": launch["edges"] * args.steps / elapsed / 1e9,
+        "per_graph_launches": {"value": seq_rate, "unit": "samples/s", "form": "64 launches, one graph each"},
+        "one_sample_per_launch": {"value": opl_rate, "unit": "samples/s", "samples": nops},
+        "speedup_vs_per_graph": value / seq_rate,
+        "speedup_vs_one_per_launch": value / opl_rate,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "sampler_kernel",
+                     "kernel_ms": avg_kernel_s * 1e3, "algorithmic_bytes_per_launch": b_alg},
+    }
+    print(json.dumps(out), flush=True)
+
+
+def run_serve(args):
+    """Poisson stream of centrality queries over 66 resident graphs (ER 1000,
+    R-MAT scale 18, 64 BA graphs): graph uniform, eps uniform in {0.01,
+    0.005, 0.001}, delta = 0.1, seed = query id. Capacity is measured with a
+    saturating burst; then streams at 50/80/95% of it give p50/p99 latency
+    (arrival to result) and aggregate samples/s, against one query at a time
+    (percis_graph_estimate per query, FIFO)."""
+    import numpy as np
+    import workloads as W
+    from paper_2509_11454_amd import percis as P
+
+    rng = np.random.default_rng(args.seed)
+    t0 = time.perf_counter()
+    g0, k0 = W.workload_er1000(args.seed)
+    c = P.Context(0)
+    c.load_csr(g0.n, g0.row_ptr, g0.col)
+    c.set_states(k0)
+    g1, k1 = W.workload_rmat18(args.seed)
+    ids = [0, c.add_graph(g1.n, g1.row_ptr, g1.col, k1)]
+    for g, k in W.workload_ba_batch(64, 4, args.seed):
+        ids.append(c.add_graph(g.n, g.row_ptr, g.col, k))
+    print("[bench] 66 graphs resident in %.1f s" % (time.perf_counter() - t0), file=sys.stderr, flush=True)
+    budget = 256 << 20
+    chunk, step = 65536, 524288
+
+    def make_queries(nq, base):
+        return [(ids[int(rng.integers(0, len(ids)))], float(rng.choice([0.01, 0.005, 0.001])), 0.1, base + i)
+                for i in range(nq)]
+
+    def drive(queries, arrivals):
+        srv = P.Server(c, budget, chunk, step)
+        t_start = time.perf_counter()
+        pending = list(range(len(queries)))
+        qid = {}
+        lat = [None] * len(queries)
+        samples = 0
+        while any(x is None for x in lat):
+            now = time.perf_counter() - t_start
+            while pending and arrivals[pending[0]] <= now:
+                i = pending.pop(0)
+                qid[i] = srv.submit(*queries[i])
+            if not qid or all(lat[i] is not None for i in qid):
+                if pending:
+                    time.sleep(max(0.0, min(0.01, arrivals[pending[0]] - now)))
+                continue
+            srv.step()
+            t_now = time.perf_counter() - t_start
+            for i, q in qid.items():
+                if lat[i] is None:
+                    r = srv.result(q)
+                    if r is not None:
+                        rc, p, info = r
+                        assert rc == 0, rc
+                        lat[i] = t_now - arrivals[i]
+                        samples += info["l1"] + info["l"]
+        wall = time.perf_counter() - t_start
+        st = srv.status()
+        srv.close()
+        return lat, wall, samples, st
+
+    # capacity: a saturating burst
+    burst = make_queries(args.queries, 10_000)
+    lat, wall, samples, _ = drive(burst, [0.0] * len(burst))
+    cap_qps = len(burst) / wall
+    print("[bench] capacity %.2f queries/s, %.3g samples/s" % (cap_qps, samples / wall), file=sys.stderr, flush=True)
+    # one query at a time on the same burst (service times for a FIFO model)
+    service = []
+    for q in burst:
+        t = time.perf_counter()
+        c.graph_estimate(*q)
+        service.append(time.perf_counter() - t)
+    levels = {}
+    for load in (0.5, 0.8, 0.95):
+        lam = load * cap_qps
+        queries = make_queries(args.queries, int(load * 1e6))
+        gaps = rng.exponential(1.0 / lam, size=len(queries))
+        arrivals = list(np.cumsum(gaps) - gaps[0])
+        lat, wall, samples, st = drive(queries, arrivals)
+        # FIFO single server with the measured one-at-a-time service times
+        seq_service = [service[i % len(service)] for i in range(len(queries))]
+        fin, seq_lat = 0.0, []
+        for a, sv in zip(arrivals, seq_service):
+            fin = max(fin, a) + sv
+            seq_lat.append(fin - a)
+        levels["%d%%" % int(load * 100)] = {
+            "arrival_qps": lam, "p50_ms": float(np.percentile(lat, 50) * 1e3),
+            "p99_ms": float(np.percentile(lat, 99) * 1e3), "samples_per_s": samples / wall,
+            "peak_admitted_bytes": st["peak_bytes"],
+            "one_at_a_time_p50_ms": float(np.percentile(seq_lat, 50) * 1e3),
+            "one_at_a_time_p99_ms": float(np.percentile(seq_lat, 99) * 1e3)}
+        print("[bench] load %.0f%%: %s" % (load * 100, levels["%d%%" % int(load * 100)]), file=sys.stderr, flush=True)
+    out = {"metric": METRIC, "value": levels["80%"]["samples_per_s"], "unit": "samples/s", "n_gpus": 1,
+           "higher_is_better": True, "dtype": "u64", "data": "synthetic", "vs_baseline": None,
+           "config": {"workload": "Poisson query stream over 66 resident graphs (ER 1000, R-MAT 18, 64 BA); "
+                                  "eps in {0.01, 0.005, 0.001}, delta 0.1; %d queries per load" % args.queries,
+                      "memory_budget_bytes": budget, "chunk": chunk, "step_samples": step},
+           "capacity_qps": cap_qps, "one_at_a_time_qps": len(service) / sum(service), "levels": levels}
     print(json.dumps(out), flush=True)
 
 
