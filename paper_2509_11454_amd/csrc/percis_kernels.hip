@@ -150,6 +150,7 @@ struct SampleShared {
     int32_t tail, tail_s, tail_t, tail_d;
     int32_t nmeet;
     int32_t status;   // 0 running, 1 met, 2 unreachable
+    int32_t side;     // side of the level being built
     int32_t ovf;
     int32_t walk_err;
     uint64_t sigma;
@@ -236,7 +237,7 @@ __device__ __forceinline__ int chunk_owner(const SampleShared& sh, int cnt, int 
     return l2;
 }
 
-constexpr int UNROLL = 4;
+constexpr int UNROLL = 8;
 
 // One BFS level over the frontier q[lo, hi) of one side (SIDE 0: s, out-arcs;
 // SIDE 1: t, in-arcs), edge-balanced: the rows of up to CH frontier nodes are
@@ -314,7 +315,7 @@ __device__ void expand_bfs(const DevGraph& g, const DevSlots& sl, int64_t so, co
                 }
             }
         }
-        __syncthreads();
+        if (base + CH < hi) __syncthreads();  // the caller's barrier follows the last chunk
     }
 }
 
@@ -351,7 +352,7 @@ __device__ void expand_sweep(const DevGraph& g, const DevSlots& sl, int64_t so, 
                 }
             }
         }
-        __syncthreads();
+        if (base + CH < hi) __syncthreads();  // the caller's barrier follows the last chunk
     }
 }
 
@@ -384,6 +385,17 @@ __device__ void finish_level(const Bits<LDS>& bits, int32_t* q, uint64_t* sg, ui
         if (smax) atomicMax(&sh.max_next, smax);
         if (of) atomicOr(&sh.ovf_next, 1u);
     }
+}
+
+// Next BFS level: the side with the smaller frontier degree sum (Section
+// III-B's balanced expansion), its queue's append position, fresh
+// accumulators. Called by one thread.
+__device__ __forceinline__ void plan_level(SampleShared& sh) {
+    sh.side = (sh.deg_s <= sh.deg_t) ? 0 : 1;
+    sh.tail = sh.side == 0 ? sh.hi_s : sh.hi_t;
+    sh.deg_next = 0;
+    sh.max_next = 0;
+    sh.ovf_next = 0;
 }
 
 __device__ __forceinline__ bool may_wrap(unsigned long long deg, unsigned long long smax, uint32_t ovf) {
@@ -464,6 +476,7 @@ __device__ void run_sample(const DevGraph& g, const DevCdf& cdf, const DevSlots&
                 sh.deg_t = (unsigned long long)(g.irp[t + 1] - g.irp[t]);
                 sh.max_s = 1; sh.max_t = 1; sh.ovf_s = 0; sh.ovf_t = 0;
                 sh.tail_s = 1; sh.tail_t = 1;
+                plan_level(sh);
             }
         }
     }
@@ -471,18 +484,12 @@ __device__ void run_sample(const DevGraph& g, const DevCdf& cdf, const DevSlots&
     phase_mark(0);
 
     // ---- balanced bidirectional BFS
+    // Thread 0 plans each level (side, append position, fresh accumulators)
+    // inside the previous level's last barrier.
     while (sh.status == 0) {
-        const int side = (sh.deg_s <= sh.deg_t) ? 0 : 1;
+        const int side = sh.side;
         const int nlo = side == 0 ? sh.hi_s : sh.hi_t;
         const bool careful = side == 0 ? may_wrap(sh.deg_s, sh.max_s, sh.ovf_s) : may_wrap(sh.deg_t, sh.max_t, sh.ovf_t);
-        __syncthreads();
-        if (tid == 0) {
-            sh.tail = nlo;
-            sh.deg_next = 0;
-            sh.max_next = 0;
-            sh.ovf_next = 0;
-        }
-        __syncthreads();
         if (side == 0) expand_bfs<0, BSZ, LDS>(g, sl, so, bits, sh.lo_s, sh.hi_s, (uint32_t)sh.a + 2, careful, sh, cn);
         else expand_bfs<1, BSZ, LDS>(g, sl, so, bits, sh.lo_t, sh.hi_t, (uint32_t)sh.b + 2, careful, sh, cn);
         level_barrier();
@@ -500,6 +507,7 @@ __device__ void run_sample(const DevGraph& g, const DevCdf& cdf, const DevSlots&
             }
             if (sh.nmeet > 0) sh.status = 1;
             else if (nhi == nlo) sh.status = 2;
+            else plan_level(sh);
         }
         level_barrier();
     }
