@@ -209,6 +209,13 @@ int percis_set_vertex_diameter(percis_ctx* ctx, int64_t D);
 int percis_debug_path(percis_ctx* ctx, int32_t s, int32_t t, uint64_t r, int32_t* path, int32_t cap,
                       int32_t* L, uint64_t* sigma, int32_t* overflow);
 
+/* Exact percolation centrality of graph `graph` (Definition 1, Eq. 1) on the
+ * device, by Brandes-style dependency accumulation from every source (the
+ * paper's exact baseline, Section IV-A): p_out[n] (host), p := 0 where S_v =
+ * 0; *kernel_ms (may be NULL) gets the device time. O(n m) work; the sums are
+ * in double, so results agree with a serial computation to rounding. */
+int percis_exact(percis_ctx* ctx, int32_t graph, double* p_out, double* kernel_ms);
+
 /* Tuning knobs (launch shape only; results never depend on them).
  * PERCIS_OPT_SLOTS: concurrent samples (resident workgroups), 0 = auto.
  * PERCIS_OPT_SCRATCH_MB: cap on the sampler's scratch memory, 0 = auto.

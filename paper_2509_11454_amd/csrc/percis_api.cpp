@@ -59,6 +59,8 @@ static void graph_clear_states(GraphData& G) {
     G.has_states = false;
     G.states_on_device = false;
     G.d_v.clear();
+    G.S_v.clear();
+    G.h_k.clear();
     G.h_perm.clear();
     G.h_kr.clear();
     G.h_W.clear();
@@ -192,18 +194,21 @@ static int graph_set_states(percis_ctx* c, GraphData& G, const uint16_t* k_in, u
     std::vector<uint64_t> cnt(65537, 0), sum(65537, 0);
     for (int32_t v = 0; v < n; v++) { cnt[k[v] + 1]++; sum[k[v] + 1] += k[v]; }
     for (int i = 0; i < 65536; i++) { cnt[i + 1] += cnt[i]; sum[i + 1] += sum[i]; }
-    std::vector<double> dv(n, 0.0);
+    std::vector<double> dv(n, 0.0), Svv(n, 0.0);
     double dh = 1.0;
     for (int32_t v = 0; v < n; v++) {
         const uint64_t kv = k[v];
         const uint64_t lo = cnt[kv] * kv - sum[kv];
         const uint64_t hi = (sum[65536] - sum[kv + 1]) - (cnt[65536] - cnt[kv + 1]) * kv;
         const uint64_t Sv = C - (lo + hi);
+        Svv[v] = (double)Sv;
         dv[v] = Sv ? (double)C / (double)Sv : 0.0;
         dh = std::max(dh, dv[v]);
     }
     graph_clear_states(G);
     G.d_v.swap(dv);
+    G.S_v.swap(Svv);
+    G.h_k.swap(k);
     G.d_hat = dh;
     G.C = C;
     G.h_perm.swap(perm);
@@ -960,6 +965,62 @@ int percis_get_option(percis_ctx* c, int option, int64_t* value) {
     *value = option == PERCIS_OPT_SLOTS ? c->nslots
            : option == PERCIS_OPT_BLOCK ? c->shape.block
                                         : (c->shape.lds_bitmaps ? 2 : 1);
+    return PERCIS_OK;
+}
+
+int percis_exact(percis_ctx* c, int32_t graph, double* p_out, double* kernel_ms) {
+    if (!c) return PERCIS_E_INVAL;
+    GraphData* G = get_graph(c, graph);
+    if (!G) return fail(c, PERCIS_E_INVAL, "no graph %d", graph);
+    if (!G->has_graph || !G->has_states) return fail(c, PERCIS_E_STATE, "graph %d has no states", graph);
+    if (!p_out) return fail(c, PERCIS_E_INVAL, "null output");
+    int rc = graph_upload(c, *G, true);
+    if (rc) return rc;
+    const int32_t n = G->n, na = std::max<int32_t>(G->n_act, 1);
+    const int64_t stride = ((int64_t)na + 63) / 64 * 64;
+    std::vector<uint16_t> kint(n);
+    for (int32_t v = 0; v < n; v++) kint[G->h_newid[v]] = G->h_k[v];
+    uint16_t* d_k = nullptr;
+    double* d_out = nullptr;
+    void* scratch = nullptr;
+    size_t free_b = 0, total_b = 0;
+    HIPCHK(c, hipMemGetInfo(&free_b, &total_b));
+    int slots = std::max(1, c->cu_count * 2);
+    while (slots > 1 && exact_scratch_bytes(stride, slots) > (int64_t)(free_b * 0.5)) slots /= 2;
+    const int64_t bytes = exact_scratch_bytes(stride, slots);
+    auto cleanup = [&]() {
+        dfree(d_k);
+        dfree(d_out);
+        if (scratch) (void)hipFree(scratch);
+        scratch = nullptr;
+    };
+    if ((rc = dalloc(c, d_k, (size_t)n)) || (rc = dalloc(c, d_out, (size_t)na))) {
+        cleanup();
+        return rc;
+    }
+    if (hipMalloc(&scratch, (size_t)bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        cleanup();
+        return fail(c, PERCIS_E_NOMEM, "cannot allocate %lld bytes of scratch", (long long)bytes);
+    }
+    hipError_t e = hipMemcpyAsync(d_k, kint.data(), sizeof(uint16_t) * n, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = launch_fill_u8(scratch, bytes, c->stream);
+    if (e == hipSuccess) e = launch_init_stats(c->d_stats, c->d_work, c->stream);
+    if (e == hipSuccess) e = hipEventRecord(c->ev0, c->stream);
+    if (e == hipSuccess) e = launch_exact(dev_graph(*G), d_k, scratch, stride, slots, c->d_work, d_out, c->stream);
+    if (e == hipSuccess) e = hipEventRecord(c->ev1, c->stream);
+    std::vector<double> num(na);
+    if (e == hipSuccess) e = hipMemcpyAsync(num.data(), d_out, sizeof(double) * na, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, c->ev0, c->ev1);
+    cleanup();
+    if (e != hipSuccess) return fail(c, PERCIS_E_DEVICE, "exact centrality: %s", hipGetErrorString(e));
+    for (int32_t v = 0; v < n; v++) {
+        const int32_t i = G->h_newid[v];
+        p_out[v] = (i < G->n_act && G->S_v[v] > 0) ? num[i] / G->S_v[v] : 0.0;
+    }
+    if (kernel_ms) *kernel_ms = ms;
     return PERCIS_OK;
 }
 

@@ -26,6 +26,8 @@ struct GraphData {
     bool has_states = false;
     uint64_t C = 0;
     std::vector<double> d_v;               // C / S_v by caller id, 0 where S_v = 0
+    std::vector<double> S_v;               // S_v by caller id (units of 1/65535)
+    std::vector<uint16_t> h_k;             // states by caller id
     double d_hat = 1.0;
     std::vector<int32_t> h_perm;           // rank -> internal id
     std::vector<uint32_t> h_kr;

@@ -104,6 +104,12 @@ hipError_t launch_sampler(const DevSlots& slots, const SampleLaunch& a, const Sa
                           hipStream_t stream);
 hipError_t launch_debug_path(const DevGraph& g, const DevSlots& slots, int32_t s, int32_t t, uint64_t r,
                              DebugOut* out, int32_t cap, const SamplerShape& shape, hipStream_t stream);
+// Exact percolation centrality: per-slot scratch of exact_scratch_bytes
+// (all-zero on entry), sum over sources of the dependencies into out[n_act].
+hipError_t launch_exact(const DevGraph& g, const uint16_t* k, void* scratch, int64_t stride, int slots,
+                        unsigned long long* work, double* out, hipStream_t stream);
+int64_t exact_scratch_bytes(int64_t stride, int slots);
+
 // Resident workgroups per CU for a shape (0 if it cannot launch).
 int sampler_occupancy(const SamplerShape& shape);
 int64_t sampler_static_lds();

@@ -99,6 +99,7 @@ _SIGS = {
                                        C.POINTER(EstimateInfo)]),
     "percis_server_status": (C.c_int, [_P, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int64),
                                        C.POINTER(C.c_int64), C.POINTER(C.c_uint64)]),
+    "percis_exact": (C.c_int, [_P, C.c_int32, _P, C.POINTER(C.c_double)]),
     "percis_set_option": (C.c_int, [_P, C.c_int, C.c_int64]),
     "percis_get_option": (C.c_int, [_P, C.c_int, C.POINTER(C.c_int64)]),
     "percis_status_str": (C.c_char_p, [C.c_int]),
@@ -272,6 +273,14 @@ class Context:
 
     def graph_set_vertex_diameter(self, graph, D):
         return self._check(_lib.percis_graph_set_vertex_diameter(self._h, int(graph), int(D)))
+
+    def exact(self, graph=0):
+        """Exact percolation centrality on the device; returns (p, kernel ms)."""
+        n = self.graph_info(graph)[0]
+        p = np.zeros(n, np.float64)
+        ms = C.c_double()
+        self._check(_lib.percis_exact(self._h, int(graph), _np_ptr(p), C.byref(ms)))
+        return p, float(ms.value)
 
     def autotune(self, graph=0, probe_samples=20000, seed=12345):
         t = Tuning()

@@ -323,3 +323,25 @@ def test_autotune_keeps_results():
     h1, s1 = gpu_hits(c, 0, 4000, 17)
     assert np.array_equal(h0, h1)
     same_stats(s0, s1)
+
+
+@pytest.mark.parametrize("ci", [0, 4, 6, 8, 11, 13, 15])
+def test_exact_centrality_on_device(ci):
+    """percis_exact against the oracle's exact centrality (both sum in
+    double in different orders: relative 1e-9, absolute 1e-12)."""
+    g, k = special_cases()[ci]
+    c = gpu_context(g, k)
+    p, ms = c.exact(0)
+    og, st = oracle_objects(g, k)
+    pe = O.exact(og, st)
+    assert np.allclose(p, pe, rtol=1e-9, atol=1e-12), (g.name, np.abs(p - pe).max())
+
+
+def test_exact_er1000_and_estimate_within_eps():
+    g, k = W.workload_er1000()
+    c = gpu_context(g, k)
+    p, ms = c.exact(0)
+    og, st = oracle_objects(g, k)
+    assert np.allclose(p, O.exact(og, st), rtol=1e-9, atol=1e-12)
+    pe, info = c.estimate(0.01, 0.1, 5)
+    assert np.abs(pe - p).max() <= 0.01
