@@ -298,7 +298,7 @@ static void free_slots(percis_ctx* c) {
     c->slots = DevSlots{};
 }
 
-constexpr int64_t kSlotBytesPerNode = 4 + 4 + 8 + 8 + 4 + 4 + 4;
+constexpr int64_t kSlotBytesPerNode = (int64_t)sizeof(NodeRec) + 4 + 4 + 4 + 4;
 constexpr int64_t kLdsPerCu = 160 * 1024;
 
 static int64_t bitmap_words(int64_t act) { return ((std::max<int64_t>(act, 1) + 31) / 32 + 63) / 64 * 64; }
@@ -340,7 +340,7 @@ static int ensure_slots(percis_ctx* c, int64_t act) {
     if (rc) return rc;
     const int64_t stride = (act + 63) / 64 * 64;
     const int64_t words = bitmap_words(act);
-    const int64_t per_slot = stride * kSlotBytesPerNode + (sh.lds_bitmaps ? 0 : 3 * words * 4);
+    const int64_t per_slot = stride * kSlotBytesPerNode + 8 + (sh.lds_bitmaps ? 0 : 3 * words * 4);
     size_t free_b = 0, total_b = 0;
     HIPCHK(c, hipMemGetInfo(&free_b, &total_b));
     const int64_t budget = c->opt_scratch_mb > 0 ? c->opt_scratch_mb * (1ll << 20) : (int64_t)(free_b * 0.6);
@@ -364,13 +364,11 @@ static int ensure_slots(percis_ctx* c, int64_t act) {
     s.stride = stride;
     s.words = words;
     const int64_t cnt = ns * stride;
-    s.lv_s = (uint32_t*)p; p += cnt * 4;
-    s.lv_t = (uint32_t*)p; p += cnt * 4;
-    s.sg_s = (uint64_t*)p; p += cnt * 8;
-    s.sg_t = (uint64_t*)p; p += cnt * 8;
+    s.rec = (NodeRec*)p; p += cnt * (int64_t)sizeof(NodeRec);
     s.q_s = (int32_t*)p; p += cnt * 4;
     s.q_t = (int32_t*)p; p += cnt * 4;
     s.q_d = (int32_t*)p; p += cnt * 4;
+    s.tls = (int32_t*)p; p += ns * (stride + 2) * 4;
     s.bm = sh.lds_bitmaps ? nullptr : (uint32_t*)p;
     c->slot_mem = mem;
     c->slots = s;

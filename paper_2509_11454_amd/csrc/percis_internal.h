@@ -33,16 +33,25 @@ struct DevCdf {
     const uint64_t* P;     // [n+1]  P[i] = sum_{j <= i} c_j, c_j = (n-j+1) kr[j] - W[j]
 };
 
+// Per-node scratch of a slot: levels (value = level + 1, 0 = unreached, plus
+// flag bits) and shortest-path counts from both ends, in one 32-byte record so
+// that a visited node touches one memory sector.
+struct NodeRec {
+    uint32_t lv_s;
+    uint32_t lv_t;
+    uint64_t sg_s;
+    uint64_t sg_t;
+    uint64_t pad;
+};
+
 // Per-slot scratch; every array is [slots][stride] (stride >= n_act) and is
 // all-zero between samples (each sample clears what it touched).
 struct DevSlots {
-    uint32_t* lv_s;   // s-side level + 1 (0 = unreached), plus flag bits
-    uint32_t* lv_t;   // t-side level + 1, plus flag bits
-    uint64_t* sg_s;   // shortest-path counts from s
-    uint64_t* sg_t;   // shortest-path counts to t
+    NodeRec* rec;     // per-node records
     int32_t* q_s;     // s-side BFS queue (levels are contiguous segments)
     int32_t* q_t;     // t-side BFS queue
-    int32_t* q_d;     // t-side shortest-path DAG, level by level
+    int32_t* q_d;     // meeting layer
+    int32_t* tls;     // [slots][stride + 2] start of each t-level in q_t
     int64_t stride;   // elements per slot
     uint32_t* bm;     // visited bitmaps when they do not live in LDS: [slots][3][words]
     int64_t words;    // 32-bit words per bitmap

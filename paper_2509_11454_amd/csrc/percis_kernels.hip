@@ -1,15 +1,15 @@
 // PercIS sampler kernels for gfx950 (MI355X).
 //
-// One persistent workgroup per slot. A slot owns per-node scratch (levels and
-// shortest-path counts from both ends, three queues) that is all-zero between
-// samples; every sample clears exactly what it touched. Visited sets are
-// bitmaps -- in LDS when they fit, otherwise in the slot's global scratch --
-// so that the per-edge test touches one bit instead of a level word.
-// Workgroups claim sample indices from a global counter, so the grid can be
-// smaller or larger than the number of samples and results never depend on
-// the launch shape: every sample's randomness is keyed on its index
-// (Philox4x64-10, counter (index, variate, attempt, 0), key (seed, phase)),
-// and all accumulation is integer.
+// One persistent workgroup per slot. A slot owns per-node scratch (one 32-byte
+// record per node holding the levels and shortest-path counts from both ends,
+// and three queues) that is all-zero between samples; every sample clears
+// exactly what it touched. Visited sets are bitmaps -- in LDS when they fit,
+// otherwise in the slot's scratch -- so that the per-edge test touches one
+// bit. Workgroups claim launch indices from a global counter; a launch is a
+// table of tasks (sample ranges of possibly different graphs), and results
+// never depend on the launch shape: every sample's randomness is keyed on its
+// index (Philox4x64-10, counter (index, variate, attempt, 0), key
+// (seed, phase)), and all accumulation is integer.
 //
 // Per sample (Algorithm 2 of the paper's appendix, then RandomSP of
 // Section III-B):
@@ -22,15 +22,16 @@
 //      balanced across the workgroup; the first level that reaches the other
 //      ball fixes d(s,t) = L and the meeting layer M, and
 //      sigma_st = sum_{w in M} sigma_s(w) sigma_t(w).
-//   3. shortest-path counts from s are pushed from M through the part of the
-//      shortest-path DAG inside the t-ball, so that every DAG node knows
-//      sigma_s.
+//   3. shortest-path counts from s are pulled level by level from M down to
+//      t through the t-ball (each t-side node sums the counts of its
+//      in-neighbours one level farther from t), so that every node of the
+//      shortest-path DAG knows sigma_s.
 //   4. r uniform in [0, sigma_st); the canonical backward walk from t takes,
 //      among the in-neighbours one level closer to s (ascending id), the
 //      first whose cumulative sigma_s exceeds r (a 64-lane prefix scan per
 //      chunk of the in-row); every node passed on the way is an internal node
 //      of the chosen path and gets one hit.
-// A sigma that reaches 2^64 anywhere on the way to t is caught by a flag that
+// A count that reaches 2^64 anywhere on the way to t is caught by a flag that
 // is set on a wrapping add and propagated along DAG arcs; the sample then adds
 // no hits and is counted as overflowed.
 #include "percis_internal.h"
@@ -39,8 +40,8 @@ namespace percis {
 
 constexpr int CH = 256;  // frontier nodes staged per chunk
 constexpr uint32_t LVMASK = 0x0FFFFFFFu;
-constexpr uint32_t DAGBIT = 0x20000000u;
 constexpr uint32_t OVFBIT = 0x40000000u;
+constexpr int UNROLL = 8;
 
 // Slot scratch is private to one workgroup (one CU), so every access to it is
 // a workgroup-scope atomic: coherent among the workgroup's waves without the
@@ -56,6 +57,12 @@ __device__ __forceinline__ uint64_t add64(uint64_t* p, uint64_t v) {
     return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, WGS);
 }
 
+// Field access by side: 0 = s side, 1 = t side.
+template <int SIDE>
+__device__ __forceinline__ uint32_t* LV(NodeRec* R, int32_t w) { return SIDE ? &R[w].lv_t : &R[w].lv_s; }
+template <int SIDE>
+__device__ __forceinline__ uint64_t* SG(NodeRec* R, int32_t w) { return SIDE ? &R[w].sg_t : &R[w].sg_s; }
+
 // Visited bitmaps: three planes per slot -- s-side visited, t-side visited,
 // and "reached in the level being built" (shared by both sides, since only
 // one side grows at a time).
@@ -64,22 +71,21 @@ struct Bits {
     uint32_t* vs;
     uint32_t* vt;
     uint32_t* nw;
-    static constexpr int SCOPE = __HIP_MEMORY_SCOPE_WORKGROUP;
     __device__ __forceinline__ static uint32_t rd(uint32_t* p, int32_t w) {
-        return __hip_atomic_load(p + (w >> 5), __ATOMIC_RELAXED, SCOPE);
+        return __hip_atomic_load(p + (w >> 5), __ATOMIC_RELAXED, WGS);
     }
     __device__ __forceinline__ static uint32_t rd_acq(uint32_t* p, int32_t w) {
-        return __hip_atomic_load(p + (w >> 5), __ATOMIC_ACQUIRE, SCOPE);
+        return __hip_atomic_load(p + (w >> 5), __ATOMIC_ACQUIRE, WGS);
     }
     __device__ __forceinline__ static uint32_t set(uint32_t* p, int32_t w) {
-        return __hip_atomic_fetch_or(p + (w >> 5), 1u << (w & 31), __ATOMIC_RELAXED, SCOPE);
+        return __hip_atomic_fetch_or(p + (w >> 5), 1u << (w & 31), __ATOMIC_RELAXED, WGS);
     }
     __device__ __forceinline__ static uint32_t set_rel(uint32_t* p, int32_t w) {
-        return __hip_atomic_fetch_or(p + (w >> 5), 1u << (w & 31), __ATOMIC_ACQ_REL, SCOPE);
+        return __hip_atomic_fetch_or(p + (w >> 5), 1u << (w & 31), __ATOMIC_ACQ_REL, WGS);
     }
     __device__ __forceinline__ static bool test(uint32_t word, int32_t w) { return (word >> (w & 31)) & 1u; }
     __device__ __forceinline__ static void clear_word(uint32_t* p, int32_t w) {
-        __hip_atomic_store(p + (w >> 5), 0u, __ATOMIC_RELAXED, SCOPE);
+        __hip_atomic_store(p + (w >> 5), 0u, __ATOMIC_RELAXED, WGS);
     }
 };
 
@@ -147,7 +153,7 @@ struct SampleShared {
     unsigned long long deg_s, deg_t, deg_next;       // frontier degree sums
     unsigned long long max_s, max_t, max_next;       // largest count in each frontier
     uint32_t ovf_s, ovf_t, ovf_next;                 // a frontier count overflowed
-    int32_t tail, tail_s, tail_t, tail_d;
+    int32_t tail, tail_s, tail_t;
     int32_t nmeet;
     int32_t status;   // 0 running, 1 met, 2 unreachable
     int32_t side;     // side of the level being built
@@ -155,7 +161,7 @@ struct SampleShared {
     int32_t walk_err;
     uint64_t sigma;
     int32_t task;
-    unsigned long long phase_ticks[5];  // pair, BFS, meeting + DAG sweep, walk, clearing
+    unsigned long long phase_ticks[5];  // pair, BFS, meeting + DAG, walk, clearing
 };
 
 struct Counters {
@@ -197,12 +203,13 @@ __device__ __forceinline__ uint64_t wave_incl_scan_u64(uint64_t v) {
     return v;
 }
 
-// Stages up to CH frontier nodes q[base, base+cnt) in LDS: row start, degree
-// prefix sum, shortest-path count and overflow flag of each; returns the
-// number of adjacency entries of the chunk. Every thread must call it.
-template <int BSZ>
-__device__ __forceinline__ int stage_chunk(int32_t* q, int base, int cnt, const int32_t* rp, uint64_t* sg,
-                                           uint32_t* lv, bool read_ovf, SampleShared& sh, Counters& cn) {
+// Stages up to CH frontier nodes q[base, base+cnt) of side SIDE in LDS: row
+// start, degree prefix sum, shortest-path count and overflow flag of each;
+// returns the number of adjacency entries of the chunk. Every thread must
+// call it.
+template <int BSZ, int SIDE>
+__device__ __forceinline__ int stage_chunk(int32_t* q, int base, int cnt, const int32_t* rp, NodeRec* R,
+                                           bool read_ovf, SampleShared& sh, Counters& cn) {
     const int tid = threadIdx.x;
     int deg = 0, beg = 0;
     uint64_t su = 0;
@@ -211,8 +218,8 @@ __device__ __forceinline__ int stage_chunk(int32_t* q, int base, int cnt, const 
         const int32_t u = ldq(q + base + tid);
         beg = rp[u];
         deg = rp[u + 1] - beg;
-        su = ld64(sg + u);
-        if (read_ovf) of = (ld32(lv + u) & OVFBIT) ? 1 : 0;
+        su = ld64(SG<SIDE>(R, u));
+        if (read_ovf) of = (ld32(LV<SIDE>(R, u)) & OVFBIT) ? 1 : 0;
         cn.V++;
     }
     int total;
@@ -237,8 +244,6 @@ __device__ __forceinline__ int chunk_owner(const SampleShared& sh, int cnt, int 
     return l2;
 }
 
-constexpr int UNROLL = 8;
-
 // One BFS level over the frontier q[lo, hi) of one side (SIDE 0: s, out-arcs;
 // SIDE 1: t, in-arcs), edge-balanced: the rows of up to CH frontier nodes are
 // concatenated and the workgroup strides over the concatenation, UNROLL
@@ -258,14 +263,13 @@ __device__ void expand_bfs(const DevGraph& g, const DevSlots& sl, int64_t so, co
     const int32_t* rp = SIDE ? g.irp : g.rp;
     const int32_t* col = SIDE ? g.icol : g.col;
     int32_t* q = (SIDE ? sl.q_t : sl.q_s) + so;
-    uint32_t* lv = (SIDE ? sl.lv_t : sl.lv_s) + so;
-    uint64_t* sg = (SIDE ? sl.sg_t : sl.sg_s) + so;
+    NodeRec* R = sl.rec + so;
     uint32_t* vis_mine = SIDE ? bits.vt : bits.vs;
     uint32_t* vis_other = SIDE ? bits.vs : bits.vt;
 
     for (int base = lo; base < hi; base += CH) {
         const int cnt = min(CH, hi - base);
-        const int total = stage_chunk<BSZ>(q, base, cnt, rp, sg, lv, careful, sh, cn);
+        const int total = stage_chunk<BSZ, SIDE>(q, base, cnt, rp, R, careful, sh, cn);
         for (int e0 = tid; e0 < total; e0 += BSZ * UNROLL) {
             int32_t w[UNROLL];
             int jj[UNROLL];
@@ -296,15 +300,15 @@ __device__ void expand_bfs(const DevGraph& g, const DevSlots& sl, int64_t so, co
                 if (add) {
                     const uint64_t addv = sh.sig[j];
                     if (careful) {
-                        const uint64_t old = add64(sg + x, addv);
-                        if (old + addv < old || sh.of[j]) or32(lv + x, OVFBIT);
+                        const uint64_t old = add64(SG<SIDE>(R, x), addv);
+                        if (old + addv < old || sh.of[j]) or32(LV<SIDE>(R, x), OVFBIT);
                     } else {
-                        (void)add64(sg + x, addv);
+                        (void)add64(SG<SIDE>(R, x), addv);
                     }
                     cn.A++;
                 }
                 if (fresh) {
-                    or32(lv + x, nl);
+                    or32(LV<SIDE>(R, x), nl);
                     const int pos = atomicAdd(&sh.tail, 1);
                     q[pos] = x;
                     cn.Vd++;
@@ -319,40 +323,48 @@ __device__ void expand_bfs(const DevGraph& g, const DevSlots& sl, int64_t so, co
     }
 }
 
-// One level of the DAG sweep inside the t-ball (out-arcs): frontier nodes
-// q_d[lo, hi) have t-level value nl + 1; out-neighbours with t-level value nl
-// lie on the DAG, receive sigma_s and join q_d. No count here exceeds
-// sigma_st, which is known to be below 2^64.
+// One level of the t-side pull: every node x of q_t[lo, hi) (t-level j - 1)
+// adds the sigma_s of its in-neighbours at t-level j (t-level value
+// want = j + 1). Counts of nodes off the shortest-path DAG are 0, so only
+// DAG arcs add. No count here exceeds sigma_st, known to be below 2^64.
 template <int BSZ, bool LDS>
-__device__ void expand_sweep(const DevGraph& g, const DevSlots& sl, int64_t so, const Bits<LDS>& bits, int lo, int hi,
-                             uint32_t nl, SampleShared& sh, Counters& cn) {
+__device__ void pull_level(const DevGraph& g, const DevSlots& sl, int64_t so, const Bits<LDS>& bits, int lo, int hi,
+                           uint32_t want, SampleShared& sh, Counters& cn) {
     using B = Bits<LDS>;
     const int tid = threadIdx.x;
-    int32_t* q = sl.q_d + so;
-    uint32_t* lv_t = sl.lv_t + so;
-    uint64_t* sg_s = sl.sg_s + so;
+    int32_t* q = sl.q_t + so;
+    NodeRec* R = sl.rec + so;
     for (int base = lo; base < hi; base += CH) {
         const int cnt = min(CH, hi - base);
-        const int total = stage_chunk<BSZ>(q, base, cnt, g.rp, sg_s, lv_t, false, sh, cn);
+        int deg = 0, beg = 0;
+        int32_t x = 0;
+        if (tid < cnt) {
+            x = ldq(q + base + tid);
+            beg = g.irp[x];
+            deg = g.irp[x + 1] - beg;
+            cn.V++;
+        }
+        int total;
+        const int ex = chunk_excl_scan<BSZ>(deg, sh.wsum, total);
+        if (tid < CH) {
+            sh.beg[tid] = beg;
+            sh.off[tid] = ex;
+            sh.sig[tid] = (uint64_t)(uint32_t)x;
+        }
+        __syncthreads();
         for (int e = tid; e < total; e += BSZ) {
             const int j = chunk_owner(sh, cnt, e);
-            const int32_t w = g.col[sh.beg[j] + (e - sh.off[j])];
+            const int32_t u = g.icol[sh.beg[j] + (e - sh.off[j])];
             cn.E++;
-            if (!B::test(B::rd(bits.vt, w), w)) continue;
-            const uint32_t lt = ld32(lv_t + w);
-            if ((lt & LVMASK) != nl) continue;
-            (void)add64(sg_s + w, sh.sig[j]);
-            cn.A++;
-            if (!(lt & DAGBIT)) {
-                const uint32_t old = or32(lv_t + w, DAGBIT);
-                if (!(old & DAGBIT)) {
-                    const int pos = atomicAdd(&sh.tail, 1);
-                    q[pos] = w;
-                    cn.Vd++;
-                }
+            if (!B::test(B::rd(bits.vt, u), u)) continue;
+            if ((ld32(&R[u].lv_t) & LVMASK) != want) continue;
+            const uint64_t su = ld64(&R[u].sg_s);
+            if (su) {
+                (void)add64(&R[(int32_t)sh.sig[j]].sg_s, su);
+                cn.A++;
             }
         }
-        if (base + CH < hi) __syncthreads();  // the caller's barrier follows the last chunk
+        if (base + CH < hi) __syncthreads();
     }
 }
 
@@ -360,18 +372,18 @@ __device__ void expand_sweep(const DevGraph& g, const DevSlots& sl, int64_t so, 
 // and gathers, for the next expansion of that side, the degree sum of the
 // new frontier, its largest shortest-path count and whether any count
 // overflowed.
-template <int BSZ, bool LDS>
-__device__ void finish_level(const Bits<LDS>& bits, int32_t* q, uint64_t* sg, uint32_t* lv, const int32_t* drp,
-                             int lo, int hi, SampleShared& sh) {
+template <int BSZ, bool LDS, int SIDE>
+__device__ void finish_level(const Bits<LDS>& bits, int32_t* q, NodeRec* R, const int32_t* drp, int lo, int hi,
+                             SampleShared& sh) {
     unsigned long long dsum = 0, smax = 0;
     uint32_t of = 0;
     for (int i = lo + (int)threadIdx.x; i < hi; i += BSZ) {
         const int32_t w = ldq(q + i);
         Bits<LDS>::clear_word(bits.nw, w);
         dsum += (unsigned long long)(drp[w + 1] - drp[w]);
-        const uint64_t sv = ld64(sg + w);
+        const uint64_t sv = ld64(SG<SIDE>(R, w));
         smax = sv > smax ? sv : smax;
-        of |= ld32(lv + w) & OVFBIT;
+        of |= ld32(LV<SIDE>(R, w)) & OVFBIT;
     }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
@@ -416,13 +428,11 @@ __device__ void run_sample(const DevGraph& g, const DevCdf& cdf, const DevSlots&
                            uint64_t dbg_r, int32_t dbg_cap) {
     using B = Bits<LDS>;
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-    uint32_t* lv_s = sl.lv_s + so;
-    uint32_t* lv_t = sl.lv_t + so;
-    uint64_t* sg_s = sl.sg_s + so;
-    uint64_t* sg_t = sl.sg_t + so;
+    NodeRec* R = sl.rec + so;
     int32_t* q_s = sl.q_s + so;
     int32_t* q_t = sl.q_t + so;
     int32_t* q_d = sl.q_d + so;
+    int32_t* tls = sl.tls + (int64_t)blockIdx.x * (sl.stride + 2);  // start of each t-level in q_t
 
     // phase timers (thread 0, constant-rate wall clock)
     unsigned long long tm_prev = 0;
@@ -459,7 +469,6 @@ __device__ void run_sample(const DevGraph& g, const DevCdf& cdf, const DevSlots&
             sh.s = s;
             sh.t = t;
             sh.nmeet = 0; sh.ovf = 0; sh.walk_err = 0; sh.sigma = 0;
-            sh.tail_d = 0;
             sh.a = 0; sh.b = 0;
             if (s >= g.n_act || t >= g.n_act) {
                 // a node without arcs reaches nothing and is reached by nothing
@@ -469,8 +478,9 @@ __device__ void run_sample(const DevGraph& g, const DevCdf& cdf, const DevSlots&
                 sh.status = 0;
                 B::set(bits.vs, s);
                 B::set(bits.vt, t);
-                or32(lv_s + s, 1u); sg_s[s] = 1; q_s[0] = s;
-                or32(lv_t + t, 1u); sg_t[t] = 1; q_t[0] = t;
+                or32(&R[s].lv_s, 1u); R[s].sg_s = 1; q_s[0] = s;
+                or32(&R[t].lv_t, 1u); R[t].sg_t = 1; q_t[0] = t;
+                tls[0] = 0; tls[1] = 1;
                 sh.lo_s = 0; sh.hi_s = 1; sh.lo_t = 0; sh.hi_t = 1;
                 sh.deg_s = (unsigned long long)(g.rp[s + 1] - g.rp[s]);
                 sh.deg_t = (unsigned long long)(g.irp[t + 1] - g.irp[t]);
@@ -494,8 +504,8 @@ __device__ void run_sample(const DevGraph& g, const DevCdf& cdf, const DevSlots&
         else expand_bfs<1, BSZ, LDS>(g, sl, so, bits, sh.lo_t, sh.hi_t, (uint32_t)sh.b + 2, careful, sh, cn);
         level_barrier();
         const int nhi = sh.tail;
-        if (side == 0) finish_level<BSZ, LDS>(bits, q_s, sg_s, lv_s, g.rp, nlo, nhi, sh);
-        else finish_level<BSZ, LDS>(bits, q_t, sg_t, lv_t, g.irp, nlo, nhi, sh);
+        if (side == 0) finish_level<BSZ, LDS, 0>(bits, q_s, R, g.rp, nlo, nhi, sh);
+        else finish_level<BSZ, LDS, 1>(bits, q_t, R, g.irp, nlo, nhi, sh);
         level_barrier();
         if (tid == 0) {
             if (side == 0) {
@@ -504,6 +514,7 @@ __device__ void run_sample(const DevGraph& g, const DevCdf& cdf, const DevSlots&
             } else {
                 sh.lo_t = nlo; sh.hi_t = nhi; sh.tail_t = nhi; sh.b++;
                 sh.deg_t = sh.deg_next; sh.max_t = sh.max_next; sh.ovf_t = sh.ovf_next;
+                tls[sh.b + 1] = nhi;
             }
             if (sh.nmeet > 0) sh.status = 1;
             else if (nhi == nlo) sh.status = 2;
@@ -523,45 +534,38 @@ __device__ void run_sample(const DevGraph& g, const DevCdf& cdf, const DevSlots&
             uint64_t acc = 0;
             int of = 0;
             for (int i = lane; i < sh.nmeet; i += 64) {
-                int32_t w = ldq(q_d + i);
-                uint32_t ls = ld32(lv_s + w), lt = ld32(lv_t + w);
+                const int32_t w = ldq(q_d + i);
+                const uint32_t ls = ld32(&R[w].lv_s), lt = ld32(&R[w].lv_t);
                 of |= ((ls | lt) & OVFBIT) ? 1 : 0;
-                uint64_t x = ld64(sg_s + w), y = ld64(sg_t + w);
+                const uint64_t x = ld64(&R[w].sg_s), y = ld64(&R[w].sg_t);
                 if (__umul64hi(x, y) != 0) of = 1;
-                uint64_t p = x * y;
-                uint64_t na = acc + p;
+                const uint64_t p = x * y;
+                const uint64_t na = acc + p;
                 if (na < acc) of = 1;
                 acc = na;
-                or32(lv_t + w, DAGBIT);
             }
 #pragma unroll
             for (int o = 32; o > 0; o >>= 1) {
-                uint64_t oa = __shfl_xor(acc, o, 64);
-                int oo = __shfl_xor(of, o, 64);
-                uint64_t na = acc + oa;
+                const uint64_t oa = __shfl_xor(acc, o, 64);
+                const int oo = __shfl_xor(of, o, 64);
+                const uint64_t na = acc + oa;
                 of |= oo | (na < acc ? 1 : 0);
                 acc = na;
             }
             if (lane == 0) {
                 sh.sigma = acc;
                 sh.ovf = of;
-                sh.tail = sh.nmeet;
             }
         }
         level_barrier();
 
-        // ---- sigma_s through the t-ball part of the DAG, level by level
-        if (!sh.ovf && sh.b > 0) {
-            int lo = 0, hi = sh.nmeet;
+        // ---- sigma_s pulled through the t-ball, from t-level b - 1 down to t
+        if (!sh.ovf) {
             for (int j = sh.b; j >= 1; j--) {
-                expand_sweep<BSZ, LDS>(g, sl, so, bits, lo, hi, (uint32_t)j, sh, cn);
+                pull_level<BSZ, LDS>(g, sl, so, bits, ldq(tls + j - 1), ldq(tls + j), (uint32_t)j + 1, sh, cn);
                 level_barrier();
-                lo = hi;
-                hi = sh.tail;
-                __syncthreads();
             }
         }
-        if (tid == 0) sh.tail_d = sh.tail;
         phase_mark(2);
 
         // ---- canonical backward walk by wave 0
@@ -580,11 +584,11 @@ __device__ void run_sample(const DevGraph& g, const DevCdf& cdf, const DevSlots&
                     if (i < end) {
                         u = g.icol[i];
                         if (p <= aM) {
-                            if (B::test(B::rd(bits.vs, u), u) && (ld32(lv_s + u) & LVMASK) == (uint32_t)p + 1)
-                                wt = ld64(sg_s + u);
+                            if (B::test(B::rd(bits.vs, u), u) && (ld32(&R[u].lv_s) & LVMASK) == (uint32_t)p + 1)
+                                wt = ld64(&R[u].sg_s);
                         } else {
-                            if (B::test(B::rd(bits.vt, u), u) && (ld32(lv_t + u) & LVMASK) == (uint32_t)(L - p) + 1)
-                                wt = ld64(sg_s + u);
+                            if (B::test(B::rd(bits.vt, u), u) && (ld32(&R[u].lv_t) & LVMASK) == (uint32_t)(L - p) + 1)
+                                wt = ld64(&R[u].sg_s);
                         }
                         cn.E++;
                     }
@@ -646,23 +650,17 @@ __device__ void run_sample(const DevGraph& g, const DevCdf& cdf, const DevSlots&
         }
     }
 
-    // ---- clear what this sample touched
-    const int ts = sh.tail_s, tt = sh.tail_t, td = sh.tail_d;
+    // ---- clear what this sample touched (every node reached is in q_s or q_t)
+    const int ts = sh.tail_s, tt = sh.tail_t;
     for (int i = tid; i < ts; i += BSZ) {
-        int32_t w = ldq(q_s + i);
-        lv_s[w] = 0;
-        sg_s[w] = 0;
+        const int32_t w = ldq(q_s + i);
+        R[w] = NodeRec{};
         B::clear_word(bits.vs, w);
     }
     for (int i = tid; i < tt; i += BSZ) {
-        int32_t w = ldq(q_t + i);
-        lv_t[w] = 0;
-        sg_t[w] = 0;
+        const int32_t w = ldq(q_t + i);
+        R[w] = NodeRec{};
         B::clear_word(bits.vt, w);
-    }
-    for (int i = tid; i < td; i += BSZ) {
-        int32_t w = ldq(q_d + i);
-        sg_s[w] = 0;
     }
     level_barrier();
     phase_mark(4);
