@@ -300,6 +300,7 @@ static void free_slots(percis_ctx* c) {
 
 constexpr int64_t kSlotBytesPerNode = (int64_t)sizeof(NodeRec) + 4 + 4 + 4 + 4;
 constexpr int64_t kLdsPerCu = 160 * 1024;
+constexpr int64_t kBitmapPlanes = 2;  // s-side and t-side visited
 
 static int64_t bitmap_words(int64_t act) { return ((std::max<int64_t>(act, 1) + 31) / 32 + 63) / 64 * 64; }
 
@@ -308,8 +309,8 @@ static int64_t bitmap_words(int64_t act) { return ((std::max<int64_t>(act, 1) + 
 static int pick_shape(percis_ctx* c, int64_t act, SamplerShape* out, int* occ_out) {
     const int64_t words = bitmap_words(act);
     SamplerShape sh{};
-    sh.block = c->opt_block ? (int)c->opt_block : 512;
-    const int64_t lds_need = 3 * words * 4;
+    sh.block = c->opt_block ? (int)c->opt_block : 256;
+    const int64_t lds_need = kBitmapPlanes * words * 4;
     const bool fits = lds_need + sampler_static_lds() <= kLdsPerCu;
     if (c->opt_bitmaps == 2 && !fits)
         return fail(c, PERCIS_E_INVAL, "bitmaps of %lld nodes do not fit in LDS", (long long)act);
@@ -340,7 +341,7 @@ static int ensure_slots(percis_ctx* c, int64_t act) {
     if (rc) return rc;
     const int64_t stride = (act + 63) / 64 * 64;
     const int64_t words = bitmap_words(act);
-    const int64_t per_slot = stride * kSlotBytesPerNode + 8 + (sh.lds_bitmaps ? 0 : 3 * words * 4);
+    const int64_t per_slot = stride * kSlotBytesPerNode + 8 + (sh.lds_bitmaps ? 0 : kBitmapPlanes * words * 4);
     size_t free_b = 0, total_b = 0;
     HIPCHK(c, hipMemGetInfo(&free_b, &total_b));
     const int64_t budget = c->opt_scratch_mb > 0 ? c->opt_scratch_mb * (1ll << 20) : (int64_t)(free_b * 0.6);
@@ -1036,7 +1037,7 @@ int percis_autotune(percis_ctx* c, int32_t graph, uint64_t probe_samples, uint64
         int64_t block, bitmaps;
     };
     std::vector<Cand> cands;
-    const bool lds_ok = 3 * bitmap_words(act) * 4 + sampler_static_lds() <= kLdsPerCu;
+    const bool lds_ok = kBitmapPlanes * bitmap_words(act) * 4 + sampler_static_lds() <= kLdsPerCu;
     for (int64_t b : {256, 512, 1024}) {
         if (lds_ok) cands.push_back({b, 2});
         cands.push_back({b, 1});

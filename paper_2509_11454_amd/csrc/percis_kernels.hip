@@ -42,6 +42,7 @@ constexpr int CH = 256;  // frontier nodes staged per chunk
 constexpr uint32_t LVMASK = 0x0FFFFFFFu;
 constexpr uint32_t OVFBIT = 0x40000000u;
 constexpr int UNROLL = 8;
+constexpr int WALK_UNROLL = 4;  // in-row chunks of 64 loaded together by the walk
 
 // Slot scratch is private to one workgroup (one CU), so every access to it is
 // a workgroup-scope atomic: coherent among the workgroup's waves without the
@@ -63,25 +64,16 @@ __device__ __forceinline__ uint32_t* LV(NodeRec* R, int32_t w) { return SIDE ? &
 template <int SIDE>
 __device__ __forceinline__ uint64_t* SG(NodeRec* R, int32_t w) { return SIDE ? &R[w].sg_t : &R[w].sg_s; }
 
-// Visited bitmaps: three planes per slot -- s-side visited, t-side visited,
-// and "reached in the level being built" (shared by both sides, since only
-// one side grows at a time).
+// Visited bitmaps: two planes per slot, s-side visited and t-side visited.
 template <bool LDS>
 struct Bits {
     uint32_t* vs;
     uint32_t* vt;
-    uint32_t* nw;
     __device__ __forceinline__ static uint32_t rd(uint32_t* p, int32_t w) {
         return __hip_atomic_load(p + (w >> 5), __ATOMIC_RELAXED, WGS);
     }
-    __device__ __forceinline__ static uint32_t rd_acq(uint32_t* p, int32_t w) {
-        return __hip_atomic_load(p + (w >> 5), __ATOMIC_ACQUIRE, WGS);
-    }
     __device__ __forceinline__ static uint32_t set(uint32_t* p, int32_t w) {
         return __hip_atomic_fetch_or(p + (w >> 5), 1u << (w & 31), __ATOMIC_RELAXED, WGS);
-    }
-    __device__ __forceinline__ static uint32_t set_rel(uint32_t* p, int32_t w) {
-        return __hip_atomic_fetch_or(p + (w >> 5), 1u << (w & 31), __ATOMIC_ACQ_REL, WGS);
     }
     __device__ __forceinline__ static bool test(uint32_t word, int32_t w) { return (word >> (w & 31)) & 1u; }
     __device__ __forceinline__ static void clear_word(uint32_t* p, int32_t w) {
@@ -139,6 +131,24 @@ __device__ __forceinline__ int32_t wave_search(int32_t lo, int32_t hi, Pred pred
     return lo + __ffsll((long long)m) - 1;
 }
 
+// The pair of sample idx (ranks drawn by Algorithm 2, returned as internal
+// ids). Called by one whole wave.
+__device__ __forceinline__ void draw_pair(const DevCdf& cdf, uint64_t seed, uint64_t phase, uint64_t idx,
+                                          int32_t& s, int32_t& t) {
+    const uint64_t Us = draw_bounded(seed, phase, idx, 0, cdf.C);
+    const uint64_t* P = cdf.P;
+    const int32_t sr = wave_search(1, cdf.n, [&](int32_t d) { return Us < P[d]; });
+    const uint64_t cs = P[sr] - P[sr - 1];
+    const uint64_t Ut = draw_bounded(seed, phase, idx, 1, cs);
+    const uint64_t ks = cdf.kr[sr], Ws = cdf.W[sr];
+    const uint64_t* W = cdf.W;
+    const int32_t tr = wave_search(sr + 1, cdf.n, [&](int32_t d) {
+        return Ut < (uint64_t)(d - sr + 1) * ks - (Ws - W[d + 1]);
+    });
+    s = cdf.perm[sr];
+    t = cdf.perm[tr];
+}
+
 // ------------------------------------------------------------ workgroup state
 struct SampleShared {
     int32_t beg[CH];
@@ -146,23 +156,48 @@ struct SampleShared {
     uint64_t sig[CH];
     uint8_t of[CH];
     int32_t wsum[16];
-    unsigned long long idx;
     int32_t s, t;
     int32_t lo_s, hi_s, lo_t, hi_t;
     int32_t a, b;
     unsigned long long deg_s, deg_t, deg_next;       // frontier degree sums
-    unsigned long long max_s, max_t, max_next;       // largest count in each frontier
-    uint32_t ovf_s, ovf_t, ovf_next;                 // a frontier count overflowed
+    unsigned long long mass_next;                    // sum of the counts of the level being built
+    uint32_t wide_s, wide_t, wide_next;              // a frontier's counts may sum to 2^64 or more
     int32_t tail, tail_s, tail_t;
     int32_t nmeet;
+    int32_t level_meets;  // the level being built has an arc into the other ball
     int32_t status;   // 0 running, 1 met, 2 unreachable
     int32_t side;     // side of the level being built
     int32_t ovf;
     int32_t walk_err;
     uint64_t sigma;
-    int32_t task;
-    unsigned long long phase_ticks[5];  // pair, BFS, meeting + DAG, walk, clearing
+    // the next sample, claimed and drawn by one wave ahead of time
+    unsigned long long nx_idx;
+    int32_t nx_task, nx_s, nx_t;
+    unsigned long long phase_ticks[5];  // start, BFS, meeting + DAG, walk (+ next pair), clearing
+    // per-sample statistics of one task, summed here by thread 0 and added to
+    // the task's counters when the workgroup moves to another task
+    unsigned long long acc_samples, acc_reach, acc_sum_I, acc_sum_I2, acc_ovf, acc_first;
+    int32_t acc_task;
 };
+
+// Thread 0 only.
+__device__ void flush_task_stats(SampleShared& sh, const SampleLaunch& L) {
+    if (sh.acc_task >= 0) {
+        DevStats* st = L.tasks[sh.acc_task].stats;
+        atomicAdd(&st->samples, sh.acc_samples);
+        if (sh.acc_reach) atomicAdd(&st->reachable, sh.acc_reach);
+        if (sh.acc_sum_I) {
+            atomicAdd(&st->sum_I, sh.acc_sum_I);
+            atomicAdd(&st->sum_I2, sh.acc_sum_I2);
+        }
+        if (sh.acc_ovf) {
+            atomicAdd(&st->overflow, sh.acc_ovf);
+            atomicMin(&st->first_overflow, sh.acc_first);
+        }
+    }
+    sh.acc_samples = sh.acc_reach = sh.acc_sum_I = sh.acc_sum_I2 = sh.acc_ovf = 0;
+    sh.acc_first = ~0ull;
+}
 
 struct Counters {
     unsigned long long E, A, V, Vd;
@@ -244,17 +279,34 @@ __device__ __forceinline__ int chunk_owner(const SampleShared& sh, int cnt, int 
     return l2;
 }
 
+// Sum of a 64-bit value over the wave, with a flag that is set when the sum
+// (or any lane's flag) wrapped.
+__device__ __forceinline__ void wave_sum_wrap(uint64_t& v, uint32_t& wrap) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const uint64_t ov = __shfl_xor(v, o, 64);
+        const uint32_t ow = __shfl_xor(wrap, o, 64);
+        const uint64_t nv = v + ov;
+        wrap |= ow | (nv < v ? 1u : 0u);
+        v = nv;
+    }
+}
+
 // One BFS level over the frontier q[lo, hi) of one side (SIDE 0: s, out-arcs;
 // SIDE 1: t, in-arcs), edge-balanced: the rows of up to CH frontier nodes are
 // concatenated and the workgroup strides over the concatenation, UNROLL
 // entries per thread at a time so that their loads overlap. An arc (u, w)
-// adds sigma(u) to w iff w is reached in this level: either this arc reaches
-// it first, or the "new" bit says another arc of this level did. The new bit
-// is set before the visited bit (release) and read after it (acquire), so a
-// visited node with a clear new bit is an old one. New nodes that the other
-// side has reached form the meeting layer, written to the head of q_d.
-// `careful` is set when a count of this level could reach 2^64 (or a
-// frontier count already did): only then are the adds checked for wrapping.
+// adds sigma(u) to w iff w is reached in this level: either its visited bit
+// was clear when the arc looked (whoever sets the bit first appends w to the
+// queue and writes its level), or w's level field reads 0 (set visited in this
+// level, level not written yet) or the new level. Nodes of earlier levels
+// carry their own nonzero level, written before the last barrier. New nodes
+// that the other side has reached form the meeting layer, written to the
+// head of q_d.
+// Every count of the new level is at most the sum of the frontier's counts
+// (no parallel arcs), so the adds are checked for wrapping (`careful`) only
+// when that sum reached 2^64. The level's own sum and degree sum (the
+// degrees its expansion will scan) are gathered on the way.
 template <int SIDE, int BSZ, bool LDS>
 __device__ void expand_bfs(const DevGraph& g, const DevSlots& sl, int64_t so, const Bits<LDS>& bits, int lo, int hi,
                            uint32_t nl, bool careful, SampleShared& sh, Counters& cn) {
@@ -266,16 +318,19 @@ __device__ void expand_bfs(const DevGraph& g, const DevSlots& sl, int64_t so, co
     NodeRec* R = sl.rec + so;
     uint32_t* vis_mine = SIDE ? bits.vt : bits.vs;
     uint32_t* vis_other = SIDE ? bits.vs : bits.vt;
+    uint64_t mass = 0, dsum = 0;
+    uint32_t wrap = 0;
 
     for (int base = lo; base < hi; base += CH) {
         const int cnt = min(CH, hi - base);
         const int total = stage_chunk<BSZ, SIDE>(q, base, cnt, rp, R, careful, sh, cn);
-        for (int e0 = tid; e0 < total; e0 += BSZ * UNROLL) {
+        for (int b0 = 0; b0 < total; b0 += BSZ * UNROLL) {
             int32_t w[UNROLL];
             int jj[UNROLL];
+            uint32_t into_other = 0;  // bit k: arc k ends in the other side's ball
 #pragma unroll
             for (int k = 0; k < UNROLL; k++) {
-                const int e = e0 + k * BSZ;
+                const int e = b0 + tid + k * BSZ;
                 jj[k] = -1;
                 w[k] = 0;
                 if (e < total) {
@@ -284,27 +339,48 @@ __device__ void expand_bfs(const DevGraph& g, const DevSlots& sl, int64_t so, co
                 }
             }
 #pragma unroll
+            for (int k = 0; k < UNROLL; k++)
+                if (jj[k] >= 0 && B::test(B::rd(vis_other, w[k]), w[k])) into_other |= 1u << k;
+            // A level with an arc into the other ball is the last one, and of
+            // its new nodes only the meeting layer is used again: once any
+            // thread has seen such an arc, arcs to other nodes are skipped.
+            // The flag only ever goes up within a level, so a thread may see
+            // it raised by the next batch while its neighbours did not; either
+            // way every arc into the meeting layer is processed, and the rest
+            // only touch nodes that nothing reads (they are still queued, so
+            // they are cleared).
+            if (into_other) sh.level_meets = 1;
+            __syncthreads();
+            const bool meets = sh.level_meets != 0;
+#pragma unroll
             for (int k = 0; k < UNROLL; k++) {
                 if (jj[k] < 0) continue;
+                cn.E++;
+                if (meets && !((into_other >> k) & 1u)) continue;
                 const int32_t x = w[k];
                 const int j = jj[k];
-                cn.E++;
                 bool add, fresh = false;
-                if (!B::test(B::rd_acq(vis_mine, x), x)) {
-                    B::set(bits.nw, x);
-                    fresh = !B::test(B::set_rel(vis_mine, x), x);
+                if (!B::test(B::rd(vis_mine, x), x)) {
+                    fresh = !B::test(B::set(vis_mine, x), x);
                     add = true;
                 } else {
-                    add = B::test(B::rd(bits.nw, x), x);
+                    const uint32_t lv = ld32(LV<SIDE>(R, x)) & LVMASK;
+                    add = lv == 0 || lv == nl;
                 }
                 if (add) {
                     const uint64_t addv = sh.sig[j];
                     if (careful) {
                         const uint64_t old = add64(SG<SIDE>(R, x), addv);
-                        if (old + addv < old || sh.of[j]) or32(LV<SIDE>(R, x), OVFBIT);
+                        if (old + addv < old || sh.of[j]) {
+                            or32(LV<SIDE>(R, x), OVFBIT);
+                            wrap = 1u;
+                        }
                     } else {
                         (void)add64(SG<SIDE>(R, x), addv);
                     }
+                    const uint64_t nm = mass + addv;
+                    wrap |= nm < mass ? 1u : 0u;
+                    mass = nm;
                     cn.A++;
                 }
                 if (fresh) {
@@ -312,7 +388,8 @@ __device__ void expand_bfs(const DevGraph& g, const DevSlots& sl, int64_t so, co
                     const int pos = atomicAdd(&sh.tail, 1);
                     q[pos] = x;
                     cn.Vd++;
-                    if (B::test(B::rd(vis_other, x), x)) {
+                    dsum += (uint64_t)(rp[x + 1] - rp[x]);
+                    if ((into_other >> k) & 1u) {
                         const int mp = atomicAdd(&sh.nmeet, 1);
                         sl.q_d[so + mp] = x;
                     }
@@ -320,6 +397,14 @@ __device__ void expand_bfs(const DevGraph& g, const DevSlots& sl, int64_t so, co
             }
         }
         if (base + CH < hi) __syncthreads();  // the caller's barrier follows the last chunk
+    }
+    wave_sum_wrap(mass, wrap);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) dsum += __shfl_xor(dsum, o, 64);
+    if ((tid & 63) == 0) {
+        const unsigned long long old = atomicAdd(&sh.mass_next, (unsigned long long)mass);
+        if (wrap || old + mass < old) sh.wide_next = 1u;
+        atomicAdd(&sh.deg_next, (unsigned long long)dsum);
     }
 }
 
@@ -357,45 +442,17 @@ __device__ void pull_level(const DevGraph& g, const DevSlots& sl, int64_t so, co
             const int32_t u = g.icol[sh.beg[j] + (e - sh.off[j])];
             cn.E++;
             if (!B::test(B::rd(bits.vt, u), u)) continue;
-            if ((ld32(&R[u].lv_t) & LVMASK) != want) continue;
-            const uint64_t su = ld64(&R[u].sg_s);
+            // levels of this level's nodes are final (set before the last
+            // barrier); their sigma_s was completed by the previous pull level
+            const uint4 rec = *reinterpret_cast<const uint4*>(&R[u]);
+            if ((rec.y & LVMASK) != want) continue;
+            const uint64_t su = ((uint64_t)rec.w << 32) | rec.z;
             if (su) {
                 (void)add64(&R[(int32_t)sh.sig[j]].sg_s, su);
                 cn.A++;
             }
         }
         if (base + CH < hi) __syncthreads();
-    }
-}
-
-// After a level of one side: clears the "new" bits of its nodes q[lo, hi)
-// and gathers, for the next expansion of that side, the degree sum of the
-// new frontier, its largest shortest-path count and whether any count
-// overflowed.
-template <int BSZ, bool LDS, int SIDE>
-__device__ void finish_level(const Bits<LDS>& bits, int32_t* q, NodeRec* R, const int32_t* drp, int lo, int hi,
-                             SampleShared& sh) {
-    unsigned long long dsum = 0, smax = 0;
-    uint32_t of = 0;
-    for (int i = lo + (int)threadIdx.x; i < hi; i += BSZ) {
-        const int32_t w = ldq(q + i);
-        Bits<LDS>::clear_word(bits.nw, w);
-        dsum += (unsigned long long)(drp[w + 1] - drp[w]);
-        const uint64_t sv = ld64(SG<SIDE>(R, w));
-        smax = sv > smax ? sv : smax;
-        of |= ld32(LV<SIDE>(R, w)) & OVFBIT;
-    }
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        dsum += __shfl_xor(dsum, o, 64);
-        const unsigned long long om = __shfl_xor(smax, o, 64);
-        smax = om > smax ? om : smax;
-        of |= __shfl_xor(of, o, 64);
-    }
-    if ((threadIdx.x & 63) == 0) {
-        if (dsum) atomicAdd(&sh.deg_next, dsum);
-        if (smax) atomicMax(&sh.max_next, smax);
-        if (of) atomicOr(&sh.ovf_next, 1u);
     }
 }
 
@@ -406,26 +463,51 @@ __device__ __forceinline__ void plan_level(SampleShared& sh) {
     sh.side = (sh.deg_s <= sh.deg_t) ? 0 : 1;
     sh.tail = sh.side == 0 ? sh.hi_s : sh.hi_t;
     sh.deg_next = 0;
-    sh.max_next = 0;
-    sh.ovf_next = 0;
-}
-
-__device__ __forceinline__ bool may_wrap(unsigned long long deg, unsigned long long smax, uint32_t ovf) {
-    return ovf || (smax > 0 && deg > ~0ull / smax);
+    sh.mass_next = 0;
+    sh.wide_next = 0;
+    sh.level_meets = 0;
 }
 
 // __syncthreads orders the workgroup's scratch accesses (workgroup-scope
 // release/acquire around the barrier).
 __device__ __forceinline__ void level_barrier() { __syncthreads(); }
 
-// One sample on this workgroup's slot. In debug mode (dbg != nullptr) the pair
-// and the path index are given instead of drawn, hits are not touched and the
-// path is written to dbg (internal ids).
+// Claims the next launch index and draws its pair into sh.nx_*. Called by one
+// whole wave.
+__device__ void claim_next(const SampleLaunch& L, SampleShared& sh) {
+    const int lane = threadIdx.x & 63;
+    unsigned long long q = 0;
+    if (lane == 0) q = atomicAdd(L.work, 1ull);
+    q = __shfl(q, 0, 64);
+    if (q >= L.total) {
+        if (lane == 0) sh.nx_idx = q;
+        return;
+    }
+    // the task holding launch index q: last task with offset <= q
+    int lo = 0, hi = L.ntasks - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (L.tasks[mid].offset <= q) lo = mid; else hi = mid - 1;
+    }
+    const DevTask& T = L.tasks[lo];
+    int32_t s, t;
+    draw_pair(T.cdf, T.seed, T.phase, T.first + (q - T.offset), s, t);
+    if (lane == 0) {
+        sh.nx_idx = q;
+        sh.nx_task = lo;
+        sh.nx_s = s;
+        sh.nx_t = t;
+    }
+}
+
+// One sample on this workgroup's slot, for the pair (s, t) already drawn. With
+// a launch given, wave 1 claims and draws the next sample during the walk. In
+// debug mode (dbg != nullptr) the path index is given instead of drawn, hits
+// are not touched and the path is written to dbg (internal ids).
 template <int BSZ, bool LDS>
-__device__ void run_sample(const DevGraph& g, const DevCdf& cdf, const DevSlots& sl, int64_t so,
-                           const Bits<LDS>& bits, uint64_t idx, const DevTask& T,
-                           SampleShared& sh, Counters& cn, DebugOut* dbg, int32_t dbg_s, int32_t dbg_t,
-                           uint64_t dbg_r, int32_t dbg_cap) {
+__device__ void run_sample(const DevGraph& g, const DevSlots& sl, int64_t so, const Bits<LDS>& bits, uint64_t idx,
+                           const DevTask& T, int32_t s, int32_t t, const SampleLaunch* next, SampleShared& sh,
+                           Counters& cn, DebugOut* dbg, uint64_t dbg_r, int32_t dbg_cap) {
     using B = Bits<LDS>;
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     NodeRec* R = sl.rec + so;
@@ -445,26 +527,8 @@ __device__ void run_sample(const DevGraph& g, const DevCdf& cdf, const DevSlots&
         }
     };
 
-    // ---- the pair (wave 0)
+    // ---- start both balls
     if (wid == 0) {
-        int32_t s, t;
-        if (!dbg) {
-            const uint64_t Us = draw_bounded(T.seed, T.phase, idx, 0, cdf.C);
-            const uint64_t* P = cdf.P;
-            const int32_t sr = wave_search(1, cdf.n, [&](int32_t d) { return Us < P[d]; });
-            const uint64_t cs = P[sr] - P[sr - 1];
-            const uint64_t Ut = draw_bounded(T.seed, T.phase, idx, 1, cs);
-            const uint64_t ks = cdf.kr[sr], Ws = cdf.W[sr];
-            const uint64_t* W = cdf.W;
-            const int32_t tr = wave_search(sr + 1, cdf.n, [&](int32_t d) {
-                return Ut < (uint64_t)(d - sr + 1) * ks - (Ws - W[d + 1]);
-            });
-            s = cdf.perm[sr];
-            t = cdf.perm[tr];
-        } else {
-            s = dbg_s;
-            t = dbg_t;
-        }
         if (lane == 0) {
             sh.s = s;
             sh.t = t;
@@ -484,7 +548,7 @@ __device__ void run_sample(const DevGraph& g, const DevCdf& cdf, const DevSlots&
                 sh.lo_s = 0; sh.hi_s = 1; sh.lo_t = 0; sh.hi_t = 1;
                 sh.deg_s = (unsigned long long)(g.rp[s + 1] - g.rp[s]);
                 sh.deg_t = (unsigned long long)(g.irp[t + 1] - g.irp[t]);
-                sh.max_s = 1; sh.max_t = 1; sh.ovf_s = 0; sh.ovf_t = 0;
+                sh.wide_s = 0; sh.wide_t = 0;
                 sh.tail_s = 1; sh.tail_t = 1;
                 plan_level(sh);
             }
@@ -499,21 +563,18 @@ __device__ void run_sample(const DevGraph& g, const DevCdf& cdf, const DevSlots&
     while (sh.status == 0) {
         const int side = sh.side;
         const int nlo = side == 0 ? sh.hi_s : sh.hi_t;
-        const bool careful = side == 0 ? may_wrap(sh.deg_s, sh.max_s, sh.ovf_s) : may_wrap(sh.deg_t, sh.max_t, sh.ovf_t);
+        const bool careful = (side == 0 ? sh.wide_s : sh.wide_t) != 0;
         if (side == 0) expand_bfs<0, BSZ, LDS>(g, sl, so, bits, sh.lo_s, sh.hi_s, (uint32_t)sh.a + 2, careful, sh, cn);
         else expand_bfs<1, BSZ, LDS>(g, sl, so, bits, sh.lo_t, sh.hi_t, (uint32_t)sh.b + 2, careful, sh, cn);
         level_barrier();
         const int nhi = sh.tail;
-        if (side == 0) finish_level<BSZ, LDS, 0>(bits, q_s, R, g.rp, nlo, nhi, sh);
-        else finish_level<BSZ, LDS, 1>(bits, q_t, R, g.irp, nlo, nhi, sh);
-        level_barrier();
         if (tid == 0) {
             if (side == 0) {
                 sh.lo_s = nlo; sh.hi_s = nhi; sh.tail_s = nhi; sh.a++;
-                sh.deg_s = sh.deg_next; sh.max_s = sh.max_next; sh.ovf_s = sh.ovf_next;
+                sh.deg_s = sh.deg_next; sh.wide_s = sh.wide_next;
             } else {
                 sh.lo_t = nlo; sh.hi_t = nhi; sh.tail_t = nhi; sh.b++;
-                sh.deg_t = sh.deg_next; sh.max_t = sh.max_next; sh.ovf_t = sh.ovf_next;
+                sh.deg_t = sh.deg_next; sh.wide_t = sh.wide_next;
                 tls[sh.b + 1] = nhi;
             }
             if (sh.nmeet > 0) sh.status = 1;
@@ -575,34 +636,45 @@ __device__ void run_sample(const DevGraph& g, const DevCdf& cdf, const DevSlots&
             int32_t w = sh.t;
             int err = 0;
             for (int32_t p = L - 1; p >= 1; p--) {
+                // predecessors of w on the DAG: s-level p, or (past the
+                // meeting layer) t-level L - p; their sigma_s weighs them
+                const bool on_s = p <= aM;
+                const uint32_t want = on_s ? (uint32_t)p + 1 : (uint32_t)(L - p) + 1;
+                uint32_t* vis = on_s ? bits.vs : bits.vt;
                 const int32_t beg = g.irp[w], end = g.irp[w + 1];
                 int32_t sel = -1;
-                for (int32_t base = beg; base < end; base += 64) {
-                    const int32_t i = base + lane;
-                    int32_t u = -1;
-                    uint64_t wt = 0;
-                    if (i < end) {
-                        u = g.icol[i];
-                        if (p <= aM) {
-                            if (B::test(B::rd(bits.vs, u), u) && (ld32(&R[u].lv_s) & LVMASK) == (uint32_t)p + 1)
-                                wt = ld64(&R[u].sg_s);
-                        } else {
-                            if (B::test(B::rd(bits.vt, u), u) && (ld32(&R[u].lv_t) & LVMASK) == (uint32_t)(L - p) + 1)
-                                wt = ld64(&R[u].sg_s);
+                for (int32_t base = beg; base < end && sel < 0; base += 64 * WALK_UNROLL) {
+                    int32_t u[WALK_UNROLL];
+                    uint64_t wt[WALK_UNROLL];
+#pragma unroll
+                    for (int k = 0; k < WALK_UNROLL; k++) {
+                        const int32_t i = base + k * 64 + lane;
+                        u[k] = i < end ? g.icol[i] : -1;
+                    }
+#pragma unroll
+                    for (int k = 0; k < WALK_UNROLL; k++) {
+                        wt[k] = 0;
+                        if (u[k] >= 0 && B::test(B::rd(vis, u[k]), u[k])) {
+                            const uint4 rec = *reinterpret_cast<const uint4*>(&R[u[k]]);
+                            const uint32_t lv = on_s ? rec.x : rec.y;
+                            if ((lv & LVMASK) == want) wt[k] = ((uint64_t)rec.w << 32) | rec.z;
                         }
-                        cn.E++;
+                        if (u[k] >= 0) cn.E++;
                     }
-                    const uint64_t incl = wave_incl_scan_u64(wt);
-                    const uint64_t tot = __shfl(incl, 63, 64);
-                    if (r < tot) {
-                        const unsigned long long m = __ballot(incl > r);
-                        const int l = __ffsll((long long)m) - 1;
-                        const uint64_t ex = __shfl(incl - wt, l, 64);
-                        sel = __shfl(u, l, 64);
-                        r -= ex;
-                        break;
+#pragma unroll
+                    for (int k = 0; k < WALK_UNROLL; k++) {
+                        if (sel >= 0) continue;
+                        const uint64_t incl = wave_incl_scan_u64(wt[k]);
+                        const uint64_t tot = __shfl(incl, 63, 64);
+                        if (r < tot) {
+                            const unsigned long long m = __ballot(incl > r);
+                            const int l = __ffsll((long long)m) - 1;
+                            r -= __shfl(incl - wt[k], l, 64);
+                            sel = __shfl(u[k], l, 64);
+                        } else {
+                            r -= tot;
+                        }
                     }
-                    r -= tot;
                 }
                 if (sel < 0) { err = 1; break; }
                 w = sel;
@@ -618,25 +690,24 @@ __device__ void run_sample(const DevGraph& g, const DevCdf& cdf, const DevSlots&
             if (lane == 0) sh.walk_err = err;
         }
     }
+    // ---- the next sample's pair, by wave 1 while wave 0 walks
+    if (next && wid == 1) claim_next(*next, sh);
     __syncthreads();
     phase_mark(3);
 
     // ---- per-sample statistics
     if (tid == 0) {
         if (!dbg) {
-            DevStats* st = T.stats;
-            atomicAdd(&st->samples, 1ull);
+            sh.acc_samples++;
             if (sh.status == 1) {
                 if (sh.ovf || sh.walk_err) {
-                    atomicAdd(&st->overflow, 1ull);
-                    atomicMin(&st->first_overflow, (unsigned long long)idx);
+                    sh.acc_ovf++;
+                    sh.acc_first = idx < sh.acc_first ? idx : sh.acc_first;
                 } else {
                     const unsigned long long I = (unsigned long long)(L - 1);
-                    atomicAdd(&st->reachable, 1ull);
-                    if (I) {
-                        atomicAdd(&st->sum_I, I);
-                        atomicAdd(&st->sum_I2, I * I);
-                    }
+                    sh.acc_reach++;
+                    sh.acc_sum_I += I;
+                    sh.acc_sum_I2 += I * I;
                 }
             }
         } else {
@@ -691,52 +762,49 @@ __device__ __forceinline__ Bits<LDS> slot_bits(const DevSlots& sl, int slot) {
     if (LDS) {
         b.vs = dyn_lds;
         b.vt = dyn_lds + sl.words;
-        b.nw = dyn_lds + 2 * sl.words;
     } else {
-        uint32_t* base = sl.bm + (int64_t)slot * 3 * sl.words;
+        uint32_t* base = sl.bm + (int64_t)slot * 2 * sl.words;
         b.vs = base;
         b.vt = base + sl.words;
-        b.nw = base + 2 * sl.words;
     }
     return b;
 }
 
 template <int BSZ, bool LDS>
 __global__ __launch_bounds__(BSZ) void sampler_kernel(DevSlots sl, SampleLaunch L) {
+    static_assert(BSZ >= 128, "wave 1 draws the next pair");
     __shared__ SampleShared sh;
     const int tid = threadIdx.x;
     const int64_t so = (int64_t)blockIdx.x * sl.stride;
     const Bits<LDS> bits = slot_bits<BSZ, LDS>(sl, blockIdx.x);
     Counters cn = {0, 0, 0, 0};
     if (LDS) {
-        for (int64_t i = tid; i < 3 * sl.words; i += BSZ) dyn_lds[i] = 0;
+        for (int64_t i = tid; i < 2 * sl.words; i += BSZ) dyn_lds[i] = 0;
     }
     if (tid == 0) {
         for (int i = 0; i < 5; i++) sh.phase_ticks[i] = 0;
+        sh.acc_task = -1;
+        flush_task_stats(sh, L);
     }
+    if (tid < 64) claim_next(L, sh);
+    __syncthreads();
+    // Every thread reads the claimed sample here; wave 1 claims the next one
+    // only after run_sample's first barrier, and run_sample ends on a barrier.
     for (;;) {
-        if (tid == 0) {
-            const unsigned long long q = atomicAdd(L.work, 1ull);
-            sh.idx = q;
-            if (q < L.total) {
-                // the task holding launch index q: last task with offset <= q
-                int lo = 0, hi = L.ntasks - 1;
-                while (lo < hi) {
-                    const int mid = (lo + hi + 1) >> 1;
-                    if (L.tasks[mid].offset <= q) lo = mid; else hi = mid - 1;
-                }
-                sh.task = lo;
-            }
-        }
-        __syncthreads();
-        const unsigned long long q = sh.idx;
+        const unsigned long long q = sh.nx_idx;
         if (q >= L.total) break;
-        const int k = __builtin_amdgcn_readfirstlane(sh.task);
+        const int k = __builtin_amdgcn_readfirstlane(sh.nx_task);
+        const int32_t s = __builtin_amdgcn_readfirstlane(sh.nx_s), t = __builtin_amdgcn_readfirstlane(sh.nx_t);
         const DevTask& T = L.tasks[k];
-        run_sample<BSZ, LDS>(T.g, T.cdf, sl, so, bits, T.first + (q - T.offset), T, sh, cn, nullptr, 0, 0, 0, 0);
+        if (tid == 0 && k != sh.acc_task) {
+            flush_task_stats(sh, L);
+            sh.acc_task = k;
+        }
+        run_sample<BSZ, LDS>(T.g, sl, so, bits, T.first + (q - T.offset), T, s, t, &L, sh, cn, nullptr, 0, 0);
     }
     flush_counters(cn, L.stats);
     if (tid == 0) {
+        flush_task_stats(sh, L);
         for (int i = 0; i < 5; i++) atomicAdd(&L.stats->phase_ticks[i], sh.phase_ticks[i]);
     }
 }
@@ -748,15 +816,14 @@ __global__ __launch_bounds__(BSZ) void debug_path_kernel(DevGraph g, DevSlots sl
     const Bits<LDS> bits = slot_bits<BSZ, LDS>(sl, 0);
     Counters cn = {0, 0, 0, 0};
     if (LDS) {
-        for (int64_t i = threadIdx.x; i < 3 * sl.words; i += BSZ) dyn_lds[i] = 0;
+        for (int64_t i = threadIdx.x; i < 2 * sl.words; i += BSZ) dyn_lds[i] = 0;
     }
     if (threadIdx.x == 0) {
         for (int i = 0; i < 5; i++) sh.phase_ticks[i] = 0;
     }
     __syncthreads();
-    DevCdf none = {};
     DevTask T = {};
-    run_sample<BSZ, LDS>(g, none, sl, 0, bits, 0, T, sh, cn, out, s, t, r, cap);
+    run_sample<BSZ, LDS>(g, sl, 0, bits, 0, T, s, t, nullptr, sh, cn, out, r, cap);
 }
 
 __global__ void fill_u32_kernel(uint32_t* p, uint32_t v, int64_t count) {
