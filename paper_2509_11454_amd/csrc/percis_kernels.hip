@@ -81,6 +81,19 @@ struct Bits {
     }
 };
 
+// Lane l's value as a wave-uniform (scalar) value; l must be wave-uniform.
+// Values that steer a wave's control flow are taken this way rather than by
+// a shuffle: the compiler cannot see that a shuffled value is the same in
+// every lane, and may then split a loop so that lanes run different
+// iterations (one lane leaving to do its own work while the others wait in
+// an inner copy of the loop).
+__device__ __forceinline__ int32_t lane_i32(int32_t v, int l) { return __builtin_amdgcn_readlane(v, l); }
+__device__ __forceinline__ uint64_t lane_u64(uint64_t v, int l) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), l);
+    return ((uint64_t)hi << 32) | lo;
+}
+
 // ---------------------------------------------------------------- Philox
 __device__ __forceinline__ uint64_t philox_word0(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3,
                                                  uint64_t k0, uint64_t k1) {
@@ -120,8 +133,8 @@ __device__ __forceinline__ int32_t wave_search(int32_t lo, int32_t hi, Pred pred
         const int32_t x = lo + (int32_t)(((int64_t)(lane + 1) * len) >> 6) - 1;
         const unsigned long long m = __ballot(pred(x));
         const int i = __ffsll((long long)m) - 1;
-        const int32_t nhi = __shfl(x, i, 64);
-        const int32_t prev = __shfl(x, i > 0 ? i - 1 : 0, 64);
+        const int32_t nhi = lane_i32(x, i);
+        const int32_t prev = lane_i32(x, i > 0 ? i - 1 : 0);
         lo = i > 0 ? prev + 1 : lo;
         hi = nhi;
     }
@@ -151,6 +164,7 @@ __device__ __forceinline__ void draw_pair(const DevCdf& cdf, uint64_t seed, uint
 
 // ------------------------------------------------------------ workgroup state
 struct SampleShared {
+    int32_t node[CH];
     int32_t beg[CH];
     int32_t off[CH];
     uint64_t sig[CH];
@@ -160,6 +174,8 @@ struct SampleShared {
     int32_t lo_s, hi_s, lo_t, hi_t;
     int32_t a, b;
     unsigned long long deg_s, deg_t, deg_next;       // frontier degree sums
+    unsigned long long deg_t_prev;                   // in-degree sum of t-level b - 1
+    unsigned long long push_cost;                    // out-degree sum of the meeting layer
     unsigned long long mass_next;                    // sum of the counts of the level being built
     uint32_t wide_s, wide_t, wide_next;              // a frontier's counts may sum to 2^64 or more
     int32_t tail, tail_s, tail_t;
@@ -247,10 +263,11 @@ __device__ __forceinline__ int stage_chunk(int32_t* q, int base, int cnt, const 
                                            bool read_ovf, SampleShared& sh, Counters& cn) {
     const int tid = threadIdx.x;
     int deg = 0, beg = 0;
+    int32_t u = 0;
     uint64_t su = 0;
     uint32_t of = 0;
     if (tid < cnt) {
-        const int32_t u = ldq(q + base + tid);
+        u = ldq(q + base + tid);
         beg = rp[u];
         deg = rp[u + 1] - beg;
         su = ld64(SG<SIDE>(R, u));
@@ -260,6 +277,7 @@ __device__ __forceinline__ int stage_chunk(int32_t* q, int base, int cnt, const 
     int total;
     const int ex = chunk_excl_scan<BSZ>(deg, sh.wsum, total);
     if (tid < CH) {
+        sh.node[tid] = u;
         sh.beg[tid] = beg;
         sh.off[tid] = ex;
         sh.sig[tid] = su;
@@ -383,6 +401,15 @@ __device__ void expand_bfs(const DevGraph& g, const DevSlots& sl, int64_t so, co
                     mass = nm;
                     cn.A++;
                 }
+                if (SIDE == 1 && ((into_other >> k) & 1u)) {
+                    // x is a meeting node (s-level a) and the frontier node, at
+                    // t-level b - 1, one of its out-neighbours: this is the
+                    // first step of the sigma_s pull, done while the arc is
+                    // at hand
+                    const uint64_t ss = ld64(&R[x].sg_s);
+                    (void)add64(&R[sh.node[j]].sg_s, ss);
+                    cn.A++;
+                }
                 if (fresh) {
                     or32(LV<SIDE>(R, x), nl);
                     const int pos = atomicAdd(&sh.tail, 1);
@@ -456,6 +483,33 @@ __device__ void pull_level(const DevGraph& g, const DevSlots& sl, int64_t so, co
     }
 }
 
+// First step of the sigma_s pull done as a push instead (when the s side
+// expanded last and the meeting layer's out-rows are shorter than the in-rows
+// of t-level b - 1): every meeting node w adds sigma_s(w) to its
+// out-neighbours at t-level b - 1 (t-level value want = b).
+template <int BSZ, bool LDS>
+__device__ void push_meeting(const DevGraph& g, const DevSlots& sl, int64_t so, const Bits<LDS>& bits, int nmeet,
+                             uint32_t want, SampleShared& sh, Counters& cn) {
+    using B = Bits<LDS>;
+    const int tid = threadIdx.x;
+    NodeRec* R = sl.rec + so;
+    int32_t* qd = sl.q_d + so;
+    for (int base = 0; base < nmeet; base += CH) {
+        const int cnt = min(CH, nmeet - base);
+        const int total = stage_chunk<BSZ, 0>(qd, base, cnt, g.rp, R, false, sh, cn);
+        for (int e = tid; e < total; e += BSZ) {
+            const int j = chunk_owner(sh, cnt, e);
+            const int32_t x = g.col[sh.beg[j] + (e - sh.off[j])];
+            cn.E++;
+            if (!B::test(B::rd(bits.vt, x), x)) continue;
+            if ((ld32(&R[x].lv_t) & LVMASK) != want) continue;
+            (void)add64(&R[x].sg_s, sh.sig[j]);
+            cn.A++;
+        }
+        if (base + CH < nmeet) __syncthreads();
+    }
+}
+
 // Next BFS level: the side with the smaller frontier degree sum (Section
 // III-B's balanced expansion), its queue's append position, fresh
 // accumulators. Called by one thread.
@@ -472,29 +526,52 @@ __device__ __forceinline__ void plan_level(SampleShared& sh) {
 // release/acquire around the barrier).
 __device__ __forceinline__ void level_barrier() { __syncthreads(); }
 
-// Claims the next launch index and draws its pair into sh.nx_*. Called by one
-// whole wave.
+// Lane 0 of the calling wave adds v to *p; every lane gets the previous value
+// (wave-uniform). Out of line, so that its lane-0 branch stays inside it and
+// a caller's loop keeps all lanes in the same iteration.
+__device__ __attribute__((noinline)) unsigned long long wave_fetch_add(unsigned long long* p, unsigned long long v) {
+    unsigned long long old = 0;
+    if ((threadIdx.x & 63) == 0) old = atomicAdd(p, v);
+    return lane_u64(old, 0);
+}
+
+// Claims launch indices and draws their pairs until one needs a search, and
+// leaves it in sh.nx_* (or an index past the end). A pair with an end that
+// has no arcs is unreachable and is only counted. Called by one whole wave.
+// No instruction inside the loop depends on the lane (every steering value
+// is wave-uniform), so the loop cannot be split between lanes.
 __device__ void claim_next(const SampleLaunch& L, SampleShared& sh) {
     const int lane = threadIdx.x & 63;
-    unsigned long long q = 0;
-    if (lane == 0) q = atomicAdd(L.work, 1ull);
-    q = __shfl(q, 0, 64);
-    if (q >= L.total) {
-        if (lane == 0) sh.nx_idx = q;
-        return;
+    unsigned long long q, triv = 0;
+    int task = 0, triv_task = -1;
+    int32_t s = 0, t = 0;
+    for (;;) {
+        q = wave_fetch_add(L.work, 1ull);
+        if (q >= L.total) break;
+        // the task holding launch index q: last task with offset <= q
+        int lo = 0, hi = L.ntasks - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (lane_u64(L.tasks[mid].offset, 0) <= q) lo = mid; else hi = mid - 1;
+        }
+        task = lo;
+        const DevTask& T = L.tasks[task];
+        draw_pair(T.cdf, T.seed, T.phase, T.first + (q - T.offset), s, t);
+        s = __builtin_amdgcn_readfirstlane(s);
+        t = __builtin_amdgcn_readfirstlane(t);
+        const int32_t n_act = __builtin_amdgcn_readfirstlane(T.g.n_act);
+        if (s < n_act && t < n_act) break;
+        if (task != triv_task) {
+            if (triv_task >= 0 && triv) (void)wave_fetch_add(&L.tasks[triv_task].stats->samples, triv);
+            triv_task = task;
+            triv = 0;
+        }
+        triv++;
     }
-    // the task holding launch index q: last task with offset <= q
-    int lo = 0, hi = L.ntasks - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (L.tasks[mid].offset <= q) lo = mid; else hi = mid - 1;
-    }
-    const DevTask& T = L.tasks[lo];
-    int32_t s, t;
-    draw_pair(T.cdf, T.seed, T.phase, T.first + (q - T.offset), s, t);
+    if (triv_task >= 0 && triv) (void)wave_fetch_add(&L.tasks[triv_task].stats->samples, triv);
     if (lane == 0) {
         sh.nx_idx = q;
-        sh.nx_task = lo;
+        sh.nx_task = task;
         sh.nx_s = s;
         sh.nx_t = t;
     }
@@ -549,6 +626,7 @@ __device__ void run_sample(const DevGraph& g, const DevSlots& sl, int64_t so, co
                 sh.deg_s = (unsigned long long)(g.rp[s + 1] - g.rp[s]);
                 sh.deg_t = (unsigned long long)(g.irp[t + 1] - g.irp[t]);
                 sh.wide_s = 0; sh.wide_t = 0;
+                sh.deg_t_prev = 0;
                 sh.tail_s = 1; sh.tail_t = 1;
                 plan_level(sh);
             }
@@ -574,6 +652,7 @@ __device__ void run_sample(const DevGraph& g, const DevSlots& sl, int64_t so, co
                 sh.deg_s = sh.deg_next; sh.wide_s = sh.wide_next;
             } else {
                 sh.lo_t = nlo; sh.hi_t = nhi; sh.tail_t = nhi; sh.b++;
+                sh.deg_t_prev = sh.deg_t;
                 sh.deg_t = sh.deg_next; sh.wide_t = sh.wide_next;
                 tls[sh.b + 1] = nhi;
             }
@@ -592,10 +671,11 @@ __device__ void run_sample(const DevGraph& g, const DevSlots& sl, int64_t so, co
     const int32_t L = sh.a + sh.b;
     if (sh.status == 1) {
         if (wid == 0) {
-            uint64_t acc = 0;
+            uint64_t acc = 0, pc = 0;
             int of = 0;
             for (int i = lane; i < sh.nmeet; i += 64) {
                 const int32_t w = ldq(q_d + i);
+                pc += (uint64_t)(g.rp[w + 1] - g.rp[w]);
                 const uint32_t ls = ld32(&R[w].lv_s), lt = ld32(&R[w].lv_t);
                 of |= ((ls | lt) & OVFBIT) ? 1 : 0;
                 const uint64_t x = ld64(&R[w].sg_s), y = ld64(&R[w].sg_t);
@@ -612,17 +692,30 @@ __device__ void run_sample(const DevGraph& g, const DevSlots& sl, int64_t so, co
                 const uint64_t na = acc + oa;
                 of |= oo | (na < acc ? 1 : 0);
                 acc = na;
+                pc += __shfl_xor(pc, o, 64);
             }
             if (lane == 0) {
                 sh.sigma = acc;
                 sh.ovf = of;
+                sh.push_cost = pc;
             }
         }
         level_barrier();
 
         // ---- sigma_s pulled through the t-ball, from t-level b - 1 down to t
+        // If the t side expanded last, its meeting level already did the first
+        // step; if the s side did, the first step is a push from the meeting
+        // layer when that scans fewer arcs.
         if (!sh.ovf) {
-            for (int j = sh.b; j >= 1; j--) {
+            int j = sh.b;
+            if (sh.side == 1) {
+                j--;
+            } else if (j >= 1 && sh.push_cost < sh.deg_t_prev) {
+                push_meeting<BSZ, LDS>(g, sl, so, bits, sh.nmeet, (uint32_t)j, sh, cn);
+                level_barrier();
+                j--;
+            }
+            for (; j >= 1; j--) {
                 pull_level<BSZ, LDS>(g, sl, so, bits, ldq(tls + j - 1), ldq(tls + j), (uint32_t)j + 1, sh, cn);
                 level_barrier();
             }
@@ -634,6 +727,7 @@ __device__ void run_sample(const DevGraph& g, const DevSlots& sl, int64_t so, co
             const int32_t aM = sh.a;
             uint64_t r = dbg ? dbg_r : draw_bounded(T.seed, T.phase, idx, 2, sh.sigma);
             int32_t w = sh.t;
+            int32_t beg = g.irp[w], end = g.irp[w + 1];
             int err = 0;
             for (int32_t p = L - 1; p >= 1; p--) {
                 // predecessors of w on the DAG: s-level p, or (past the
@@ -641,21 +735,26 @@ __device__ void run_sample(const DevGraph& g, const DevSlots& sl, int64_t so, co
                 const bool on_s = p <= aM;
                 const uint32_t want = on_s ? (uint32_t)p + 1 : (uint32_t)(L - p) + 1;
                 uint32_t* vis = on_s ? bits.vs : bits.vt;
-                const int32_t beg = g.irp[w], end = g.irp[w + 1];
-                int32_t sel = -1;
+                int32_t sel = -1, nbeg = 0, nend = 0;
                 for (int32_t base = beg; base < end && sel < 0; base += 64 * WALK_UNROLL) {
-                    int32_t u[WALK_UNROLL];
+                    int32_t u[WALK_UNROLL], rb[WALK_UNROLL], re[WALK_UNROLL];
                     uint64_t wt[WALK_UNROLL];
 #pragma unroll
                     for (int k = 0; k < WALK_UNROLL; k++) {
                         const int32_t i = base + k * 64 + lane;
                         u[k] = i < end ? g.icol[i] : -1;
                     }
+                    // the in-row bounds of every candidate are loaded with its
+                    // record, so the next step can start as soon as one is chosen
 #pragma unroll
                     for (int k = 0; k < WALK_UNROLL; k++) {
                         wt[k] = 0;
+                        rb[k] = 0;
+                        re[k] = 0;
                         if (u[k] >= 0 && B::test(B::rd(vis, u[k]), u[k])) {
                             const uint4 rec = *reinterpret_cast<const uint4*>(&R[u[k]]);
+                            rb[k] = g.irp[u[k]];
+                            re[k] = g.irp[u[k] + 1];
                             const uint32_t lv = on_s ? rec.x : rec.y;
                             if ((lv & LVMASK) == want) wt[k] = ((uint64_t)rec.w << 32) | rec.z;
                         }
@@ -665,12 +764,14 @@ __device__ void run_sample(const DevGraph& g, const DevSlots& sl, int64_t so, co
                     for (int k = 0; k < WALK_UNROLL; k++) {
                         if (sel >= 0) continue;
                         const uint64_t incl = wave_incl_scan_u64(wt[k]);
-                        const uint64_t tot = __shfl(incl, 63, 64);
+                        const uint64_t tot = lane_u64(incl, 63);
                         if (r < tot) {
                             const unsigned long long m = __ballot(incl > r);
                             const int l = __ffsll((long long)m) - 1;
-                            r -= __shfl(incl - wt[k], l, 64);
-                            sel = __shfl(u[k], l, 64);
+                            r -= lane_u64(incl - wt[k], l);
+                            sel = lane_i32(u[k], l);
+                            nbeg = lane_i32(rb[k], l);
+                            nend = lane_i32(re[k], l);
                         } else {
                             r -= tot;
                         }
@@ -678,6 +779,8 @@ __device__ void run_sample(const DevGraph& g, const DevSlots& sl, int64_t so, co
                 }
                 if (sel < 0) { err = 1; break; }
                 w = sel;
+                beg = nbeg;
+                end = nend;
                 if (lane == 0) {
                     if (dbg) {
                         if (p < dbg_cap) dbg->path[p] = w;
@@ -786,6 +889,7 @@ __global__ __launch_bounds__(BSZ) void sampler_kernel(DevSlots sl, SampleLaunch 
         sh.acc_task = -1;
         flush_task_stats(sh, L);
     }
+    __syncthreads();
     if (tid < 64) claim_next(L, sh);
     __syncthreads();
     // Every thread reads the claimed sample here; wave 1 claims the next one
