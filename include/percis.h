@@ -219,7 +219,7 @@ int percis_exact(percis_ctx* ctx, int32_t graph, double* p_out, double* kernel_m
 /* Tuning knobs (launch shape only; results never depend on them).
  * PERCIS_OPT_SLOTS: concurrent samples (resident workgroups), 0 = auto.
  * PERCIS_OPT_SCRATCH_MB: cap on the sampler's scratch memory, 0 = auto.
- * PERCIS_OPT_BLOCK: threads per sample (256, 512 or 1024), 0 = auto.
+ * PERCIS_OPT_BLOCK: threads per sample (128, 256, 512 or 1024), 0 = auto.
  * PERCIS_OPT_BITMAPS: where the visited bitmaps live: 0 = auto (LDS when
  * they fit), 1 = device memory, 2 = LDS (PERCIS_E_INVAL if they do not fit).
  * Reading PERCIS_OPT_SLOTS, _BLOCK or _BITMAPS after a graph is loaded gives
@@ -233,7 +233,7 @@ int percis_get_option(percis_ctx* ctx, int option, int64_t* value);
 
 /* Autotuner: times probe_samples samples of graph `graph` (stream phase 3,
  * seed `seed`) under every launch shape that can run (threads per sample
- * 256/512/1024, bitmaps in LDS when they fit or in device memory, slots
+ * 128/256/512/1024, bitmaps in LDS when they fit or in device memory, slots
  * filling the device) and keeps the fastest as the context's shape. The
  * chosen shape is reported in *result (may be NULL). Results of sampling
  * calls never depend on the shape. */

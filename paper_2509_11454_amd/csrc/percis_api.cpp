@@ -309,12 +309,22 @@ static int64_t bitmap_words(int64_t act) { return ((std::max<int64_t>(act, 1) + 
 static int pick_shape(percis_ctx* c, int64_t act, SamplerShape* out, int* occ_out) {
     const int64_t words = bitmap_words(act);
     SamplerShape sh{};
-    sh.block = c->opt_block ? (int)c->opt_block : 256;
+    sh.block = c->opt_block ? (int)c->opt_block : 128;
     const int64_t lds_need = kBitmapPlanes * words * 4;
     const bool fits = lds_need + sampler_static_lds() <= kLdsPerCu;
     if (c->opt_bitmaps == 2 && !fits)
         return fail(c, PERCIS_E_INVAL, "bitmaps of %lld nodes do not fit in LDS", (long long)act);
-    sh.lds_bitmaps = c->opt_bitmaps == 2 || (c->opt_bitmaps == 0 && fits);
+    if (c->opt_bitmaps == 0) {
+        // LDS bitmaps unless they cost resident samples: the sampler is
+        // latency-bound, so samples in flight per CU matter more than where
+        // the visited bits live
+        SamplerShape dev = sh, lds = sh;
+        lds.lds_bitmaps = true;
+        lds.lds_bytes = lds_need;
+        sh.lds_bitmaps = fits && sampler_occupancy(lds) >= sampler_occupancy(dev);
+    } else {
+        sh.lds_bitmaps = c->opt_bitmaps == 2;
+    }
     sh.lds_bytes = sh.lds_bitmaps ? lds_need : 0;
     const int occ = sampler_occupancy(sh);
     if (occ <= 0)
@@ -931,8 +941,8 @@ int percis_set_option(percis_ctx* c, int option, int64_t value) {
         case PERCIS_OPT_SLOTS: c->opt_slots = value; break;
         case PERCIS_OPT_SCRATCH_MB: c->opt_scratch_mb = value; break;
         case PERCIS_OPT_BLOCK:
-            if (value != 0 && value != 256 && value != 512 && value != 1024)
-                return fail(c, PERCIS_E_INVAL, "block must be 256, 512 or 1024");
+            if (value != 0 && value != 128 && value != 256 && value != 512 && value != 1024)
+                return fail(c, PERCIS_E_INVAL, "block must be 128, 256, 512 or 1024");
             c->opt_block = value;
             break;
         case PERCIS_OPT_BITMAPS:
@@ -1038,7 +1048,7 @@ int percis_autotune(percis_ctx* c, int32_t graph, uint64_t probe_samples, uint64
     };
     std::vector<Cand> cands;
     const bool lds_ok = kBitmapPlanes * bitmap_words(act) * 4 + sampler_static_lds() <= kLdsPerCu;
-    for (int64_t b : {256, 512, 1024}) {
+    for (int64_t b : {128, 256, 512, 1024}) {
         if (lds_ok) cands.push_back({b, 2});
         cands.push_back({b, 1});
     }

@@ -38,7 +38,10 @@
 
 namespace percis {
 
-constexpr int CH = 256;  // frontier nodes staged per chunk
+constexpr int CH = 256;  // capacity of the LDS chunk arrays
+// Frontier nodes staged per chunk: one per thread, at most CH.
+template <int BSZ>
+constexpr int chunk_len() { return BSZ < CH ? BSZ : CH; }
 constexpr uint32_t LVMASK = 0x0FFFFFFFu;
 constexpr uint32_t OVFBIT = 0x40000000u;
 constexpr int UNROLL = 8;
@@ -219,12 +222,12 @@ struct Counters {
     unsigned long long E, A, V, Vd;
 };
 
-// Exclusive scan over the first CH threads (the chunk); every thread of the
-// block must call it.
+// Exclusive scan over the first chunk_len<BSZ>() threads (the chunk); every
+// thread of the block must call it.
 template <int BSZ>
 __device__ __forceinline__ int chunk_excl_scan(int v, int32_t* wsum, int& total) {
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    constexpr int NW = CH / 64;
+    constexpr int NW = chunk_len<BSZ>() / 64;
     int x = v;
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) {
@@ -254,7 +257,7 @@ __device__ __forceinline__ uint64_t wave_incl_scan_u64(uint64_t v) {
     return v;
 }
 
-// Stages up to CH frontier nodes q[base, base+cnt) of side SIDE in LDS: row
+// Stages up to chunk_len<BSZ>() frontier nodes q[base, base+cnt) of side SIDE in LDS: row
 // start, degree prefix sum, shortest-path count and overflow flag of each;
 // returns the number of adjacency entries of the chunk. Every thread must
 // call it.
@@ -276,7 +279,7 @@ __device__ __forceinline__ int stage_chunk(int32_t* q, int base, int cnt, const 
     }
     int total;
     const int ex = chunk_excl_scan<BSZ>(deg, sh.wsum, total);
-    if (tid < CH) {
+    if (tid < chunk_len<BSZ>()) {
         sh.node[tid] = u;
         sh.beg[tid] = beg;
         sh.off[tid] = ex;
@@ -311,7 +314,7 @@ __device__ __forceinline__ void wave_sum_wrap(uint64_t& v, uint32_t& wrap) {
 }
 
 // One BFS level over the frontier q[lo, hi) of one side (SIDE 0: s, out-arcs;
-// SIDE 1: t, in-arcs), edge-balanced: the rows of up to CH frontier nodes are
+// SIDE 1: t, in-arcs), edge-balanced: the rows of a chunk of frontier nodes are
 // concatenated and the workgroup strides over the concatenation, UNROLL
 // entries per thread at a time so that their loads overlap. An arc (u, w)
 // adds sigma(u) to w iff w is reached in this level: either its visited bit
@@ -339,8 +342,9 @@ __device__ void expand_bfs(const DevGraph& g, const DevSlots& sl, int64_t so, co
     uint64_t mass = 0, dsum = 0;
     uint32_t wrap = 0;
 
-    for (int base = lo; base < hi; base += CH) {
-        const int cnt = min(CH, hi - base);
+    constexpr int CHK = chunk_len<BSZ>();
+    for (int base = lo; base < hi; base += CHK) {
+        const int cnt = min(CHK, hi - base);
         const int total = stage_chunk<BSZ, SIDE>(q, base, cnt, rp, R, careful, sh, cn);
         for (int b0 = 0; b0 < total; b0 += BSZ * UNROLL) {
             int32_t w[UNROLL];
@@ -423,7 +427,7 @@ __device__ void expand_bfs(const DevGraph& g, const DevSlots& sl, int64_t so, co
                 }
             }
         }
-        if (base + CH < hi) __syncthreads();  // the caller's barrier follows the last chunk
+        if (base + CHK < hi) __syncthreads();  // the caller's barrier follows the last chunk
     }
     wave_sum_wrap(mass, wrap);
 #pragma unroll
@@ -446,8 +450,9 @@ __device__ void pull_level(const DevGraph& g, const DevSlots& sl, int64_t so, co
     const int tid = threadIdx.x;
     int32_t* q = sl.q_t + so;
     NodeRec* R = sl.rec + so;
-    for (int base = lo; base < hi; base += CH) {
-        const int cnt = min(CH, hi - base);
+    constexpr int CHK = chunk_len<BSZ>();
+    for (int base = lo; base < hi; base += CHK) {
+        const int cnt = min(CHK, hi - base);
         int deg = 0, beg = 0;
         int32_t x = 0;
         if (tid < cnt) {
@@ -458,7 +463,7 @@ __device__ void pull_level(const DevGraph& g, const DevSlots& sl, int64_t so, co
         }
         int total;
         const int ex = chunk_excl_scan<BSZ>(deg, sh.wsum, total);
-        if (tid < CH) {
+        if (tid < CHK) {
             sh.beg[tid] = beg;
             sh.off[tid] = ex;
             sh.sig[tid] = (uint64_t)(uint32_t)x;
@@ -479,7 +484,7 @@ __device__ void pull_level(const DevGraph& g, const DevSlots& sl, int64_t so, co
                 cn.A++;
             }
         }
-        if (base + CH < hi) __syncthreads();
+        if (base + CHK < hi) __syncthreads();
     }
 }
 
@@ -494,8 +499,9 @@ __device__ void push_meeting(const DevGraph& g, const DevSlots& sl, int64_t so, 
     const int tid = threadIdx.x;
     NodeRec* R = sl.rec + so;
     int32_t* qd = sl.q_d + so;
-    for (int base = 0; base < nmeet; base += CH) {
-        const int cnt = min(CH, nmeet - base);
+    constexpr int CHK = chunk_len<BSZ>();
+    for (int base = 0; base < nmeet; base += CHK) {
+        const int cnt = min(CHK, nmeet - base);
         const int total = stage_chunk<BSZ, 0>(qd, base, cnt, g.rp, R, false, sh, cn);
         for (int e = tid; e < total; e += BSZ) {
             const int j = chunk_owner(sh, cnt, e);
@@ -506,7 +512,7 @@ __device__ void push_meeting(const DevGraph& g, const DevSlots& sl, int64_t so, 
             (void)add64(&R[x].sg_s, sh.sig[j]);
             cn.A++;
         }
-        if (base + CH < nmeet) __syncthreads();
+        if (base + CHK < nmeet) __syncthreads();
     }
 }
 
@@ -1013,6 +1019,7 @@ static const void* sampler_fn() {
 
 static const void* pick_sampler(const SamplerShape& s) {
     switch (s.block) {
+        case 128: return s.lds_bitmaps ? sampler_fn<128, true>() : sampler_fn<128, false>();
         case 256: return s.lds_bitmaps ? sampler_fn<256, true>() : sampler_fn<256, false>();
         case 512: return s.lds_bitmaps ? sampler_fn<512, true>() : sampler_fn<512, false>();
         case 1024: return s.lds_bitmaps ? sampler_fn<1024, true>() : sampler_fn<1024, false>();
@@ -1047,6 +1054,7 @@ hipError_t launch_debug_path(const DevGraph& g, const DevSlots& slots, int32_t s
                              DebugOut* out, int32_t cap, const SamplerShape& shape, hipStream_t stream) {
     const void* fn = nullptr;
     switch (shape.block) {
+        case 128: fn = shape.lds_bitmaps ? (const void*)&debug_path_kernel<128, true> : (const void*)&debug_path_kernel<128, false>; break;
         case 256: fn = shape.lds_bitmaps ? (const void*)&debug_path_kernel<256, true> : (const void*)&debug_path_kernel<256, false>; break;
         case 512: fn = shape.lds_bitmaps ? (const void*)&debug_path_kernel<512, true> : (const void*)&debug_path_kernel<512, false>; break;
         case 1024: fn = shape.lds_bitmaps ? (const void*)&debug_path_kernel<1024, true> : (const void*)&debug_path_kernel<1024, false>; break;

@@ -121,3 +121,18 @@ def test_status_strings(P):
     for code in range(0, -8, -1):
         assert lib.percis_status_str(code)
     assert lib.percis_status_str(-99) == b"unknown status"
+
+
+def test_option_validation(P):
+    c = ctx(P)
+    for b in (0, 128, 256, 512, 1024):
+        c.set_option(P.OPT_BLOCK, b)
+        assert c.get_option(P.OPT_BLOCK) == b
+    for b in (64, 100, 2048):
+        with pytest.raises(P.PercisError) as e:
+            c.set_option(P.OPT_BLOCK, b)
+        assert e.value.status == P.E_INVAL
+    with pytest.raises(P.PercisError):
+        c.set_option(P.OPT_BITMAPS, 3)
+    with pytest.raises(P.PercisError):
+        c.set_option(P.OPT_SLOTS, -1)
