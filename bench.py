@@ -100,7 +100,8 @@ def main():
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--slots", type=int, default=0)
     ap.add_argument("--block", type=int, default=0)
-    ap.add_argument("--bitmaps", type=int, default=0, help="0 auto, 1 device memory, 2 LDS")
+    ap.add_argument("--bitmaps", type=int, default=0,
+                    help="visited sets: 0 auto, 1 device bitmaps, 2 LDS hash tables")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-estimate", action="store_true")
@@ -176,7 +177,7 @@ def main():
     traffic = measured_traffic(args.workload, samples)
     slots = c.get_option(P.OPT_SLOTS)
     block = c.get_option(P.OPT_BLOCK)
-    bitmaps = "lds" if c.get_option(P.OPT_BITMAPS) == 2 else "device"
+    bitmaps = "lds tables" if c.get_option(P.OPT_BITMAPS) == 2 else "device bitmaps"
 
     out = {
         "metric": METRIC,
@@ -193,7 +194,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": "%s: %s" % (args.workload, desc), "n": g.n, "m_arcs": g.m,
                    "samples_per_step": samples, "seed": args.seed, "slots": slots,
-                   "threads_per_sample": block, "bitmaps": bitmaps},
+                   "threads_per_sample": block, "visited_sets": bitmaps},
         "gteps": totals["edges"] / elapsed / 1e9,
         "edges_per_sample": totals["edges"] / (samples * args.steps),
         "reachable_fraction": totals["reachable"] / (samples * args.steps),

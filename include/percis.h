@@ -77,10 +77,10 @@ typedef struct {
     uint64_t vertices_discovered;
     double   kernel_ms;         /* device time of the sampling kernel */
     /* Time spent per sample phase, summed over the concurrently running
-     * samples (slot-milliseconds): drawing the pair (Algorithm 2), the
-     * bidirectional BFS, the meeting layer and DAG sweep, the path walk, and
-     * clearing the slot. Their ratios give the split between pair sampling
-     * and traversal that the paper reports (Section IV-B). */
+     * samples (slot-milliseconds): starting the two balls, the bidirectional
+     * BFS, the meeting layer and the sigma_s sweep, the path walk (during
+     * which one wave claims the next sample and draws its pair, Algorithm 2),
+     * and clearing the slot. */
     double   phase_ms[5];
 } percis_stats;
 
@@ -220,8 +220,10 @@ int percis_exact(percis_ctx* ctx, int32_t graph, double* p_out, double* kernel_m
  * PERCIS_OPT_SLOTS: concurrent samples (resident workgroups), 0 = auto.
  * PERCIS_OPT_SCRATCH_MB: cap on the sampler's scratch memory, 0 = auto.
  * PERCIS_OPT_BLOCK: threads per sample (128, 256, 512 or 1024), 0 = auto.
- * PERCIS_OPT_BITMAPS: where the visited bitmaps live: 0 = auto (LDS when
- * they fit), 1 = device memory, 2 = LDS (PERCIS_E_INVAL if they do not fit).
+ * PERCIS_OPT_BITMAPS: how a sample's visited sets are kept: 1 = one bitmap
+ * per side in device memory; 2 = an exact hash table per side in LDS (8 KB
+ * per sample), moved to the device bitmap if a side grows past 768 nodes;
+ * 0 = auto (2 unless it lowers the number of resident samples).
  * Reading PERCIS_OPT_SLOTS, _BLOCK or _BITMAPS after a graph is loaded gives
  * the shape in use (BITMAPS then reads 1 or 2). */
 #define PERCIS_OPT_SLOTS       1
@@ -233,13 +235,13 @@ int percis_get_option(percis_ctx* ctx, int option, int64_t* value);
 
 /* Autotuner: times probe_samples samples of graph `graph` (stream phase 3,
  * seed `seed`) under every launch shape that can run (threads per sample
- * 128/256/512/1024, bitmaps in LDS when they fit or in device memory, slots
+ * 128/256/512/1024, visited sets in LDS tables or device bitmaps, slots
  * filling the device) and keeps the fastest as the context's shape. The
  * chosen shape is reported in *result (may be NULL). Results of sampling
  * calls never depend on the shape. */
 typedef struct {
     int32_t block;          /* threads per sample */
-    int32_t bitmaps;        /* 1 = device memory, 2 = LDS */
+    int32_t bitmaps;        /* visited sets: 1 = device bitmaps, 2 = LDS tables */
     int32_t slots;          /* concurrent samples */
     int32_t candidates;     /* shapes timed */
     double samples_per_s;   /* probe throughput of the chosen shape */

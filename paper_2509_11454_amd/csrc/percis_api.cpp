@@ -310,26 +310,27 @@ static int pick_shape(percis_ctx* c, int64_t act, SamplerShape* out, int* occ_ou
     const int64_t words = bitmap_words(act);
     SamplerShape sh{};
     sh.block = c->opt_block ? (int)c->opt_block : 128;
-    const int64_t lds_need = kBitmapPlanes * words * 4;
+    (void)words;
+    const int64_t lds_need = sampler_table_lds();
     const bool fits = lds_need + sampler_static_lds() <= kLdsPerCu;
     if (c->opt_bitmaps == 2 && !fits)
-        return fail(c, PERCIS_E_INVAL, "bitmaps of %lld nodes do not fit in LDS", (long long)act);
+        return fail(c, PERCIS_E_INVAL, "visited-set tables do not fit in LDS");
     if (c->opt_bitmaps == 0) {
-        // LDS bitmaps unless they cost resident samples: the sampler is
+        // LDS tables unless they cost resident samples: the sampler is
         // latency-bound, so samples in flight per CU matter more than where
-        // the visited bits live
+        // the visited sets live
         SamplerShape dev = sh, lds = sh;
-        lds.lds_bitmaps = true;
+        lds.lds_sets = true;
         lds.lds_bytes = lds_need;
-        sh.lds_bitmaps = fits && sampler_occupancy(lds) >= sampler_occupancy(dev);
+        sh.lds_sets = fits && sampler_occupancy(lds) >= sampler_occupancy(dev);
     } else {
-        sh.lds_bitmaps = c->opt_bitmaps == 2;
+        sh.lds_sets = c->opt_bitmaps == 2;
     }
-    sh.lds_bytes = sh.lds_bitmaps ? lds_need : 0;
+    sh.lds_bytes = sh.lds_sets ? lds_need : 0;
     const int occ = sampler_occupancy(sh);
     if (occ <= 0)
-        return fail(c, PERCIS_E_DEVICE, "sampler shape (block %d, %s bitmaps) cannot launch", sh.block,
-                    sh.lds_bitmaps ? "LDS" : "device");
+        return fail(c, PERCIS_E_DEVICE, "sampler shape (block %d, visited sets in %s) cannot launch", sh.block,
+                    sh.lds_sets ? "LDS tables" : "device bitmaps");
     *out = sh;
     *occ_out = occ;
     return PERCIS_OK;
@@ -351,7 +352,7 @@ static int ensure_slots(percis_ctx* c, int64_t act) {
     if (rc) return rc;
     const int64_t stride = (act + 63) / 64 * 64;
     const int64_t words = bitmap_words(act);
-    const int64_t per_slot = stride * kSlotBytesPerNode + 8 + (sh.lds_bitmaps ? 0 : kBitmapPlanes * words * 4);
+    const int64_t per_slot = stride * kSlotBytesPerNode + 8 + kBitmapPlanes * words * 4;  // device bitmaps (spill space in LDS mode)
     size_t free_b = 0, total_b = 0;
     HIPCHK(c, hipMemGetInfo(&free_b, &total_b));
     const int64_t budget = c->opt_scratch_mb > 0 ? c->opt_scratch_mb * (1ll << 20) : (int64_t)(free_b * 0.6);
@@ -380,7 +381,7 @@ static int ensure_slots(percis_ctx* c, int64_t act) {
     s.q_t = (int32_t*)p; p += cnt * 4;
     s.q_d = (int32_t*)p; p += cnt * 4;
     s.tls = (int32_t*)p; p += ns * (stride + 2) * 4;
-    s.bm = sh.lds_bitmaps ? nullptr : (uint32_t*)p;
+    s.bm = (uint32_t*)p;
     c->slot_mem = mem;
     c->slots = s;
     c->nslots = (int)ns;
@@ -946,7 +947,7 @@ int percis_set_option(percis_ctx* c, int option, int64_t value) {
             c->opt_block = value;
             break;
         case PERCIS_OPT_BITMAPS:
-            if (value > 2) return fail(c, PERCIS_E_INVAL, "bitmaps option is 0 (auto), 1 (device memory) or 2 (LDS)");
+            if (value > 2) return fail(c, PERCIS_E_INVAL, "bitmaps option is 0 (auto), 1 (device bitmaps) or 2 (LDS tables)");
             c->opt_bitmaps = value;
             break;
         default: return fail(c, PERCIS_E_INVAL, "unknown option %d", option);
@@ -973,7 +974,7 @@ int percis_get_option(percis_ctx* c, int option, int64_t* value) {
     if ((rc = ensure_slots(c, act))) return rc;
     *value = option == PERCIS_OPT_SLOTS ? c->nslots
            : option == PERCIS_OPT_BLOCK ? c->shape.block
-                                        : (c->shape.lds_bitmaps ? 2 : 1);
+                                        : (c->shape.lds_sets ? 2 : 1);
     return PERCIS_OK;
 }
 
@@ -1047,7 +1048,7 @@ int percis_autotune(percis_ctx* c, int32_t graph, uint64_t probe_samples, uint64
         int64_t block, bitmaps;
     };
     std::vector<Cand> cands;
-    const bool lds_ok = kBitmapPlanes * bitmap_words(act) * 4 + sampler_static_lds() <= kLdsPerCu;
+    const bool lds_ok = sampler_table_lds() + sampler_static_lds() <= kLdsPerCu;
     for (int64_t b : {128, 256, 512, 1024}) {
         if (lds_ok) cands.push_back({b, 2});
         cands.push_back({b, 1});
@@ -1083,7 +1084,7 @@ int percis_autotune(percis_ctx* c, int32_t graph, uint64_t probe_samples, uint64
     if ((rc = ensure_slots(c, act))) return rc;
     if (result) {
         result->block = (int32_t)c->shape.block;
-        result->bitmaps = c->shape.lds_bitmaps ? 2 : 1;
+        result->bitmaps = c->shape.lds_sets ? 2 : 1;
         result->slots = c->nslots;
         result->candidates = tried;
         result->samples_per_s = best_rate;

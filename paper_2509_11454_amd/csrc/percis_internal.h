@@ -100,8 +100,8 @@ struct DebugOut {
 // visited bitmaps live in LDS.
 struct SamplerShape {
     int block;        // 256, 512 or 1024
-    bool lds_bitmaps;
-    int64_t lds_bytes;  // dynamic LDS per workgroup (3 bitmaps) when lds_bitmaps
+    bool lds_sets;
+    int64_t lds_bytes;  // dynamic LDS per workgroup (the visited-set tables) when lds_sets
 };
 
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t count, hipStream_t stream);
@@ -122,5 +122,6 @@ int64_t exact_scratch_bytes(int64_t stride, int slots);
 // Resident workgroups per CU for a shape (0 if it cannot launch).
 int sampler_occupancy(const SamplerShape& shape);
 int64_t sampler_static_lds();
+int64_t sampler_table_lds();  // dynamic LDS of the visited-set tables (LDS mode)
 
 }  // namespace percis

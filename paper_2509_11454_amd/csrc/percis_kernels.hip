@@ -67,11 +67,8 @@ __device__ __forceinline__ uint32_t* LV(NodeRec* R, int32_t w) { return SIDE ? &
 template <int SIDE>
 __device__ __forceinline__ uint64_t* SG(NodeRec* R, int32_t w) { return SIDE ? &R[w].sg_t : &R[w].sg_s; }
 
-// Visited bitmaps: two planes per slot, s-side visited and t-side visited.
-template <bool LDS>
+// Bitmap operations on one plane of a slot's device bitmaps.
 struct Bits {
-    uint32_t* vs;
-    uint32_t* vt;
     __device__ __forceinline__ static uint32_t rd(uint32_t* p, int32_t w) {
         return __hip_atomic_load(p + (w >> 5), __ATOMIC_RELAXED, WGS);
     }
@@ -83,6 +80,64 @@ struct Bits {
         __hip_atomic_store(p + (w >> 5), 0u, __ATOMIC_RELAXED, WGS);
     }
 };
+
+// Visited sets of a sample's two balls.
+// LDS = false: one bitmap plane per side in the slot's device memory.
+// LDS = true: an exact open-addressing hash table per side in LDS (node id + 1,
+// 0 = empty, linear probing), small because a sample's balls are small once
+// the last level keeps only its meeting layer. A side whose table would fill
+// up is spilled to its device bitmap plane (every node of the side is in its
+// queue) and uses the bitmap from then on.
+constexpr int HBITS = 10;
+constexpr int HCAP = 1 << HBITS;       // table slots per side
+constexpr int HLIMIT = 3 * HCAP / 4;   // most entries a table takes
+constexpr int HADMIT = 5 * HCAP / 8;   // a level decides first visits by the table if it cannot add more
+template <bool LDS>
+struct Vis {
+    uint32_t* bm[2];   // device bitmap planes
+    uint32_t* tab[2];  // LDS tables (LDS = true)
+};
+
+__device__ __forceinline__ uint32_t hslot(int32_t x) { return ((uint32_t)x * 0x9E3779B1u) >> (32 - HBITS); }
+
+__device__ __forceinline__ bool table_has(uint32_t* T, int32_t x) {
+    const uint32_t key = (uint32_t)x + 1;
+    for (uint32_t i = hslot(x);; i = (i + 1) & (HCAP - 1)) {
+        const uint32_t v = __hip_atomic_load(T + i, __ATOMIC_RELAXED, WGS);
+        if (v == key) return true;
+        if (v == 0) return false;
+    }
+}
+
+// Inserts x, known to be absent and inserted by this thread only; false if
+// the table is full (it then stays without x).
+__device__ __forceinline__ bool table_put(uint32_t* T, int32_t* cnt, int32_t x) {
+    if (atomicAdd(cnt, 1) >= HLIMIT) return false;
+    const uint32_t key = (uint32_t)x + 1;
+    for (uint32_t i = hslot(x);; i = (i + 1) & (HCAP - 1)) {
+        uint32_t expect = 0;
+        if (__hip_atomic_compare_exchange_strong(T + i, &expect, key, __ATOMIC_RELAXED, __ATOMIC_RELAXED, WGS))
+            return true;
+    }
+}
+
+// Finds or inserts x; true iff this call inserted it. The caller guarantees
+// room (fewer than HCAP entries after every possible insert).
+__device__ __forceinline__ bool table_visit(uint32_t* T, int32_t* cnt, int32_t x) {
+    const uint32_t key = (uint32_t)x + 1;
+    for (uint32_t i = hslot(x);; i = (i + 1) & (HCAP - 1)) {
+        uint32_t v = __hip_atomic_load(T + i, __ATOMIC_RELAXED, WGS);
+        if (v == 0) {
+            uint32_t expect = 0;
+            if (__hip_atomic_compare_exchange_strong(T + i, &expect, key, __ATOMIC_RELAXED, __ATOMIC_RELAXED, WGS)) {
+                atomicAdd(cnt, 1);
+                return true;
+            }
+            v = expect;
+        }
+        if (v == key) return false;
+    }
+}
 
 // Lane l's value as a wave-uniform (scalar) value; l must be wave-uniform.
 // Values that steer a wave's control flow are taken this way rather than by
@@ -184,6 +239,10 @@ struct SampleShared {
     int32_t tail, tail_s, tail_t;
     int32_t nmeet;
     int32_t level_meets;  // the level being built has an arc into the other ball
+    int32_t level_table;  // the level being built decides first visits by its side's table
+    int32_t hcnt[2];      // entries reserved in each side's table
+    int32_t spilled[2];   // the side's visited set lives in its device bitmap
+    int32_t spill_req[2]; // the side's table overflowed in the level being built
     int32_t status;   // 0 running, 1 met, 2 unreachable
     int32_t side;     // side of the level being built
     int32_t ovf;
@@ -198,6 +257,13 @@ struct SampleShared {
     unsigned long long acc_samples, acc_reach, acc_sum_I, acc_sum_I2, acc_ovf, acc_first;
     int32_t acc_task;
 };
+
+// Is x in side `side`'s ball? Exact.
+template <bool LDS>
+__device__ __forceinline__ bool member(const Vis<LDS>& V, const SampleShared& sh, int side, int32_t x) {
+    if (!LDS || sh.spilled[side]) return Bits::test(Bits::rd(V.bm[side], x), x);
+    return table_has(V.tab[side], x);
+}
 
 // Thread 0 only.
 __device__ void flush_task_stats(SampleShared& sh, const SampleLaunch& L) {
@@ -329,16 +395,16 @@ __device__ __forceinline__ void wave_sum_wrap(uint64_t& v, uint32_t& wrap) {
 // when that sum reached 2^64. The level's own sum and degree sum (the
 // degrees its expansion will scan) are gathered on the way.
 template <int SIDE, int BSZ, bool LDS>
-__device__ void expand_bfs(const DevGraph& g, const DevSlots& sl, int64_t so, const Bits<LDS>& bits, int lo, int hi,
+__device__ void expand_bfs(const DevGraph& g, const DevSlots& sl, int64_t so, const Vis<LDS>& V, int lo, int hi,
                            uint32_t nl, bool careful, SampleShared& sh, Counters& cn) {
-    using B = Bits<LDS>;
+    using B = Bits;
     const int tid = threadIdx.x;
+    const bool by_table = LDS && sh.level_table;   // else: bitmap (device mode) or record CAS (LDS mode)
     const int32_t* rp = SIDE ? g.irp : g.rp;
     const int32_t* col = SIDE ? g.icol : g.col;
     int32_t* q = (SIDE ? sl.q_t : sl.q_s) + so;
     NodeRec* R = sl.rec + so;
-    uint32_t* vis_mine = SIDE ? bits.vt : bits.vs;
-    uint32_t* vis_other = SIDE ? bits.vs : bits.vt;
+    uint32_t* vis_mine = V.bm[SIDE];
     uint64_t mass = 0, dsum = 0;
     uint32_t wrap = 0;
 
@@ -362,7 +428,7 @@ __device__ void expand_bfs(const DevGraph& g, const DevSlots& sl, int64_t so, co
             }
 #pragma unroll
             for (int k = 0; k < UNROLL; k++)
-                if (jj[k] >= 0 && B::test(B::rd(vis_other, w[k]), w[k])) into_other |= 1u << k;
+                if (jj[k] >= 0 && member<LDS>(V, sh, 1 - SIDE, w[k])) into_other |= 1u << k;
             // A level with an arc into the other ball is the last one, and of
             // its new nodes only the meeting layer is used again: once any
             // thread has seen such an arc, arcs to other nodes are skipped.
@@ -381,13 +447,34 @@ __device__ void expand_bfs(const DevGraph& g, const DevSlots& sl, int64_t so, co
                 if (meets && !((into_other >> k) & 1u)) continue;
                 const int32_t x = w[k];
                 const int j = jj[k];
-                bool add, fresh = false;
-                if (!B::test(B::rd(vis_mine, x), x)) {
-                    fresh = !B::test(B::set(vis_mine, x), x);
-                    add = true;
+                bool add, fresh = false, lv_written = false;
+                if (!LDS) {
+                    if (!B::test(B::rd(vis_mine, x), x)) {
+                        fresh = !B::test(B::set(vis_mine, x), x);
+                        add = true;
+                    } else {
+                        const uint32_t lv = ld32(LV<SIDE>(R, x)) & LVMASK;
+                        add = lv == 0 || lv == nl;
+                    }
+                } else if (by_table) {
+                    fresh = table_visit(V.tab[SIDE], &sh.hcnt[SIDE], x);
+                    if (fresh) {
+                        add = true;
+                    } else {
+                        const uint32_t lv = ld32(LV<SIDE>(R, x)) & LVMASK;
+                        add = lv == 0 || lv == nl;
+                    }
                 } else {
-                    const uint32_t lv = ld32(LV<SIDE>(R, x)) & LVMASK;
-                    add = lv == 0 || lv == nl;
+                    // the record's level field decides: 0 = not reached yet
+                    uint32_t old = 0;
+                    fresh = __hip_atomic_compare_exchange_strong(LV<SIDE>(R, x), &old, nl, __ATOMIC_RELAXED,
+                                                                 __ATOMIC_RELAXED, WGS);
+                    add = fresh || (old & LVMASK) == nl;
+                    lv_written = true;
+                    if (fresh) {
+                        if (sh.spilled[SIDE]) (void)B::set(vis_mine, x);
+                        else if (!table_put(V.tab[SIDE], &sh.hcnt[SIDE], x)) sh.spill_req[SIDE] = 1;
+                    }
                 }
                 if (add) {
                     const uint64_t addv = sh.sig[j];
@@ -415,7 +502,7 @@ __device__ void expand_bfs(const DevGraph& g, const DevSlots& sl, int64_t so, co
                     cn.A++;
                 }
                 if (fresh) {
-                    or32(LV<SIDE>(R, x), nl);
+                    if (!lv_written) or32(LV<SIDE>(R, x), nl);
                     const int pos = atomicAdd(&sh.tail, 1);
                     q[pos] = x;
                     cn.Vd++;
@@ -444,9 +531,8 @@ __device__ void expand_bfs(const DevGraph& g, const DevSlots& sl, int64_t so, co
 // want = j + 1). Counts of nodes off the shortest-path DAG are 0, so only
 // DAG arcs add. No count here exceeds sigma_st, known to be below 2^64.
 template <int BSZ, bool LDS>
-__device__ void pull_level(const DevGraph& g, const DevSlots& sl, int64_t so, const Bits<LDS>& bits, int lo, int hi,
+__device__ void pull_level(const DevGraph& g, const DevSlots& sl, int64_t so, const Vis<LDS>& V, int lo, int hi,
                            uint32_t want, SampleShared& sh, Counters& cn) {
-    using B = Bits<LDS>;
     const int tid = threadIdx.x;
     int32_t* q = sl.q_t + so;
     NodeRec* R = sl.rec + so;
@@ -473,7 +559,7 @@ __device__ void pull_level(const DevGraph& g, const DevSlots& sl, int64_t so, co
             const int j = chunk_owner(sh, cnt, e);
             const int32_t u = g.icol[sh.beg[j] + (e - sh.off[j])];
             cn.E++;
-            if (!B::test(B::rd(bits.vt, u), u)) continue;
+            if (!member<LDS>(V, sh, 1, u)) continue;
             // levels of this level's nodes are final (set before the last
             // barrier); their sigma_s was completed by the previous pull level
             const uint4 rec = *reinterpret_cast<const uint4*>(&R[u]);
@@ -493,9 +579,8 @@ __device__ void pull_level(const DevGraph& g, const DevSlots& sl, int64_t so, co
 // of t-level b - 1): every meeting node w adds sigma_s(w) to its
 // out-neighbours at t-level b - 1 (t-level value want = b).
 template <int BSZ, bool LDS>
-__device__ void push_meeting(const DevGraph& g, const DevSlots& sl, int64_t so, const Bits<LDS>& bits, int nmeet,
+__device__ void push_meeting(const DevGraph& g, const DevSlots& sl, int64_t so, const Vis<LDS>& V, int nmeet,
                              uint32_t want, SampleShared& sh, Counters& cn) {
-    using B = Bits<LDS>;
     const int tid = threadIdx.x;
     NodeRec* R = sl.rec + so;
     int32_t* qd = sl.q_d + so;
@@ -507,7 +592,7 @@ __device__ void push_meeting(const DevGraph& g, const DevSlots& sl, int64_t so, 
             const int j = chunk_owner(sh, cnt, e);
             const int32_t x = g.col[sh.beg[j] + (e - sh.off[j])];
             cn.E++;
-            if (!B::test(B::rd(bits.vt, x), x)) continue;
+            if (!member<LDS>(V, sh, 1, x)) continue;
             if ((ld32(&R[x].lv_t) & LVMASK) != want) continue;
             (void)add64(&R[x].sg_s, sh.sig[j]);
             cn.A++;
@@ -522,6 +607,9 @@ __device__ void push_meeting(const DevGraph& g, const DevSlots& sl, int64_t so, 
 __device__ __forceinline__ void plan_level(SampleShared& sh) {
     sh.side = (sh.deg_s <= sh.deg_t) ? 0 : 1;
     sh.tail = sh.side == 0 ? sh.hi_s : sh.hi_t;
+    // a level adds at most its frontier degree sum of new nodes
+    const unsigned long long deg = sh.side == 0 ? sh.deg_s : sh.deg_t;
+    sh.level_table = !sh.spilled[sh.side] && (unsigned long long)sh.hcnt[sh.side] + deg <= (unsigned long long)HADMIT;
     sh.deg_next = 0;
     sh.mass_next = 0;
     sh.wide_next = 0;
@@ -588,10 +676,10 @@ __device__ void claim_next(const SampleLaunch& L, SampleShared& sh) {
 // debug mode (dbg != nullptr) the path index is given instead of drawn, hits
 // are not touched and the path is written to dbg (internal ids).
 template <int BSZ, bool LDS>
-__device__ void run_sample(const DevGraph& g, const DevSlots& sl, int64_t so, const Bits<LDS>& bits, uint64_t idx,
+__device__ void run_sample(const DevGraph& g, const DevSlots& sl, int64_t so, const Vis<LDS>& V, uint64_t idx,
                            const DevTask& T, int32_t s, int32_t t, const SampleLaunch* next, SampleShared& sh,
                            Counters& cn, DebugOut* dbg, uint64_t dbg_r, int32_t dbg_cap) {
-    using B = Bits<LDS>;
+    using B = Bits;
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     NodeRec* R = sl.rec + so;
     int32_t* q_s = sl.q_s + so;
@@ -617,14 +705,22 @@ __device__ void run_sample(const DevGraph& g, const DevSlots& sl, int64_t so, co
             sh.t = t;
             sh.nmeet = 0; sh.ovf = 0; sh.walk_err = 0; sh.sigma = 0;
             sh.a = 0; sh.b = 0;
+            sh.hcnt[0] = sh.hcnt[1] = 0;
+            sh.spilled[0] = sh.spilled[1] = 0;
+            sh.spill_req[0] = sh.spill_req[1] = 0;
             if (s >= g.n_act || t >= g.n_act) {
                 // a node without arcs reaches nothing and is reached by nothing
                 sh.status = 2;
                 sh.tail_s = 0; sh.tail_t = 0;
             } else {
                 sh.status = 0;
-                B::set(bits.vs, s);
-                B::set(bits.vt, t);
+                if (LDS) {
+                    (void)table_put(V.tab[0], &sh.hcnt[0], s);
+                    (void)table_put(V.tab[1], &sh.hcnt[1], t);
+                } else {
+                    B::set(V.bm[0], s);
+                    B::set(V.bm[1], t);
+                }
                 or32(&R[s].lv_s, 1u); R[s].sg_s = 1; q_s[0] = s;
                 or32(&R[t].lv_t, 1u); R[t].sg_t = 1; q_t[0] = t;
                 tls[0] = 0; tls[1] = 1;
@@ -648,10 +744,21 @@ __device__ void run_sample(const DevGraph& g, const DevSlots& sl, int64_t so, co
         const int side = sh.side;
         const int nlo = side == 0 ? sh.hi_s : sh.hi_t;
         const bool careful = (side == 0 ? sh.wide_s : sh.wide_t) != 0;
-        if (side == 0) expand_bfs<0, BSZ, LDS>(g, sl, so, bits, sh.lo_s, sh.hi_s, (uint32_t)sh.a + 2, careful, sh, cn);
-        else expand_bfs<1, BSZ, LDS>(g, sl, so, bits, sh.lo_t, sh.hi_t, (uint32_t)sh.b + 2, careful, sh, cn);
+        if (side == 0) expand_bfs<0, BSZ, LDS>(g, sl, so, V, sh.lo_s, sh.hi_s, (uint32_t)sh.a + 2, careful, sh, cn);
+        else expand_bfs<1, BSZ, LDS>(g, sl, so, V, sh.lo_t, sh.hi_t, (uint32_t)sh.b + 2, careful, sh, cn);
         level_barrier();
         const int nhi = sh.tail;
+        if (LDS && sh.spill_req[side]) {
+            // the side's table overflowed: its whole ball (its queue) moves to
+            // the device bitmap, which answers for the side from now on
+            int32_t* qq = side == 0 ? q_s : q_t;
+            for (int i = tid; i < nhi; i += BSZ) (void)B::set(V.bm[side], ldq(qq + i));
+            __syncthreads();
+            if (tid == 0) {
+                sh.spilled[side] = 1;
+                sh.spill_req[side] = 0;
+            }
+        }
         if (tid == 0) {
             if (side == 0) {
                 sh.lo_s = nlo; sh.hi_s = nhi; sh.tail_s = nhi; sh.a++;
@@ -717,12 +824,12 @@ __device__ void run_sample(const DevGraph& g, const DevSlots& sl, int64_t so, co
             if (sh.side == 1) {
                 j--;
             } else if (j >= 1 && sh.push_cost < sh.deg_t_prev) {
-                push_meeting<BSZ, LDS>(g, sl, so, bits, sh.nmeet, (uint32_t)j, sh, cn);
+                push_meeting<BSZ, LDS>(g, sl, so, V, sh.nmeet, (uint32_t)j, sh, cn);
                 level_barrier();
                 j--;
             }
             for (; j >= 1; j--) {
-                pull_level<BSZ, LDS>(g, sl, so, bits, ldq(tls + j - 1), ldq(tls + j), (uint32_t)j + 1, sh, cn);
+                pull_level<BSZ, LDS>(g, sl, so, V, ldq(tls + j - 1), ldq(tls + j), (uint32_t)j + 1, sh, cn);
                 level_barrier();
             }
         }
@@ -740,7 +847,6 @@ __device__ void run_sample(const DevGraph& g, const DevSlots& sl, int64_t so, co
                 // meeting layer) t-level L - p; their sigma_s weighs them
                 const bool on_s = p <= aM;
                 const uint32_t want = on_s ? (uint32_t)p + 1 : (uint32_t)(L - p) + 1;
-                uint32_t* vis = on_s ? bits.vs : bits.vt;
                 int32_t sel = -1, nbeg = 0, nend = 0;
                 for (int32_t base = beg; base < end && sel < 0; base += 64 * WALK_UNROLL) {
                     int32_t u[WALK_UNROLL], rb[WALK_UNROLL], re[WALK_UNROLL];
@@ -757,7 +863,7 @@ __device__ void run_sample(const DevGraph& g, const DevSlots& sl, int64_t so, co
                         wt[k] = 0;
                         rb[k] = 0;
                         re[k] = 0;
-                        if (u[k] >= 0 && B::test(B::rd(vis, u[k]), u[k])) {
+                        if (u[k] >= 0 && member<LDS>(V, sh, on_s ? 0 : 1, u[k])) {
                             const uint4 rec = *reinterpret_cast<const uint4*>(&R[u[k]]);
                             rb[k] = g.irp[u[k]];
                             re[k] = g.irp[u[k] + 1];
@@ -832,15 +938,19 @@ __device__ void run_sample(const DevGraph& g, const DevSlots& sl, int64_t so, co
 
     // ---- clear what this sample touched (every node reached is in q_s or q_t)
     const int ts = sh.tail_s, tt = sh.tail_t;
+    const bool bm_s = !LDS || sh.spilled[0], bm_t = !LDS || sh.spilled[1];
     for (int i = tid; i < ts; i += BSZ) {
         const int32_t w = ldq(q_s + i);
         R[w] = NodeRec{};
-        B::clear_word(bits.vs, w);
+        if (bm_s) B::clear_word(V.bm[0], w);
     }
     for (int i = tid; i < tt; i += BSZ) {
         const int32_t w = ldq(q_t + i);
         R[w] = NodeRec{};
-        B::clear_word(bits.vt, w);
+        if (bm_t) B::clear_word(V.bm[1], w);
+    }
+    if (LDS) {
+        for (int i = tid; i < 2 * HCAP; i += BSZ) __hip_atomic_store(V.tab[0] + i, 0u, __ATOMIC_RELAXED, WGS);
     }
     level_barrier();
     phase_mark(4);
@@ -866,17 +976,14 @@ __device__ void flush_counters(const Counters& cn, DevStats* st) {
 extern __shared__ uint32_t dyn_lds[];
 
 template <int BSZ, bool LDS>
-__device__ __forceinline__ Bits<LDS> slot_bits(const DevSlots& sl, int slot) {
-    Bits<LDS> b;
-    if (LDS) {
-        b.vs = dyn_lds;
-        b.vt = dyn_lds + sl.words;
-    } else {
-        uint32_t* base = sl.bm + (int64_t)slot * 2 * sl.words;
-        b.vs = base;
-        b.vt = base + sl.words;
-    }
-    return b;
+__device__ __forceinline__ Vis<LDS> slot_vis(const DevSlots& sl, int slot) {
+    Vis<LDS> v;
+    uint32_t* base = sl.bm + (int64_t)slot * 2 * sl.words;
+    v.bm[0] = base;
+    v.bm[1] = base + sl.words;
+    v.tab[0] = dyn_lds;          // the two tables are adjacent
+    v.tab[1] = dyn_lds + HCAP;
+    return v;
 }
 
 template <int BSZ, bool LDS>
@@ -885,10 +992,10 @@ __global__ __launch_bounds__(BSZ) void sampler_kernel(DevSlots sl, SampleLaunch 
     __shared__ SampleShared sh;
     const int tid = threadIdx.x;
     const int64_t so = (int64_t)blockIdx.x * sl.stride;
-    const Bits<LDS> bits = slot_bits<BSZ, LDS>(sl, blockIdx.x);
+    const Vis<LDS> V = slot_vis<BSZ, LDS>(sl, blockIdx.x);
     Counters cn = {0, 0, 0, 0};
     if (LDS) {
-        for (int64_t i = tid; i < 2 * sl.words; i += BSZ) dyn_lds[i] = 0;
+        for (int i = tid; i < 2 * HCAP; i += BSZ) dyn_lds[i] = 0;
     }
     if (tid == 0) {
         for (int i = 0; i < 5; i++) sh.phase_ticks[i] = 0;
@@ -910,7 +1017,7 @@ __global__ __launch_bounds__(BSZ) void sampler_kernel(DevSlots sl, SampleLaunch 
             flush_task_stats(sh, L);
             sh.acc_task = k;
         }
-        run_sample<BSZ, LDS>(T.g, sl, so, bits, T.first + (q - T.offset), T, s, t, &L, sh, cn, nullptr, 0, 0);
+        run_sample<BSZ, LDS>(T.g, sl, so, V, T.first + (q - T.offset), T, s, t, &L, sh, cn, nullptr, 0, 0);
     }
     flush_counters(cn, L.stats);
     if (tid == 0) {
@@ -923,17 +1030,17 @@ template <int BSZ, bool LDS>
 __global__ __launch_bounds__(BSZ) void debug_path_kernel(DevGraph g, DevSlots sl, int32_t s, int32_t t, uint64_t r,
                                                          DebugOut* out, int32_t cap) {
     __shared__ SampleShared sh;
-    const Bits<LDS> bits = slot_bits<BSZ, LDS>(sl, 0);
+    const Vis<LDS> V = slot_vis<BSZ, LDS>(sl, 0);
     Counters cn = {0, 0, 0, 0};
     if (LDS) {
-        for (int64_t i = threadIdx.x; i < 2 * sl.words; i += BSZ) dyn_lds[i] = 0;
+        for (int i = threadIdx.x; i < 2 * HCAP; i += BSZ) dyn_lds[i] = 0;
     }
     if (threadIdx.x == 0) {
         for (int i = 0; i < 5; i++) sh.phase_ticks[i] = 0;
     }
     __syncthreads();
     DevTask T = {};
-    run_sample<BSZ, LDS>(g, sl, 0, bits, 0, T, s, t, nullptr, sh, cn, out, r, cap);
+    run_sample<BSZ, LDS>(g, sl, 0, V, 0, T, s, t, nullptr, sh, cn, out, r, cap);
 }
 
 __global__ void fill_u32_kernel(uint32_t* p, uint32_t v, int64_t count) {
@@ -1011,6 +1118,7 @@ hipError_t launch_clear_tasks(const DevTask* tasks, int ntasks, int64_t max_n, h
 }
 
 int64_t sampler_static_lds() { return (int64_t)sizeof(SampleShared); }
+int64_t sampler_table_lds() { return (int64_t)2 * HCAP * sizeof(uint32_t); }
 
 template <int BSZ, bool LDS>
 static const void* sampler_fn() {
@@ -1019,10 +1127,10 @@ static const void* sampler_fn() {
 
 static const void* pick_sampler(const SamplerShape& s) {
     switch (s.block) {
-        case 128: return s.lds_bitmaps ? sampler_fn<128, true>() : sampler_fn<128, false>();
-        case 256: return s.lds_bitmaps ? sampler_fn<256, true>() : sampler_fn<256, false>();
-        case 512: return s.lds_bitmaps ? sampler_fn<512, true>() : sampler_fn<512, false>();
-        case 1024: return s.lds_bitmaps ? sampler_fn<1024, true>() : sampler_fn<1024, false>();
+        case 128: return s.lds_sets ? sampler_fn<128, true>() : sampler_fn<128, false>();
+        case 256: return s.lds_sets ? sampler_fn<256, true>() : sampler_fn<256, false>();
+        case 512: return s.lds_sets ? sampler_fn<512, true>() : sampler_fn<512, false>();
+        case 1024: return s.lds_sets ? sampler_fn<1024, true>() : sampler_fn<1024, false>();
         default: return nullptr;
     }
 }
@@ -1031,7 +1139,7 @@ int sampler_occupancy(const SamplerShape& s) {
     const void* fn = pick_sampler(s);
     if (!fn) return 0;
     int blocks = 0;
-    const size_t dyn = s.lds_bitmaps ? (size_t)s.lds_bytes : 0;
+    const size_t dyn = s.lds_sets ? (size_t)s.lds_bytes : 0;
     if (dyn > 0) (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn);
     (void)hipGetLastError();
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, fn, s.block, dyn) != hipSuccess) return 0;
@@ -1043,7 +1151,7 @@ hipError_t launch_sampler(const DevSlots& slots, const SampleLaunch& a, const Sa
     if (a.total == 0 || a.slots <= 0) return hipSuccess;
     const void* fn = pick_sampler(shape);
     if (!fn) return hipErrorInvalidValue;
-    const size_t dyn = shape.lds_bitmaps ? (size_t)shape.lds_bytes : 0;
+    const size_t dyn = shape.lds_sets ? (size_t)shape.lds_bytes : 0;
     if (dyn > 0) (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn);
     (void)hipGetLastError();
     void* args[] = {(void*)&slots, (void*)&a};
@@ -1054,13 +1162,13 @@ hipError_t launch_debug_path(const DevGraph& g, const DevSlots& slots, int32_t s
                              DebugOut* out, int32_t cap, const SamplerShape& shape, hipStream_t stream) {
     const void* fn = nullptr;
     switch (shape.block) {
-        case 128: fn = shape.lds_bitmaps ? (const void*)&debug_path_kernel<128, true> : (const void*)&debug_path_kernel<128, false>; break;
-        case 256: fn = shape.lds_bitmaps ? (const void*)&debug_path_kernel<256, true> : (const void*)&debug_path_kernel<256, false>; break;
-        case 512: fn = shape.lds_bitmaps ? (const void*)&debug_path_kernel<512, true> : (const void*)&debug_path_kernel<512, false>; break;
-        case 1024: fn = shape.lds_bitmaps ? (const void*)&debug_path_kernel<1024, true> : (const void*)&debug_path_kernel<1024, false>; break;
+        case 128: fn = shape.lds_sets ? (const void*)&debug_path_kernel<128, true> : (const void*)&debug_path_kernel<128, false>; break;
+        case 256: fn = shape.lds_sets ? (const void*)&debug_path_kernel<256, true> : (const void*)&debug_path_kernel<256, false>; break;
+        case 512: fn = shape.lds_sets ? (const void*)&debug_path_kernel<512, true> : (const void*)&debug_path_kernel<512, false>; break;
+        case 1024: fn = shape.lds_sets ? (const void*)&debug_path_kernel<1024, true> : (const void*)&debug_path_kernel<1024, false>; break;
         default: return hipErrorInvalidValue;
     }
-    const size_t dyn = shape.lds_bitmaps ? (size_t)shape.lds_bytes : 0;
+    const size_t dyn = shape.lds_sets ? (size_t)shape.lds_bytes : 0;
     if (dyn > 0) (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn);
     (void)hipGetLastError();
     void* args[] = {(void*)&g, (void*)&slots, (void*)&s, (void*)&t, (void*)&r, (void*)&out, (void*)&cap};

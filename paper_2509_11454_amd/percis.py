@@ -32,7 +32,7 @@ class Stats(C.Structure):
                 ("edges", C.c_uint64), ("sigma_adds", C.c_uint64), ("vertices_expanded", C.c_uint64),
                 ("vertices_discovered", C.c_uint64), ("kernel_ms", C.c_double), ("phase_ms", C.c_double * 5)]
 
-    PHASES = ("pair", "bfs", "dag", "walk", "clear")
+    PHASES = ("start", "bfs", "dag", "walk", "clear")
 
     def to_dict(self):
         d = {}
