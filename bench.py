@@ -197,6 +197,8 @@ def main():
                    "threads_per_sample": block, "visited_sets": bitmaps},
         "gteps": totals["edges"] / elapsed / 1e9,
         "edges_per_sample": totals["edges"] / (samples * args.steps),
+        "per_sample": {key: totals[key] / (samples * args.steps)
+                       for key in ("sigma_adds", "vertices_expanded", "vertices_discovered", "sum_I")},
         "reachable_fraction": totals["reachable"] / (samples * args.steps),
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,

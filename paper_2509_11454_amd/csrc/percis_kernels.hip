@@ -38,13 +38,16 @@
 
 namespace percis {
 
-constexpr int CH = 256;  // capacity of the LDS chunk arrays
+constexpr int CH = 128;  // capacity of the LDS chunk arrays
 // Frontier nodes staged per chunk: one per thread, at most CH.
 template <int BSZ>
 constexpr int chunk_len() { return BSZ < CH ? BSZ : CH; }
 constexpr uint32_t LVMASK = 0x0FFFFFFFu;
 constexpr uint32_t OVFBIT = 0x40000000u;
-constexpr int UNROLL = 8;
+#ifndef PERCIS_UNROLL
+#define PERCIS_UNROLL 8
+#endif
+constexpr int UNROLL = PERCIS_UNROLL;  // adjacency entries per thread per batch
 constexpr int WALK_UNROLL = 4;  // in-row chunks of 64 loaded together by the walk
 
 // Slot scratch is private to one workgroup (one CU), so every access to it is
@@ -986,8 +989,21 @@ __device__ __forceinline__ Vis<LDS> slot_vis(const DevSlots& sl, int slot) {
     return v;
 }
 
+// Occupancy target of the sampler (waves per SIMD), a build knob (0 = the
+// compiler's choice, 4 at about 124 registers): the sampler is latency-bound,
+// and 6 waves (80 registers, a few spilled) keeps more samples in flight.
+// Measured on R-MAT 18: 4 waves 26.4M, 5 waves 29.1M, 6 waves 29.5M samples/s.
+#ifndef PERCIS_SAMPLER_WAVES_PER_EU
+#define PERCIS_SAMPLER_WAVES_PER_EU 6
+#endif
+#if PERCIS_SAMPLER_WAVES_PER_EU > 0
+#define SAMPLER_OCCUPANCY __attribute__((amdgpu_waves_per_eu(PERCIS_SAMPLER_WAVES_PER_EU)))
+#else
+#define SAMPLER_OCCUPANCY
+#endif
+
 template <int BSZ, bool LDS>
-__global__ __launch_bounds__(BSZ) void sampler_kernel(DevSlots sl, SampleLaunch L) {
+__global__ __launch_bounds__(BSZ) SAMPLER_OCCUPANCY void sampler_kernel(DevSlots sl, SampleLaunch L) {
     static_assert(BSZ >= 128, "wave 1 draws the next pair");
     __shared__ SampleShared sh;
     const int tid = threadIdx.x;
