@@ -301,6 +301,7 @@ static void free_slots(percis_ctx* c) {
 constexpr int64_t kSlotBytesPerNode = (int64_t)sizeof(NodeRec) + 4 + 4 + 4 + 4;
 constexpr int64_t kLdsPerCu = 160 * 1024;
 constexpr int64_t kBitmapPlanes = 2;  // s-side and t-side visited
+constexpr int64_t kArcsPerSlot = 4096;  // DAG arcs a sample may record for its walk
 
 static int64_t bitmap_words(int64_t act) { return ((std::max<int64_t>(act, 1) + 31) / 32 + 63) / 64 * 64; }
 
@@ -352,7 +353,8 @@ static int ensure_slots(percis_ctx* c, int64_t act) {
     if (rc) return rc;
     const int64_t stride = (act + 63) / 64 * 64;
     const int64_t words = bitmap_words(act);
-    const int64_t per_slot = stride * kSlotBytesPerNode + 8 + kBitmapPlanes * words * 4;  // device bitmaps (spill space in LDS mode)
+    const int64_t per_slot = stride * kSlotBytesPerNode + 8 + kBitmapPlanes * words * 4  // device bitmaps (spill space in LDS mode)
+                             + kArcsPerSlot * (int64_t)sizeof(DagArc);
     size_t free_b = 0, total_b = 0;
     HIPCHK(c, hipMemGetInfo(&free_b, &total_b));
     const int64_t budget = c->opt_scratch_mb > 0 ? c->opt_scratch_mb * (1ll << 20) : (int64_t)(free_b * 0.6);
@@ -381,7 +383,9 @@ static int ensure_slots(percis_ctx* c, int64_t act) {
     s.q_t = (int32_t*)p; p += cnt * 4;
     s.q_d = (int32_t*)p; p += cnt * 4;
     s.tls = (int32_t*)p; p += ns * (stride + 2) * 4;
-    s.bm = (uint32_t*)p;
+    s.bm = (uint32_t*)p; p += ns * kBitmapPlanes * words * 4;
+    s.arcs = (DagArc*)p;
+    s.acap = (int32_t)kArcsPerSlot;
     c->slot_mem = mem;
     c->slots = s;
     c->nslots = (int)ns;

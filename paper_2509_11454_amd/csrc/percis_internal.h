@@ -44,7 +44,14 @@ struct NodeRec {
     uint64_t pad;
 };
 
-// Per-slot scratch; every array is [slots][stride] (stride >= n_act) and is
+// One arc u -> v of a sample's shortest-path DAG with the count sigma_s(u)
+// that weighs u among v's predecessors in the canonical walk.
+struct DagArc {
+    int32_t tail, head;
+    uint64_t w;
+};
+
+// Per-slot scratch; the node arrays are [slots][stride] (stride >= n_act) and
 // all-zero between samples (each sample clears what it touched).
 struct DevSlots {
     NodeRec* rec;     // per-node records
@@ -53,8 +60,10 @@ struct DevSlots {
     int32_t* q_d;     // meeting layer
     int32_t* tls;     // [slots][stride + 2] start of each t-level in q_t
     int64_t stride;   // elements per slot
-    uint32_t* bm;     // visited bitmaps when they do not live in LDS: [slots][3][words]
+    uint32_t* bm;     // visited bitmaps (device mode, or a spilled side in LDS mode): [slots][2][words]
     int64_t words;    // 32-bit words per bitmap
+    DagArc* arcs;     // [slots][acap] arcs of the sample's shortest-path DAG, for the walk
+    int32_t acap;     // arcs per slot
 };
 
 // Device-side accumulators of one sampling call.
@@ -97,9 +106,9 @@ struct DebugOut {
 };
 
 // Launch shape of the sampler: threads per workgroup and whether the
-// visited bitmaps live in LDS.
+// visited sets are LDS tables (else device bitmaps).
 struct SamplerShape {
-    int block;        // 256, 512 or 1024
+    int block;        // 128, 256, 512 or 1024
     bool lds_sets;
     int64_t lds_bytes;  // dynamic LDS per workgroup (the visited-set tables) when lds_sets
 };

@@ -48,7 +48,9 @@ constexpr uint32_t OVFBIT = 0x40000000u;
 #define PERCIS_UNROLL 8
 #endif
 constexpr int UNROLL = PERCIS_UNROLL;  // adjacency entries per thread per batch
-constexpr int WALK_UNROLL = 4;  // in-row chunks of 64 loaded together by the walk
+constexpr int WALK_UNROLL = 4;  // in-row chunks of 64 loaded together by the walk's row scan
+constexpr int ARC_UNROLL = 4;   // DAG-arc chunks of 64 loaded together by the walk
+constexpr int KCAP = 64;        // predecessors a walk step gathers from the arc list
 
 // Slot scratch is private to one workgroup (one CU), so every access to it is
 // a workgroup-scope atomic: coherent among the workgroup's waves without the
@@ -242,6 +244,9 @@ struct SampleShared {
     int32_t tail, tail_s, tail_t;
     int32_t nmeet;
     int32_t level_meets;  // the level being built has an arc into the other ball
+    int32_t narcs;        // DAG arcs recorded by this sample (may exceed the slot's capacity)
+    int32_t wk_u[KCAP];   // predecessors of the walk's current node, and their sigma_s
+    uint64_t wk_w[KCAP];
     int32_t level_table;  // the level being built decides first visits by its side's table
     int32_t hcnt[2];      // entries reserved in each side's table
     int32_t spilled[2];   // the side's visited set lives in its device bitmap
@@ -266,6 +271,14 @@ template <bool LDS>
 __device__ __forceinline__ bool member(const Vis<LDS>& V, const SampleShared& sh, int side, int32_t x) {
     if (!LDS || sh.spilled[side]) return Bits::test(Bits::rd(V.bm[side], x), x);
     return table_has(V.tab[side], x);
+}
+
+// Records the DAG arc tail -> head weighed by sigma_s(tail) = w; arcs past the
+// slot's capacity are dropped (the walk then scans in-rows instead).
+__device__ __forceinline__ void record_arc(DagArc* arcs, int32_t acap, SampleShared& sh, int32_t tail, int32_t head,
+                                           uint64_t w) {
+    const int i = atomicAdd(&sh.narcs, 1);
+    if (i < acap) arcs[i] = DagArc{tail, head, w};
 }
 
 // Thread 0 only.
@@ -403,6 +416,7 @@ __device__ void expand_bfs(const DevGraph& g, const DevSlots& sl, int64_t so, co
     using B = Bits;
     const int tid = threadIdx.x;
     const bool by_table = LDS && sh.level_table;   // else: bitmap (device mode) or record CAS (LDS mode)
+    DagArc* arcs = sl.arcs + (int64_t)blockIdx.x * sl.acap;
     const int32_t* rp = SIDE ? g.irp : g.rp;
     const int32_t* col = SIDE ? g.icol : g.col;
     int32_t* q = (SIDE ? sl.q_t : sl.q_s) + so;
@@ -494,6 +508,7 @@ __device__ void expand_bfs(const DevGraph& g, const DevSlots& sl, int64_t so, co
                     wrap |= nm < mass ? 1u : 0u;
                     mass = nm;
                     cn.A++;
+                    if (SIDE == 0) record_arc(arcs, sl.acap, sh, sh.node[j], x, addv);
                 }
                 if (SIDE == 1 && ((into_other >> k) & 1u)) {
                     // x is a meeting node (s-level a) and the frontier node, at
@@ -502,6 +517,7 @@ __device__ void expand_bfs(const DevGraph& g, const DevSlots& sl, int64_t so, co
                     // at hand
                     const uint64_t ss = ld64(&R[x].sg_s);
                     (void)add64(&R[sh.node[j]].sg_s, ss);
+                    record_arc(arcs, sl.acap, sh, x, sh.node[j], ss);
                     cn.A++;
                 }
                 if (fresh) {
@@ -539,6 +555,7 @@ __device__ void pull_level(const DevGraph& g, const DevSlots& sl, int64_t so, co
     const int tid = threadIdx.x;
     int32_t* q = sl.q_t + so;
     NodeRec* R = sl.rec + so;
+    DagArc* arcs = sl.arcs + (int64_t)blockIdx.x * sl.acap;
     constexpr int CHK = chunk_len<BSZ>();
     for (int base = lo; base < hi; base += CHK) {
         const int cnt = min(CHK, hi - base);
@@ -570,6 +587,7 @@ __device__ void pull_level(const DevGraph& g, const DevSlots& sl, int64_t so, co
             const uint64_t su = ((uint64_t)rec.w << 32) | rec.z;
             if (su) {
                 (void)add64(&R[(int32_t)sh.sig[j]].sg_s, su);
+                record_arc(arcs, sl.acap, sh, u, (int32_t)sh.sig[j], su);
                 cn.A++;
             }
         }
@@ -587,6 +605,7 @@ __device__ void push_meeting(const DevGraph& g, const DevSlots& sl, int64_t so, 
     const int tid = threadIdx.x;
     NodeRec* R = sl.rec + so;
     int32_t* qd = sl.q_d + so;
+    DagArc* arcs = sl.arcs + (int64_t)blockIdx.x * sl.acap;
     constexpr int CHK = chunk_len<BSZ>();
     for (int base = 0; base < nmeet; base += CHK) {
         const int cnt = min(CHK, nmeet - base);
@@ -598,6 +617,7 @@ __device__ void push_meeting(const DevGraph& g, const DevSlots& sl, int64_t so, 
             if (!member<LDS>(V, sh, 1, x)) continue;
             if ((ld32(&R[x].lv_t) & LVMASK) != want) continue;
             (void)add64(&R[x].sg_s, sh.sig[j]);
+            record_arc(arcs, sl.acap, sh, sh.node[j], x, sh.sig[j]);
             cn.A++;
         }
         if (base + CHK < nmeet) __syncthreads();
@@ -707,6 +727,7 @@ __device__ void run_sample(const DevGraph& g, const DevSlots& sl, int64_t so, co
             sh.s = s;
             sh.t = t;
             sh.nmeet = 0; sh.ovf = 0; sh.walk_err = 0; sh.sigma = 0;
+            sh.narcs = 0;
             sh.a = 0; sh.b = 0;
             sh.hcnt[0] = sh.hcnt[1] = 0;
             sh.spilled[0] = sh.spilled[1] = 0;
@@ -839,63 +860,114 @@ __device__ void run_sample(const DevGraph& g, const DevSlots& sl, int64_t so, co
         phase_mark(2);
 
         // ---- canonical backward walk by wave 0
+        // The predecessors of the current node w are the DAG arcs into w that
+        // the search recorded (each with sigma_s of its tail); the walk takes
+        // the one of smallest id whose cumulative sigma_s, in id order, exceeds
+        // r. Without a complete arc list (or with more than KCAP
+        // predecessors) a step scans w's in-row instead: the same choice.
         if (!sh.ovf && wid == 0) {
             const int32_t aM = sh.a;
             uint64_t r = dbg ? dbg_r : draw_bounded(T.seed, T.phase, idx, 2, sh.sigma);
+            const int32_t na = __builtin_amdgcn_readfirstlane(sh.narcs);
+            const bool by_arcs = na <= sl.acap;
+            const DagArc* arcs = sl.arcs + (int64_t)blockIdx.x * sl.acap;
+            const unsigned long long below = (1ull << lane) - 1;  // lanes under this one
             int32_t w = sh.t;
-            int32_t beg = g.irp[w], end = g.irp[w + 1];
             int err = 0;
             for (int32_t p = L - 1; p >= 1; p--) {
-                // predecessors of w on the DAG: s-level p, or (past the
-                // meeting layer) t-level L - p; their sigma_s weighs them
                 const bool on_s = p <= aM;
-                const uint32_t want = on_s ? (uint32_t)p + 1 : (uint32_t)(L - p) + 1;
-                int32_t sel = -1, nbeg = 0, nend = 0;
-                for (int32_t base = beg; base < end && sel < 0; base += 64 * WALK_UNROLL) {
-                    int32_t u[WALK_UNROLL], rb[WALK_UNROLL], re[WALK_UNROLL];
-                    uint64_t wt[WALK_UNROLL];
+                int32_t sel = -1;
+                int kc = KCAP + 1;
+                if (by_arcs) {
+                    kc = 0;
+                    for (int base = 0; base < na; base += 64 * ARC_UNROLL) {
+                        DagArc a[ARC_UNROLL];
+                        bool m[ARC_UNROLL];
 #pragma unroll
-                    for (int k = 0; k < WALK_UNROLL; k++) {
-                        const int32_t i = base + k * 64 + lane;
-                        u[k] = i < end ? g.icol[i] : -1;
-                    }
-                    // the in-row bounds of every candidate are loaded with its
-                    // record, so the next step can start as soon as one is chosen
-#pragma unroll
-                    for (int k = 0; k < WALK_UNROLL; k++) {
-                        wt[k] = 0;
-                        rb[k] = 0;
-                        re[k] = 0;
-                        if (u[k] >= 0 && member<LDS>(V, sh, on_s ? 0 : 1, u[k])) {
-                            const uint4 rec = *reinterpret_cast<const uint4*>(&R[u[k]]);
-                            rb[k] = g.irp[u[k]];
-                            re[k] = g.irp[u[k] + 1];
-                            const uint32_t lv = on_s ? rec.x : rec.y;
-                            if ((lv & LVMASK) == want) wt[k] = ((uint64_t)rec.w << 32) | rec.z;
+                        for (int k = 0; k < ARC_UNROLL; k++) {
+                            const int i = base + k * 64 + lane;
+                            m[k] = false;
+                            if (i < na) {
+                                a[k] = arcs[i];
+                                m[k] = a[k].head == w;
+                            }
                         }
-                        if (u[k] >= 0) cn.E++;
-                    }
 #pragma unroll
-                    for (int k = 0; k < WALK_UNROLL; k++) {
-                        if (sel >= 0) continue;
-                        const uint64_t incl = wave_incl_scan_u64(wt[k]);
-                        const uint64_t tot = lane_u64(incl, 63);
-                        if (r < tot) {
-                            const unsigned long long m = __ballot(incl > r);
-                            const int l = __ffsll((long long)m) - 1;
-                            r -= lane_u64(incl - wt[k], l);
-                            sel = lane_i32(u[k], l);
-                            nbeg = lane_i32(rb[k], l);
-                            nend = lane_i32(re[k], l);
-                        } else {
-                            r -= tot;
+                        for (int k = 0; k < ARC_UNROLL; k++) {
+                            const unsigned long long bal = __ballot(m[k]);
+                            const int pos = kc + __popcll(bal & below);
+                            if (m[k] && pos < KCAP) {
+                                sh.wk_u[pos] = a[k].tail;
+                                sh.wk_w[pos] = a[k].w;
+                            }
+                            kc += __popcll(bal);
+                        }
+                    }
+                    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+                    if (kc <= KCAP) {
+                        int32_t ui = INT32_MAX;
+                        uint64_t wi = 0, ci = 0;  // weight, cumulative weight up to and with ui
+                        if (lane < kc) {
+                            ui = sh.wk_u[lane];
+                            wi = sh.wk_w[lane];
+                        }
+                        for (int j = 0; j < kc; j++)
+                            if (sh.wk_u[j] <= ui) ci += sh.wk_w[j];
+                        const bool cand = lane < kc && ci > r;
+                        int32_t best = cand ? ui : INT32_MAX;
+#pragma unroll
+                        for (int o = 32; o > 0; o >>= 1) best = min(best, __shfl_xor(best, o, 64));
+                        best = __builtin_amdgcn_readfirstlane(best);
+                        if (best != INT32_MAX) {
+                            const unsigned long long hit = __ballot(cand && ui == best);
+                            const int l = __ffsll((long long)hit) - 1;
+                            r -= lane_u64(ci, l) - lane_u64(wi, l);
+                            sel = best;
+                        }
+                    }
+                    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+                }
+                if (kc > KCAP) {
+                    // in-row scan: in-neighbours one level closer to s (s-level p,
+                    // or t-level L - p past the meeting layer), weighed by sigma_s
+                    const uint32_t want = on_s ? (uint32_t)p + 1 : (uint32_t)(L - p) + 1;
+                    const int32_t beg = lane_i32(g.irp[w], 0), end = lane_i32(g.irp[w + 1], 0);
+                    for (int32_t base = beg; base < end && sel < 0; base += 64 * WALK_UNROLL) {
+                        int32_t u[WALK_UNROLL];
+                        uint64_t wt[WALK_UNROLL];
+#pragma unroll
+                        for (int k = 0; k < WALK_UNROLL; k++) {
+                            const int32_t i = base + k * 64 + lane;
+                            u[k] = i < end ? g.icol[i] : -1;
+                        }
+#pragma unroll
+                        for (int k = 0; k < WALK_UNROLL; k++) {
+                            wt[k] = 0;
+                            if (u[k] >= 0 && member<LDS>(V, sh, on_s ? 0 : 1, u[k])) {
+                                const uint4 rec = *reinterpret_cast<const uint4*>(&R[u[k]]);
+                                const uint32_t lv = on_s ? rec.x : rec.y;
+                                if ((lv & LVMASK) == want) wt[k] = ((uint64_t)rec.w << 32) | rec.z;
+                            }
+                            if (u[k] >= 0) cn.E++;
+                        }
+#pragma unroll
+                        for (int k = 0; k < WALK_UNROLL; k++) {
+                            if (sel >= 0) continue;
+                            const uint64_t incl = wave_incl_scan_u64(wt[k]);
+                            const uint64_t tot = lane_u64(incl, 63);
+                            if (r < tot) {
+                                const unsigned long long m = __ballot(incl > r);
+                                const int l = __ffsll((long long)m) - 1;
+                                r -= lane_u64(incl - wt[k], l);
+                                sel = lane_i32(u[k], l);
+                            } else {
+                                r -= tot;
+                            }
                         }
                     }
                 }
                 if (sel < 0) { err = 1; break; }
                 w = sel;
-                beg = nbeg;
-                end = nend;
                 if (lane == 0) {
                     if (dbg) {
                         if (p < dbg_cap) dbg->path[p] = w;

@@ -79,6 +79,41 @@ def test_debug_path_sigma_extremes():
     c.close()
 
 
+def test_walk_many_predecessors_and_arc_overflow():
+    """Nodes with more than 64 DAG predecessors, and searches that record more
+    DAG arcs than a slot keeps, make the walk scan in-rows instead of the arc
+    list; the paths still equal the oracle's."""
+    from paper_2509_11454_amd import percis as P
+    for g in [W.layered_graph([1, 100, 100, 1]), W.layered_graph([1, 3, 70, 2, 1]),
+              W.layered_graph([1, 90, 60, 1], directed=True), W.layered_graph([1, 65, 1])]:
+        c = P.Context(0)
+        c.load_csr(g.n, g.row_ptr, g.col, directed=g.directed)
+        og = O.Graph(g.n, g.row_ptr, g.col, g.directed)
+        s, t = 0, g.n - 1
+        L0, sig0, _ = O.path(og, s, t, 0)
+        assert L0 > 0
+        for r in sorted({0, 1, sig0 // 3, sig0 // 2, sig0 - 2, sig0 - 1}):
+            L, sig, ovf, p = c.debug_path(s, t, r)
+            assert (L, sig, ovf) == (L0, sig0, 0), g.name
+            assert p == O.path(og, s, t, r)[2], (g.name, r)
+        c.close()
+
+
+@pytest.mark.parametrize("sizes,directed", [([1, 3, 70, 2, 1], False), ([5, 40, 80, 40, 5], False),
+                                             ([2, 90, 60, 3], True)])
+def test_layered_sampling_parity(sizes, directed):
+    """Sampling on layered graphs (walk steps over many predecessors, DAGs
+    with more arcs than a slot records): bit-identical to the oracle."""
+    g = W.layered_graph(sizes, directed=directed)
+    k = W.uniform_states(g.n, np.random.default_rng(len(sizes)))
+    og, st = oracle_objects(g, k)
+    ho, so = oracle_hits(og, st, 0, 3000, 21)
+    c = gpu_context(g, k)
+    hg, sg = gpu_hits(c, 0, 3000, 21)
+    assert np.array_equal(ho, hg)
+    same_stats(so, sg)
+
+
 def test_er1000_parity():
     """ER G(1000, 5000), uniform states, 10^4 samples, seed 1: bit-identical."""
     g, k = W.workload_er1000()

@@ -179,6 +179,20 @@ def diamond_chain(k):
     return from_edge_list(k + 1 + 2 * k, e, name="diamonds%d" % k)
 
 
+def layered_graph(sizes, directed=False):
+    """Layers of the given sizes, consecutive layers completely joined (arcs
+    from each layer to the next if directed); ids layer by layer. Between the
+    first node and the last, sigma is the product of the inner layer sizes."""
+    starts = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    e = []
+    for i in range(len(sizes) - 1):
+        for u in range(starts[i], starts[i + 1]):
+            for v in range(starts[i + 1], starts[i + 2]):
+                e.append((u, v))
+    return from_edge_list(int(starts[-1]), e, directed=directed,
+                          name="layers%s%s" % ("-".join(map(str, sizes)), "d" if directed else ""))
+
+
 def complete_bipartite(a, b):
     return from_edge_list(a + b, [(i, a + j) for i in range(a) for j in range(b)], name="K%d,%d" % (a, b))
 
