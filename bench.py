@@ -157,6 +157,7 @@ def main():
     totals = dict(edges=0, sigma_adds=0, vertices_expanded=0, vertices_discovered=0, sum_I=0, reachable=0)
     phases = {}
     kernel_ms = []
+    pair_ms = []
     t_start = time.perf_counter()
     for i in range(args.steps):
         _, st = c.sample_range(0, samples, args.seed, 0, hits=hits)
@@ -165,7 +166,9 @@ def main():
         for key, v in st["phase_ms"].items():
             phases[key] = phases.get(key, 0.0) + v
         kernel_ms.append(st["kernel_ms"])
-        print("[bench] step %d: kernel %.1f ms" % (i, st["kernel_ms"]), file=sys.stderr, flush=True)
+        pair_ms.append(st["pair_ms"])
+        print("[bench] step %d: sampler %.1f ms, pairs %.2f ms" % (i, st["kernel_ms"], st["pair_ms"]),
+              file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
 
@@ -203,6 +206,7 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "sampler_kernel", "kernel_ms": avg_kernel_s * 1e3,
+                     "pair_kernel_ms": sum(pair_ms) / len(pair_ms),
                      "algorithmic_bytes_per_launch": b_alg},
         "hbm_gbs_measured": (traffic / avg_kernel_s / 1e9) if traffic else None,
     }

@@ -75,13 +75,13 @@ typedef struct {
     uint64_t sigma_adds;
     uint64_t vertices_expanded;
     uint64_t vertices_discovered;
-    double   kernel_ms;         /* device time of the sampling kernel */
+    double   kernel_ms;         /* device time of the sampling kernel (searches and walks) */
     /* Time spent per sample phase, summed over the concurrently running
      * samples (slot-milliseconds): starting the two balls, the bidirectional
      * BFS, the meeting layer and the sigma_s sweep, the path walk (during
-     * which one wave claims the next sample and draws its pair, Algorithm 2),
-     * and clearing the slot. */
+     * which one wave claims the next sample), and clearing the slot. */
     double   phase_ms[5];
+    double   pair_ms;           /* device time of the pair kernel (Algorithm 2 draws) */
 } percis_stats;
 
 /* Result summary of percis_estimate (Algorithm 1). */

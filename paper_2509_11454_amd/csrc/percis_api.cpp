@@ -302,6 +302,7 @@ constexpr int64_t kSlotBytesPerNode = (int64_t)sizeof(NodeRec) + 4 + 4 + 4 + 4;
 constexpr int64_t kLdsPerCu = 160 * 1024;
 constexpr int64_t kBitmapPlanes = 2;  // s-side and t-side visited
 constexpr int64_t kArcsPerSlot = 4096;  // DAG arcs a sample may record for its walk
+constexpr uint64_t kPairChunk = 1ull << 22;  // samples per pair-kernel chunk (16 bytes each listed)
 
 static int64_t bitmap_words(int64_t act) { return ((std::max<int64_t>(act, 1) + 31) / 32 + 63) / 64 * 64; }
 
@@ -560,23 +561,51 @@ int run_tasks(percis_ctx* c, const std::vector<TaskSpec>& tasks, std::vector<per
     HIPCHK(c, hipMemcpyAsync(c->d_tasks, ht.data(), sizeof(DevTask) * nt, hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, launch_clear_tasks(c->d_tasks, nt, max_n, c->stream));
     HIPCHK(c, launch_init_stats(c->d_stats, c->d_work, c->stream));
+    // The launch runs in chunks of at most kPairChunk samples: the pair kernel
+    // draws a chunk's pairs and lists those that need a search, then the
+    // sampler works through the list.
+    const uint64_t chunk = std::max<uint64_t>(1, std::min<uint64_t>(total, kPairChunk));
+    if (chunk > c->pair_cap) {
+        if (c->stream) HIPCHK(c, hipStreamSynchronize(c->stream));
+        if ((rc = dalloc(c, c->d_pairs, (size_t)chunk))) return rc;
+        c->pair_cap = chunk;
+    }
+    const size_t nchunks = (size_t)((total + chunk - 1) / chunk);
+    while (c->chunk_ev.size() < 3 * nchunks) {
+        hipEvent_t e;
+        HIPCHK(c, hipEventCreate(&e));
+        c->chunk_ev.push_back(e);
+    }
     SampleLaunch a{};
     a.tasks = c->d_tasks;
     a.ntasks = nt;
-    a.total = total;
+    a.pairs = c->d_pairs;
     a.work = c->d_work;
+    a.npairs = c->d_work + 1;
     a.stats = c->d_stats;
-    a.slots = (int)std::min<uint64_t>((uint64_t)c->nslots, std::max<uint64_t>(total, 1));
-    HIPCHK(c, hipEventRecord(c->ev0, c->stream));
-    HIPCHK(c, launch_sampler(c->slots, a, c->shape, c->stream));
-    HIPCHK(c, hipEventRecord(c->ev1, c->stream));
+    a.slots = (int)std::min<uint64_t>((uint64_t)c->nslots, chunk);
+    for (size_t i = 0; i < nchunks; i++) {
+        a.base = (uint64_t)i * chunk;
+        a.count = std::min<uint64_t>(chunk, total - a.base);
+        HIPCHK(c, hipEventRecord(c->chunk_ev[3 * i], c->stream));
+        HIPCHK(c, launch_pairs(a, c->stream));
+        HIPCHK(c, hipEventRecord(c->chunk_ev[3 * i + 1], c->stream));
+        HIPCHK(c, launch_sampler(c->slots, a, c->shape, c->stream));
+        HIPCHK(c, hipEventRecord(c->chunk_ev[3 * i + 2], c->stream));
+    }
     std::vector<DevStats> hts(nt);
     DevStats hl{};
     HIPCHK(c, hipMemcpyAsync(hts.data(), c->d_task_stats, sizeof(DevStats) * nt, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipMemcpyAsync(&hl, c->d_stats, sizeof hl, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    float ms = 0.f;
-    HIPCHK(c, hipEventElapsedTime(&ms, c->ev0, c->ev1));
+    double ms = 0.0, pair_ms = 0.0;
+    for (size_t i = 0; i < nchunks; i++) {
+        float a_ms = 0.f, b_ms = 0.f;
+        HIPCHK(c, hipEventElapsedTime(&a_ms, c->chunk_ev[3 * i], c->chunk_ev[3 * i + 1]));
+        HIPCHK(c, hipEventElapsedTime(&b_ms, c->chunk_ev[3 * i + 1], c->chunk_ev[3 * i + 2]));
+        pair_ms += a_ms;
+        ms += b_ms;
+    }
     percis_stats agg{};
     agg.first_overflow = ~0ull;
     if (out) out->resize(nt);
@@ -584,6 +613,7 @@ int run_tasks(percis_ctx* c, const std::vector<TaskSpec>& tasks, std::vector<per
         percis_stats st;
         stats_from_dev(hts[i], &st);
         st.kernel_ms = ms;
+        st.pair_ms = pair_ms;
         if (out) (*out)[i] = st;
         if (st.samples != tasks[i].count)
             return fail(c, PERCIS_E_DEVICE, "task %d: sampler processed %llu of %llu samples", i,
@@ -600,6 +630,7 @@ int run_tasks(percis_ctx* c, const std::vector<TaskSpec>& tasks, std::vector<per
     agg.vertices_expanded = hl.vexp;
     agg.vertices_discovered = hl.vdisc;
     agg.kernel_ms = ms;
+    agg.pair_ms = pair_ms;
     for (int i = 0; i < 5; i++) agg.phase_ms[i] = c->wall_hz > 0 ? (double)hl.phase_ticks[i] / c->wall_hz * 1e3 : 0.0;
     if (launch) *launch = agg;
     if (agg.overflow)
@@ -730,7 +761,7 @@ int percis_create(int device, void* hip_stream, percis_ctx** out) {
         if (hipDeviceGetAttribute(&wall_khz, hipDeviceAttributeWallClockRate, device) == hipSuccess)
             c->wall_hz = wall_khz * 1e3;
         if (hipMalloc((void**)&c->d_stats, sizeof(DevStats)) != hipSuccess ||
-            hipMalloc((void**)&c->d_work, sizeof(unsigned long long)) != hipSuccess ||
+            hipMalloc((void**)&c->d_work, 2 * sizeof(unsigned long long)) != hipSuccess ||
             hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess) {
             percis_destroy(c);
             return PERCIS_E_DEVICE;
@@ -761,6 +792,9 @@ void percis_destroy(percis_ctx* c) {
     free_slots(c);
     dfree(c->d_stats);
     dfree(c->d_work);
+    dfree(c->d_pairs);
+    for (hipEvent_t e : c->chunk_ev) (void)hipEventDestroy(e);
+    c->chunk_ev.clear();
     dfree(c->d_dbg);
     dfree(c->d_tasks);
     dfree(c->d_task_stats);

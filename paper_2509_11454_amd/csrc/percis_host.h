@@ -68,7 +68,10 @@ struct percis_ctx {
     percis::SamplerShape shape{};
 
     percis::DevStats* d_stats = nullptr;   // launch-wide counters
-    unsigned long long* d_work = nullptr;
+    unsigned long long* d_work = nullptr;  // [2]: next list entry (or source), listed pairs
+    percis::PairRec* d_pairs = nullptr;    // pair list of one chunk
+    uint64_t pair_cap = 0;
+    std::vector<hipEvent_t> chunk_ev;      // 3 per chunk: pairs, sampler, end
     percis::DevTask* d_tasks = nullptr;
     percis::DevStats* d_task_stats = nullptr;
     int task_cap = 0;

@@ -88,13 +88,26 @@ struct DevTask {
     uint32_t pad;
 };
 
+// A sample whose pair needs a search: its launch index (minus the chunk's
+// first), its pair (internal ids) and its task.
+struct PairRec {
+    uint32_t q;
+    int32_t s, t, task;
+};
+
+// One chunk of a launch: launch indices base .. base+count-1. The pair kernel
+// draws every pair of the chunk, counts the samples whose pair has an end
+// without arcs (unreachable) and lists the others in pairs[0 .. *npairs);
+// the sampler then claims list entries through *work.
 struct SampleLaunch {
     const DevTask* tasks;            // device array
     int ntasks;
-    unsigned long long total;        // sum of the tasks' counts
-    unsigned long long* work;        // next unclaimed launch index
+    unsigned long long base, count;  // the chunk
+    PairRec* pairs;                  // [count] capacity
+    unsigned long long* npairs;      // entries listed (written by the pair kernel)
+    unsigned long long* work;        // next unclaimed list entry
     DevStats* stats;                 // launch-wide work counters and phase times
-    int slots;                       // grid size
+    int slots;                       // sampler grid size
 };
 
 // Debug request: one (s, t, r) path; output written to `out`.
@@ -118,6 +131,8 @@ hipError_t launch_fill_u8(void* p, int64_t bytes, hipStream_t stream);
 hipError_t launch_init_stats(DevStats* st, unsigned long long* work, hipStream_t stream);
 // Zeroes every task's statistics and, where asked, its hits (one launch).
 hipError_t launch_clear_tasks(const DevTask* tasks, int ntasks, int64_t max_n, hipStream_t stream);
+// Zeroes *work and *npairs, then draws the chunk's pairs (one lane per sample).
+hipError_t launch_pairs(const SampleLaunch& a, hipStream_t stream);
 hipError_t launch_sampler(const DevSlots& slots, const SampleLaunch& a, const SamplerShape& shape,
                           hipStream_t stream);
 hipError_t launch_debug_path(const DevGraph& g, const DevSlots& slots, int32_t s, int32_t t, uint64_t r,

@@ -187,42 +187,14 @@ __device__ uint64_t draw_bounded(uint64_t seed, uint64_t phase, uint64_t idx, ui
 }
 
 // Smallest d in [lo, hi] with pred(d), for a monotone pred with pred(hi)
-// true; one wave probes 64 points per step. Wave-uniform arguments.
+// true (one lane).
 template <class Pred>
-__device__ __forceinline__ int32_t wave_search(int32_t lo, int32_t hi, Pred pred) {
-    const int lane = threadIdx.x & 63;
-    while (hi - lo + 1 > 64) {
-        const int64_t len = (int64_t)hi - lo + 1;
-        const int32_t x = lo + (int32_t)(((int64_t)(lane + 1) * len) >> 6) - 1;
-        const unsigned long long m = __ballot(pred(x));
-        const int i = __ffsll((long long)m) - 1;
-        const int32_t nhi = lane_i32(x, i);
-        const int32_t prev = lane_i32(x, i > 0 ? i - 1 : 0);
-        lo = i > 0 ? prev + 1 : lo;
-        hi = nhi;
+__device__ __forceinline__ int32_t lane_search(int32_t lo, int32_t hi, Pred pred) {
+    while (lo < hi) {
+        const int32_t mid = lo + ((hi - lo) >> 1);
+        if (pred(mid)) hi = mid; else lo = mid + 1;
     }
-    const int32_t x = lo + lane;
-    const bool p = (x > hi) || pred(x);
-    const unsigned long long m = __ballot(p);
-    return lo + __ffsll((long long)m) - 1;
-}
-
-// The pair of sample idx (ranks drawn by Algorithm 2, returned as internal
-// ids). Called by one whole wave.
-__device__ __forceinline__ void draw_pair(const DevCdf& cdf, uint64_t seed, uint64_t phase, uint64_t idx,
-                                          int32_t& s, int32_t& t) {
-    const uint64_t Us = draw_bounded(seed, phase, idx, 0, cdf.C);
-    const uint64_t* P = cdf.P;
-    const int32_t sr = wave_search(1, cdf.n, [&](int32_t d) { return Us < P[d]; });
-    const uint64_t cs = P[sr] - P[sr - 1];
-    const uint64_t Ut = draw_bounded(seed, phase, idx, 1, cs);
-    const uint64_t ks = cdf.kr[sr], Ws = cdf.W[sr];
-    const uint64_t* W = cdf.W;
-    const int32_t tr = wave_search(sr + 1, cdf.n, [&](int32_t d) {
-        return Ut < (uint64_t)(d - sr + 1) * ks - (Ws - W[d + 1]);
-    });
-    s = cdf.perm[sr];
-    t = cdf.perm[tr];
+    return lo;
 }
 
 // ------------------------------------------------------------ workgroup state
@@ -258,7 +230,7 @@ struct SampleShared {
     uint64_t sigma;
     // the next sample, claimed and drawn by one wave ahead of time
     unsigned long long nx_idx;
-    int32_t nx_task, nx_s, nx_t;
+    int32_t nx_ok, nx_task, nx_s, nx_t;
     unsigned long long phase_ticks[5];  // start, BFS, meeting + DAG, walk (+ next pair), clearing
     // per-sample statistics of one task, summed here by thread 0 and added to
     // the task's counters when the workgroup moves to another task
@@ -652,45 +624,23 @@ __device__ __attribute__((noinline)) unsigned long long wave_fetch_add(unsigned 
     return lane_u64(old, 0);
 }
 
-// Claims launch indices and draws their pairs until one needs a search, and
-// leaves it in sh.nx_* (or an index past the end). A pair with an end that
-// has no arcs is unreachable and is only counted. Called by one whole wave.
-// No instruction inside the loop depends on the lane (every steering value
-// is wave-uniform), so the loop cannot be split between lanes.
-__device__ void claim_next(const SampleLaunch& L, SampleShared& sh) {
+// Claims the next listed sample into sh.nx_* (sh.nx_ok = 0 past the end of
+// the list). Called by one whole wave; no instruction depends on the lane
+// except inside the out-of-line claim.
+__device__ void claim_next(const SampleLaunch& L, unsigned long long npairs, SampleShared& sh) {
     const int lane = threadIdx.x & 63;
-    unsigned long long q, triv = 0;
-    int task = 0, triv_task = -1;
-    int32_t s = 0, t = 0;
-    for (;;) {
-        q = wave_fetch_add(L.work, 1ull);
-        if (q >= L.total) break;
-        // the task holding launch index q: last task with offset <= q
-        int lo = 0, hi = L.ntasks - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (lane_u64(L.tasks[mid].offset, 0) <= q) lo = mid; else hi = mid - 1;
-        }
-        task = lo;
-        const DevTask& T = L.tasks[task];
-        draw_pair(T.cdf, T.seed, T.phase, T.first + (q - T.offset), s, t);
-        s = __builtin_amdgcn_readfirstlane(s);
-        t = __builtin_amdgcn_readfirstlane(t);
-        const int32_t n_act = __builtin_amdgcn_readfirstlane(T.g.n_act);
-        if (s < n_act && t < n_act) break;
-        if (task != triv_task) {
-            if (triv_task >= 0 && triv) (void)wave_fetch_add(&L.tasks[triv_task].stats->samples, triv);
-            triv_task = task;
-            triv = 0;
-        }
-        triv++;
+    const unsigned long long q = wave_fetch_add(L.work, 1ull);
+    if (q >= npairs) {
+        if (lane == 0) sh.nx_ok = 0;
+        return;
     }
-    if (triv_task >= 0 && triv) (void)wave_fetch_add(&L.tasks[triv_task].stats->samples, triv);
+    const PairRec rec = L.pairs[q];
     if (lane == 0) {
-        sh.nx_idx = q;
-        sh.nx_task = task;
-        sh.nx_s = s;
-        sh.nx_t = t;
+        sh.nx_ok = 1;
+        sh.nx_idx = L.base + rec.q;
+        sh.nx_task = rec.task;
+        sh.nx_s = rec.s;
+        sh.nx_t = rec.t;
     }
 }
 
@@ -700,7 +650,8 @@ __device__ void claim_next(const SampleLaunch& L, SampleShared& sh) {
 // are not touched and the path is written to dbg (internal ids).
 template <int BSZ, bool LDS>
 __device__ void run_sample(const DevGraph& g, const DevSlots& sl, int64_t so, const Vis<LDS>& V, uint64_t idx,
-                           const DevTask& T, int32_t s, int32_t t, const SampleLaunch* next, SampleShared& sh,
+                           const DevTask& T, int32_t s, int32_t t, const SampleLaunch* next,
+                           unsigned long long npairs, SampleShared& sh,
                            Counters& cn, DebugOut* dbg, uint64_t dbg_r, int32_t dbg_cap) {
     using B = Bits;
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
@@ -981,7 +932,7 @@ __device__ void run_sample(const DevGraph& g, const DevSlots& sl, int64_t so, co
         }
     }
     // ---- the next sample's pair, by wave 1 while wave 0 walks
-    if (next && wid == 1) claim_next(*next, sh);
+    if (next && wid == 1) claim_next(*next, npairs, sh);
     __syncthreads();
     phase_mark(3);
 
@@ -1076,7 +1027,7 @@ __device__ __forceinline__ Vis<LDS> slot_vis(const DevSlots& sl, int slot) {
 
 template <int BSZ, bool LDS>
 __global__ __launch_bounds__(BSZ) SAMPLER_OCCUPANCY void sampler_kernel(DevSlots sl, SampleLaunch L) {
-    static_assert(BSZ >= 128, "wave 1 draws the next pair");
+    static_assert(BSZ >= 128, "wave 1 claims the next sample");
     __shared__ SampleShared sh;
     const int tid = threadIdx.x;
     const int64_t so = (int64_t)blockIdx.x * sl.stride;
@@ -1091,13 +1042,14 @@ __global__ __launch_bounds__(BSZ) SAMPLER_OCCUPANCY void sampler_kernel(DevSlots
         flush_task_stats(sh, L);
     }
     __syncthreads();
-    if (tid < 64) claim_next(L, sh);
+    const unsigned long long npairs = lane_u64(*L.npairs, 0);
+    if (tid < 64) claim_next(L, npairs, sh);
     __syncthreads();
     // Every thread reads the claimed sample here; wave 1 claims the next one
     // only after run_sample's first barrier, and run_sample ends on a barrier.
     for (;;) {
+        if (!sh.nx_ok) break;
         const unsigned long long q = sh.nx_idx;
-        if (q >= L.total) break;
         const int k = __builtin_amdgcn_readfirstlane(sh.nx_task);
         const int32_t s = __builtin_amdgcn_readfirstlane(sh.nx_s), t = __builtin_amdgcn_readfirstlane(sh.nx_t);
         const DevTask& T = L.tasks[k];
@@ -1105,7 +1057,7 @@ __global__ __launch_bounds__(BSZ) SAMPLER_OCCUPANCY void sampler_kernel(DevSlots
             flush_task_stats(sh, L);
             sh.acc_task = k;
         }
-        run_sample<BSZ, LDS>(T.g, sl, so, V, T.first + (q - T.offset), T, s, t, &L, sh, cn, nullptr, 0, 0);
+        run_sample<BSZ, LDS>(T.g, sl, so, V, T.first + (q - T.offset), T, s, t, &L, npairs, sh, cn, nullptr, 0, 0);
     }
     flush_counters(cn, L.stats);
     if (tid == 0) {
@@ -1128,7 +1080,7 @@ __global__ __launch_bounds__(BSZ) void debug_path_kernel(DevGraph g, DevSlots sl
     }
     __syncthreads();
     DevTask T = {};
-    run_sample<BSZ, LDS>(g, sl, 0, V, 0, T, s, t, nullptr, sh, cn, out, r, cap);
+    run_sample<BSZ, LDS>(g, sl, 0, V, 0, T, s, t, nullptr, 0, sh, cn, out, r, cap);
 }
 
 __global__ void fill_u32_kernel(uint32_t* p, uint32_t v, int64_t count) {
@@ -1144,6 +1096,65 @@ __global__ void fill_u8_kernel(uint8_t* p, int64_t bytes) {
     for (int64_t i = words * 16 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < bytes;
          i += (int64_t)gridDim.x * blockDim.x)
         p[i] = 0;
+}
+
+// The pairs of one chunk of a launch, one lane per sample (Algorithm 2: U_s
+// picks rank s by the prefix sums P, U_t picks rank t > s by F_s, both
+// searches binary). Pairs with an end without arcs are counted as samples of
+// their task (unreachable); the others are listed for the sampler.
+__global__ __launch_bounds__(256) void pair_kernel(SampleLaunch L) {
+    const int lane = threadIdx.x & 63;
+    const unsigned long long below = (1ull << lane) - 1;
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    const int64_t count = (int64_t)L.count;
+    for (int64_t b = wave * 64; b < count; b += nwaves * 64) {
+        const int64_t qi = b + lane;
+        int32_t k = 0, s = 0, t = 0;
+        bool listed = false, trivial = false;
+        if (qi < count) {
+            const unsigned long long q = L.base + (unsigned long long)qi;
+            // the task holding launch index q: last task with offset <= q
+            int lo = 0, hi = L.ntasks - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (L.tasks[mid].offset <= q) lo = mid; else hi = mid - 1;
+            }
+            k = lo;
+            const DevTask& T = L.tasks[k];
+            const DevCdf& cdf = T.cdf;
+            const uint64_t idx = T.first + (q - T.offset);
+            const uint64_t Us = draw_bounded(T.seed, T.phase, idx, 0, cdf.C);
+            const int32_t sr = lane_search(1, cdf.n, [&](int32_t d) { return Us < cdf.P[d]; });
+            const uint64_t cs = cdf.P[sr] - cdf.P[sr - 1];
+            const uint64_t Ut = draw_bounded(T.seed, T.phase, idx, 1, cs);
+            const uint64_t ks = cdf.kr[sr], Ws = cdf.W[sr];
+            const int32_t tr = lane_search(sr + 1, cdf.n, [&](int32_t d) {
+                return Ut < (uint64_t)(d - sr + 1) * ks - (Ws - cdf.W[d + 1]);
+            });
+            s = cdf.perm[sr];
+            t = cdf.perm[tr];
+            trivial = s >= T.g.n_act || t >= T.g.n_act;
+            listed = !trivial;
+        }
+        const unsigned long long lst = __ballot(listed);
+        if (lst) {
+            const unsigned long long at = wave_fetch_add(L.npairs, (unsigned long long)__popcll(lst));
+            if (listed) L.pairs[at + __popcll(lst & below)] = PairRec{(uint32_t)qi, s, t, k};
+        }
+        // lane 0 is always in range here; its task takes one add per wave
+        const int k0 = __builtin_amdgcn_readfirstlane(k);
+        const unsigned long long same = __ballot(trivial && k == k0);
+        if (same) (void)wave_fetch_add(&L.tasks[k0].stats->samples, (unsigned long long)__popcll(same));
+        if (trivial && k != k0) atomicAdd(&L.tasks[k].stats->samples, 1ull);
+    }
+}
+
+__global__ void init_chunk_kernel(unsigned long long* work, unsigned long long* npairs) {
+    if (threadIdx.x == 0) {
+        *work = 0;
+        *npairs = 0;
+    }
 }
 
 __global__ void init_stats_kernel(DevStats* st, unsigned long long* work) {
@@ -1192,6 +1203,16 @@ hipError_t launch_fill_u8(void* p, int64_t bytes, hipStream_t stream) {
     return hipGetLastError();
 }
 
+hipError_t launch_pairs(const SampleLaunch& a, hipStream_t stream) {
+    hipLaunchKernelGGL(init_chunk_kernel, dim3(1), dim3(64), 0, stream, a.work, a.npairs);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || a.count == 0) return e;
+    int64_t blocks = ((int64_t)a.count + 255) / 256;
+    blocks = blocks < 1 ? 1 : (blocks > 8192 ? 8192 : blocks);
+    hipLaunchKernelGGL(pair_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, a);
+    return hipGetLastError();
+}
+
 hipError_t launch_init_stats(DevStats* st, unsigned long long* work, hipStream_t stream) {
     hipLaunchKernelGGL(init_stats_kernel, dim3(1), dim3(64), 0, stream, st, work);
     return hipGetLastError();
@@ -1236,7 +1257,7 @@ int sampler_occupancy(const SamplerShape& s) {
 
 hipError_t launch_sampler(const DevSlots& slots, const SampleLaunch& a, const SamplerShape& shape,
                           hipStream_t stream) {
-    if (a.total == 0 || a.slots <= 0) return hipSuccess;
+    if (a.count == 0 || a.slots <= 0) return hipSuccess;
     const void* fn = pick_sampler(shape);
     if (!fn) return hipErrorInvalidValue;
     const size_t dyn = shape.lds_sets ? (size_t)shape.lds_bytes : 0;

@@ -205,7 +205,7 @@ int percis_server_step(percis_server* s, int32_t* completed) {
     rc = run_tasks(c, tasks, &ts, &launch);
     if (rc != PERCIS_OK && rc != PERCIS_E_SIGMA_OVERFLOW) return rc;
     s->samples_done += launch.samples;
-    s->kernel_ms += launch.kernel_ms;
+    s->kernel_ms += launch.kernel_ms + launch.pair_ms;
 
     int32_t done = 0;
     for (size_t i = 0; i < owners.size(); i++) {
