@@ -246,6 +246,8 @@ def main():
         threads = min(16, os.cpu_count() or 1)
         out["cpu_baseline"] = cpu_baseline(g, k, args.seed, args.cpu_seconds, threads)
         out["cpu_baseline"]["host"] = host_cpu_model()
+        one = cpu_baseline(g, k, args.seed, min(4.0, args.cpu_seconds / 4), 1)
+        out["cpu_baseline"]["one_thread"] = {"value": one["value"], "sample": one["sample"]}
         print("[bench] cpu baseline: %.1f samples/s" % out["cpu_baseline"]["value"], file=sys.stderr, flush=True)
 
     print(json.dumps(out), flush=True)

@@ -194,6 +194,14 @@ int percis_sample_tasks(percis_ctx* ctx, int32_t ntasks, const percis_task* task
 /* Algorithm 1 on graph `graph` (percis_estimate is this with graph 0). */
 int percis_graph_estimate(percis_ctx* ctx, int32_t graph, double eps, double delta, uint64_t seed, double* p_out,
                           percis_estimate_info* info);
+
+/* PercIS-DI, the data-independent variant of Section IV (sample size bound
+ * experiment): no first phase; rho_hat = D (the vertex-diameter bound) and
+ * v_hat = d_hat^2 / 4 (its largest possible value) in Theorem 1's sample size
+ * (Alg. 1's constants), then l samples of stream phase 2 and
+ * p_out[v] = d_v h_v / l as in percis_estimate. info->l1 = 0. */
+int percis_graph_estimate_di(percis_ctx* ctx, int32_t graph, double eps, double delta, uint64_t seed,
+                             double* p_out, percis_estimate_info* info);
 int percis_graph_set_vertex_diameter(percis_ctx* ctx, int32_t graph, int64_t D);
 
 /* Overrides VertexDiamUB with a caller-known bound D >= the maximum number of

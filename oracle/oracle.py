@@ -74,6 +74,7 @@ def _load():
         "orc_vertex_diam_ub": (i64, [P]),
         "orc_sample_size": (C.c_double, [C.c_double] * 5 + [P]),
         "orc_estimate": (C.c_int, [P, P, C.c_double, C.c_double, u64, i64, P, P]),
+        "orc_estimate_di": (C.c_int, [P, P, C.c_double, C.c_double, u64, i64, P, P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -212,4 +213,13 @@ def estimate(g, st, eps, delta, seed, D=-1):
     p = np.zeros(g.n, np.float64)
     info = _EstInfo()
     rc = int(_load().orc_estimate(g._h, st._h, eps, delta, seed, D, _ptr(p), C.byref(info)))
+    return rc, p, info.to_dict()
+
+
+def estimate_di(g, st, eps, delta, seed, D=-1):
+    """PercIS-DI (no first phase, rho_hat = D, v_hat = d_hat^2/4). Returns
+    (status, p[n], info dict)."""
+    p = np.zeros(g.n, np.float64)
+    info = _EstInfo()
+    rc = int(_load().orc_estimate_di(g._h, st._h, eps, delta, seed, D, _ptr(p), C.byref(info)))
     return rc, p, info.to_dict()

@@ -32,6 +32,9 @@
  *   orc_estimate        Algorithm 1 (PercIS): two sampling phases and the bounds
  *                       of Proposition 2 (rho-hat), Proposition 3 (v-hat) and
  *                       Theorem 1 (sample size), with the constants of Alg. 1.
+ *   orc_estimate_di     PercIS-DI (Section IV, sample size bound experiment):
+ *                       Algorithm 1 without its first phase, with rho-hat = D
+ *                       and v-hat = d-hat^2 / 4 in Theorem 1's sample size.
  *
  * Parity status: every function above is pinned by a CPU test (brute force on
  * tiny graphs, closed forms, an independent Philox implementation, exhaustive
@@ -644,5 +647,32 @@ int orc_estimate(const orc_graph* g, const orc_states* st, double eps, double de
     I.overflow = S1.overflow + S2.overflow;
     if (info) *info = I;
     free(p1); free(Is); free(Is2);
+    return I.overflow ? -2 : 0;
+}
+
+/* PercIS-DI: the data-independent variant the paper compares its bound with.
+ * There is no first phase; the vertex-diameter bound D stands for rho-hat and
+ * the largest possible value d-hat^2 / 4 for v-hat (so x-hat = d-hat / 2);
+ * the l samples of phase 2 give p as in Algorithm 1. */
+int orc_estimate_di(const orc_graph* g, const orc_states* st, double eps, double delta, uint64_t seed,
+                    int64_t D, double* p_out, orc_estimate_info* info)
+{
+    orc_estimate_info I; memset(&I, 0, sizeof I);
+    if (st->C == 0) return -1;
+    int32_t n = g->n;
+    I.D = D >= 0 ? D : orc_vertex_diam_ub(g);
+    double d_hat = 1.0;
+    for (int32_t v = 0; v < n; v++)
+        if (st->S[v] > 0 && (double)st->C / st->S[v] > d_hat) d_hat = (double)st->C / st->S[v];
+    I.d_hat = d_hat;
+    I.rho_hat = (double)I.D;
+    I.v_hat = d_hat * d_hat / 4.0;
+    I.l = (uint64_t)ceil(orc_sample_size(d_hat, I.rho_hat, I.v_hat, eps, delta, &I.x_hat));
+    orc_stats S2;
+    int32_t* Is2 = (int32_t*)malloc(sizeof(int32_t) * (size_t)(I.l > 0 ? I.l : 1));
+    phase_estimate(g, st, I.l, seed, 2, p_out, &S2, Is2);
+    I.overflow = S2.overflow;
+    if (info) *info = I;
+    free(Is2);
     return I.overflow ? -2 : 0;
 }

@@ -645,8 +645,10 @@ GraphData* get_graph(percis_ctx* c, int32_t id) {
 }
 
 // Algorithm 1 on graph `id`: D, phase 1, the bounds, phase 2, the estimate.
+// Algorithm 1 (di = false), or PercIS-DI (di = true: no phase 1, rho_hat = D,
+// v_hat = d_hat^2 / 4).
 static int estimate_graph(percis_ctx* c, int32_t id, double eps, double delta, uint64_t seed, double* p_out,
-                          percis_estimate_info* info) {
+                          percis_estimate_info* info, bool di = false) {
     GraphData* G = get_graph(c, id);
     if (!G) return fail(c, PERCIS_E_INVAL, "no graph %d", id);
     if (!G->has_graph || !G->has_states) return fail(c, PERCIS_E_STATE, "load a graph and set states first");
@@ -659,25 +661,33 @@ static int estimate_graph(percis_ctx* c, int32_t id, double eps, double delta, u
     const int32_t n = G->n;
     I.D = G->D_override >= 0 ? G->D_override : vertex_diam_ub(*G);
     I.d_hat = G->d_hat;
-    I.l1 = (uint64_t)std::ceil(std::max(1000.0, std::log(1.0 / delta) / eps));
     std::vector<uint32_t> h(n);
-
-    std::vector<percis_stats> ts;
     std::vector<TaskSpec> one(1);
-    one[0] = TaskSpec{id, 1, 0, I.l1, seed, G->d_hits, false};
     percis_stats s1{};
-    rc = run_tasks(c, one, &ts, &s1);
-    if (rc != PERCIS_OK) {
-        I.overflow = s1.overflow;
-        if (info) *info = I;
-        return rc;
+    if (di) {
+        I.rho_hat = (double)I.D;
+        I.v_hat = I.d_hat * I.d_hat / 4.0;
+        auto tb = std::chrono::steady_clock::now();
+        const double lb = sample_size_sup(I.d_hat, I.rho_hat, I.v_hat, eps, delta, &I.x_hat);
+        I.l = lb < 4294967295.0 ? (uint64_t)std::ceil(lb) : ~0ull;
+        I.bounds_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - tb).count();
+    } else {
+        I.l1 = (uint64_t)std::ceil(std::max(1000.0, std::log(1.0 / delta) / eps));
+        std::vector<percis_stats> ts;
+        one[0] = TaskSpec{id, 1, 0, I.l1, seed, G->d_hits, false};
+        rc = run_tasks(c, one, &ts, &s1);
+        if (rc != PERCIS_OK) {
+            I.overflow = s1.overflow;
+            if (info) *info = I;
+            return rc;
+        }
+        HIPCHK(c, hipMemcpy(h.data(), G->d_hits, sizeof(uint32_t) * n, hipMemcpyDeviceToHost));
+        I.phase1_ms = s1.kernel_ms;
+        auto tb = std::chrono::steady_clock::now();
+        bounds_from_phase1(*G, I.l1, ts[0].sum_I, ts[0].sum_I2, h.data(), eps, delta, &I);
+        auto te = std::chrono::steady_clock::now();
+        I.bounds_ms = std::chrono::duration<double, std::milli>(te - tb).count();
     }
-    HIPCHK(c, hipMemcpy(h.data(), G->d_hits, sizeof(uint32_t) * n, hipMemcpyDeviceToHost));
-    I.phase1_ms = s1.kernel_ms;
-    auto tb = std::chrono::steady_clock::now();
-    bounds_from_phase1(*G, I.l1, ts[0].sum_I, ts[0].sum_I2, h.data(), eps, delta, &I);
-    auto te = std::chrono::steady_clock::now();
-    I.bounds_ms = std::chrono::duration<double, std::milli>(te - tb).count();
     if (I.l >= 4294967295ull) {
         if (info) *info = I;
         return fail(c, PERCIS_E_TOO_LARGE, "phase-2 sample size exceeds 2^32 - 1");
@@ -931,6 +941,12 @@ int percis_graph_set_vertex_diameter(percis_ctx* c, int32_t graph, int64_t D) {
 int percis_estimate(percis_ctx* c, double eps, double delta, uint64_t seed, double* p_out, percis_estimate_info* info) {
     if (!c) return PERCIS_E_INVAL;
     return estimate_graph(c, 0, eps, delta, seed, p_out, info);
+}
+
+int percis_graph_estimate_di(percis_ctx* c, int32_t graph, double eps, double delta, uint64_t seed, double* p_out,
+                             percis_estimate_info* info) {
+    if (!c) return PERCIS_E_INVAL;
+    return estimate_graph(c, graph, eps, delta, seed, p_out, info, true);
 }
 
 int percis_graph_estimate(percis_ctx* c, int32_t graph, double eps, double delta, uint64_t seed, double* p_out,

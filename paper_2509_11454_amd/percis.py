@@ -90,6 +90,8 @@ _SIGS = {
     "percis_sample_tasks": (C.c_int, [_P, C.c_int32, C.POINTER(Task), C.POINTER(Stats)]),
     "percis_graph_estimate": (C.c_int, [_P, C.c_int32, C.c_double, C.c_double, C.c_uint64, _P,
                                         C.POINTER(EstimateInfo)]),
+    "percis_graph_estimate_di": (C.c_int, [_P, C.c_int32, C.c_double, C.c_double, C.c_uint64, _P,
+                                           C.POINTER(EstimateInfo)]),
     "percis_graph_set_vertex_diameter": (C.c_int, [_P, C.c_int32, C.c_int64]),
     "percis_autotune": (C.c_int, [_P, C.c_int32, C.c_uint64, C.c_uint64, C.POINTER(Tuning)]),
     "percis_server_create": (C.c_int, [_P, C.c_int64, C.c_uint64, C.c_uint64, C.POINTER(_P)]),
@@ -270,6 +272,15 @@ class Context:
         info = EstimateInfo()
         self._check(_lib.percis_graph_estimate(self._h, int(graph), float(eps), float(delta), int(seed), _np_ptr(p),
                                                C.byref(info)))
+        return p, info.to_dict()
+
+    def graph_estimate_di(self, graph, eps, delta, seed):
+        """PercIS-DI on graph `graph` (no first phase; data-independent bound)."""
+        n = self.graph_info(graph)[0]
+        p = np.zeros(n, np.float64)
+        info = EstimateInfo()
+        self._check(_lib.percis_graph_estimate_di(self._h, int(graph), float(eps), float(delta), int(seed),
+                                                  _np_ptr(p), C.byref(info)))
         return p, info.to_dict()
 
     def graph_set_vertex_diameter(self, graph, D):

@@ -171,6 +171,25 @@ def test_rmat18_shapes_agree():
         c.close()
 
 
+@pytest.mark.timeout(900)
+def test_rmat24_directed_window_parity():
+    """The largest workload, directed R-MAT 24 with Beta(1/2, 1/2) states:
+    hits and statistics of the sample window [10^6, 10^6 + 192) are
+    bit-identical to the oracle's. The oracle does about 8 samples/s on 16
+    threads at this size, so a window stands in for a full run."""
+    g, k = W.workload_rmat24_directed()
+    og, st = oracle_objects(g, k)
+    first, count = 1_000_000, 192
+    ho, so = oracle_hits(og, st, first, count, 1)
+    assert so["reachable"] > 0
+    c = gpu_context(g, k)
+    hg, sg = gpu_hits(c, first, count, 1)
+    assert np.array_equal(ho, hg)
+    same_stats(so, sg)
+    c.close()
+    del og, st
+
+
 def test_ranges_add_up_and_accumulate():
     g, k = W.workload_er1000()
     c = gpu_context(g, k)
@@ -282,6 +301,32 @@ def test_estimate_parity():
             assert np.allclose(pg, po, rtol=1e-12, atol=1e-15)
         p_exact = O.exact(og, st)
         assert np.abs(pg - p_exact).max() <= eps
+
+
+def test_estimate_di_parity():
+    """PercIS-DI against the oracle: D and the data-independent rho_hat, v_hat,
+    x_hat agree (d_hat to 1e-12 relative), l up to the resolution of the two
+    supremum searches; the phase-2 hits of the oracle's l are bit-identical,
+    and with equal l so is the estimate (to the double formula's rounding)."""
+    g, k = W.workload_er1000()
+    og, st = oracle_objects(g, k)
+    c = gpu_context(g, k)
+    for eps, delta, seed in [(0.05, 0.1, 5), (0.1, 0.05, 6)]:
+        rc, po, io = O.estimate_di(og, st, eps, delta, seed)
+        assert rc == 0
+        pg, ig = c.graph_estimate_di(0, eps, delta, seed)
+        assert ig["l1"] == 0 and ig["D"] == io["D"] and ig["rho_hat"] == io["rho_hat"]
+        for key in ("d_hat", "v_hat", "x_hat"):
+            assert abs(ig[key] - io[key]) <= 1e-12 * max(1.0, abs(io[key])), key
+        assert abs(ig["l"] - io["l"]) <= 1 + 1e-6 * io["l"]
+        h2o, _ = O.sample_range(og, st, 0, io["l"], seed, 2)
+        h2g, _ = gpu_hits(c, 0, io["l"], seed, phase=2)
+        assert np.array_equal(h2o, h2g)
+        if ig["l"] == io["l"]:
+            assert np.allclose(pg, po, rtol=1e-12, atol=1e-15)
+        # the data-dependent bound is the smaller one
+        _, i2 = c.estimate(eps, delta, seed)
+        assert i2["l"] <= ig["l"]
 
 
 def test_device_pointer_inputs():

@@ -168,3 +168,32 @@ def test_eps_guarantee_ic_setting():
     rc, pe, info = O.estimate(og, st, 0.05, 0.1, 77)
     assert rc == 0
     assert np.abs(pe - p).max() <= 0.05
+
+
+def test_percis_di_bound_and_sampling():
+    """PercIS-DI (Section IV, sample size bound experiment): no first phase,
+    rho_hat = D and v_hat = d_hat^2/4, so x_hat = d_hat/2; its phase-2 hits
+    are the plain sampler's; its bound is at least PercIS's data-dependent
+    one (the paper finds it larger in every setting) and grows like
+    1/eps^2 (it is O(ln(D/delta)/eps^2))."""
+    rng = np.random.default_rng(12)
+    g = W.er_graph(120, 360, 12)
+    k = W.uniform_states(g.n, rng)
+    og, st = O.Graph(g.n, g.row_ptr, g.col), O.States(k)
+    rc, p_di, I = O.estimate_di(og, st, 0.1, 0.1, 31)
+    assert rc == 0 and I["l1"] == 0
+    D = O.vertex_diam_ub(og)
+    assert I["D"] == D and I["rho_hat"] == D
+    assert abs(I["v_hat"] - I["d_hat"] ** 2 / 4) < 1e-15
+    assert abs(I["x_hat"] - I["d_hat"] / 2) < 1e-15
+    want_l = math.ceil(O.sample_size(I["d_hat"], D, I["d_hat"] ** 2 / 4, 0.1, 0.1)[0])
+    assert I["l"] == want_l
+    # the estimate is phase 2 of the plain sampler, scaled by d_v / l
+    hits, _ = O.sample_range(og, st, 0, I["l"], 31, 2)
+    dv = np.array([float(x) for x in B.likelihood_ratios(k)])
+    assert np.allclose(p_di, dv * hits / I["l"], rtol=1e-15, atol=0)
+    # data-dependent bound no larger; 1/eps^2 growth
+    rc2, _, I2 = O.estimate(og, st, 0.1, 0.1, 31)
+    assert rc2 == 0 and I2["l"] <= I["l"]
+    l_half = O.sample_size(I["d_hat"], D, I["d_hat"] ** 2 / 4, 0.05, 0.1)[0]
+    assert 3.0 < l_half / want_l < 4.6
