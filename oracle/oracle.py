@@ -69,6 +69,8 @@ def _load():
         "orc_search_t": (None, [P, i32, u64, P]),
         "orc_draw_pair": (None, [P, u64, u64, u64, P, P, P, P]),
         "orc_path": (i32, [P, i32, i32, u64, P, i32, P, P]),
+        "orc_path128": (i32, [P, i32, i32, u64, u64, P, i32, P, P]),
+        "orc_bounded128_parts": (None, [u64, u64, u64, u64, u64, u64, P, P, P]),
         "orc_sample_range": (None, [P, P, u64, u64, u64, u64, P, P, P]),
         "orc_exact": (None, [P, P, P]),
         "orc_vertex_diam_ub": (i64, [P]),
@@ -167,16 +169,30 @@ def draw_pair(st, seed, phase, idx):
     return int(s.value), int(t.value), int(sr.value), int(tr.value)
 
 
+SIGMA_SATURATED = (1 << 128) - 1
+
+
 def path(g, s, t, r=0):
-    """Returns (L, sigma, path) with path = [s, ..., t] or None."""
+    """Returns (L, sigma, path) with path = [s, ..., t] or None; r and sigma
+    are Python ints (sigma saturates at 2^128 - 1, which means overflow)."""
     buf = np.zeros(g.n + 1, np.int32)
     lo, hi = C.c_uint64(0), C.c_uint64(0)
-    L = int(_load().orc_path(g._h, s, t, r, _ptr(buf), g.n + 1, C.byref(lo), C.byref(hi)))
+    L = int(_load().orc_path128(g._h, s, t, r & ((1 << 64) - 1), r >> 64, _ptr(buf), g.n + 1,
+                                C.byref(lo), C.byref(hi)))
     sigma = (int(hi.value) << 64) | int(lo.value)
     p = None
-    if L >= 0 and sigma < (1 << 64) and r < sigma:
+    if L >= 0 and sigma < SIGMA_SATURATED and r < sigma:
         p = [int(v) for v in buf[:L + 1]]
     return L, sigma, p
+
+
+def bounded128(seed, phase, idx, variate, N):
+    """Uniform integer in [0, N) for 2^64 <= N < 2^128 (Lemire at 128 bits);
+    returns (value, attempts)."""
+    lo, hi, used = C.c_uint64(0), C.c_uint64(0), C.c_uint64(0)
+    _load().orc_bounded128_parts(seed, phase, idx, variate, N & ((1 << 64) - 1), N >> 64,
+                                 C.byref(lo), C.byref(hi), C.byref(used))
+    return (int(hi.value) << 64) | int(lo.value), int(used.value)
 
 
 def sample_range(g, st, first, count, seed, phase=0, with_I=False):

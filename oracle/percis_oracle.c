@@ -22,6 +22,7 @@
  *   orc_path            RandomSP (Section III-B): BFS from s expanded until t is
  *                       found, shortest-path counts sigma (Section II-A), and one
  *                       shortest path chosen by the canonical backward walk.
+ *   orc_bounded128      Lemire's method at 128 bits, for r when sigma_st >= 2^64.
  *   orc_sample_range    The sampling loop of Algorithm 2 with RandomSP, reporting
  *                       per-node counts of internal-node hits (estimator of
  *                       Section III-A) and the |I(tau)| statistics used by Alg. 1.
@@ -299,6 +300,47 @@ void orc_draw_pair(const orc_states* st, uint64_t seed, uint64_t phase, uint64_t
     *t_node = st->perm[t];
 }
 
+/* Lemire's method at 128 bits, for ranges N >= 2^64: x = the low two words of
+ * the Philox block (word 0 low, word 1 high), m = x*N as 256 bits; the high
+ * 128 bits are the result unless the low 128 fall in [0, 2^128 mod N). */
+static void mul128(u128 a, u128 b, u128* hi, u128* lo)
+{
+    const u128 M = ((u128)1 << 64) - 1;
+    u128 a0 = a & M, a1 = a >> 64, b0 = b & M, b1 = b >> 64;
+    u128 p00 = a0 * b0, p01 = a0 * b1, p10 = a1 * b0, p11 = a1 * b1;
+    u128 mid = (p00 >> 64) + (p01 & M) + (p10 & M);
+    *lo = (p00 & M) | (mid << 64);
+    *hi = p11 + (p01 >> 64) + (p10 >> 64) + (mid >> 64);
+}
+
+u128 orc_bounded128(uint64_t seed, uint64_t phase, uint64_t idx, uint64_t variate, u128 N, uint64_t* attempts_used)
+{
+    for (uint64_t attempt = 0;; attempt++) {
+        uint64_t ctr[4] = { idx, variate, attempt, 0 };
+        uint64_t key[2] = { seed, phase };
+        uint64_t out[4];
+        orc_philox4x64_10(ctr, key, out);
+        u128 x = (u128)out[0] | ((u128)out[1] << 64);
+        u128 hi, lo;
+        mul128(x, N, &hi, &lo);
+        if (lo < N) {
+            u128 threshold = (u128)(0 - N) % N; /* 2^128 mod N */
+            if (lo < threshold) continue;
+        }
+        if (attempts_used) *attempts_used = attempt + 1;
+        return hi;
+    }
+}
+
+/* Python-facing form: N and the result as two 64-bit halves. */
+void orc_bounded128_parts(uint64_t seed, uint64_t phase, uint64_t idx, uint64_t variate, uint64_t n_lo,
+                          uint64_t n_hi, uint64_t* r_lo, uint64_t* r_hi, uint64_t* attempts_used)
+{
+    u128 r = orc_bounded128(seed, phase, idx, variate, (u128)n_lo | ((u128)n_hi << 64), attempts_used);
+    *r_lo = (uint64_t)r;
+    *r_hi = (uint64_t)(r >> 64);
+}
+
 /* ------------------------------------------------------------------------- */
 /* RandomSP: truncated BFS from s, shortest-path counts, canonical path.      */
 /* ------------------------------------------------------------------------- */
@@ -350,8 +392,9 @@ static int32_t truncated_bfs(const orc_graph* g, int32_t s, int32_t t, orc_work*
  * subtracting the sigma of every predecessor passed over. This maps
  * r in [0, sigma_st) one-to-one onto the shortest s-t paths, so a uniform r
  * gives a uniform path (Section III-A, distribution q). Writes the path
- * s = path[0], ..., path[L] = t. Requires sigma_st < 2^64. */
-static void canonical_walk(const orc_graph* g, int32_t t, int32_t L, uint64_t r, const orc_work* wk, int32_t* path)
+ * s = path[0], ..., path[L] = t. Requires sigma_st below the saturation value
+ * (every count on the walk is at most sigma_st, so none saturated). */
+static void canonical_walk(const orc_graph* g, int32_t t, int32_t L, u128 r, const orc_work* wk, int32_t* path)
 {
     int32_t w = t;
     path[L] = t;
@@ -360,7 +403,7 @@ static void canonical_walk(const orc_graph* g, int32_t t, int32_t L, uint64_t r,
         for (int64_t e = g->irp[w]; e < g->irp[w + 1]; e++) {
             int32_t u = g->icol[e];
             if (wk->dist[u] != pos - 1) continue;
-            uint64_t su = (uint64_t)wk->sigma[u];
+            u128 su = wk->sigma[u];
             if (r < su) { next = u; break; }
             r -= su;
         }
@@ -369,20 +412,37 @@ static void canonical_walk(const orc_graph* g, int32_t t, int32_t L, uint64_t r,
     }
 }
 
-/* One canonical path for (s, t, r); returns L = d(s,t), or -1 if t is not
- * reachable. sigma is returned as two 64-bit halves (saturated at 2^128-1).
- * The path is written only if sigma < 2^64, r < sigma and cap >= L+1. */
-int32_t orc_path(const orc_graph* g, int32_t s, int32_t t, uint64_t r, int32_t* path, int32_t cap,
-                 uint64_t* sigma_lo, uint64_t* sigma_hi)
+/* r for a reachable sample with sigma_st = sg (below saturation): the 64-bit
+ * draw of variate 2 when sigma_st < 2^64, else the 128-bit one. */
+static u128 draw_r(uint64_t seed, uint64_t phase, uint64_t idx, u128 sg)
+{
+    if ((sg >> 64) == 0) return orc_bounded(seed, phase, idx, 2, (uint64_t)sg, NULL);
+    return orc_bounded128(seed, phase, idx, 2, sg, NULL);
+}
+
+/* One canonical path for (s, t, r), r = r_lo + 2^64 r_hi; returns L = d(s,t),
+ * or -1 if t is not reachable. sigma is returned as two 64-bit halves
+ * (saturated at 2^128-1, which counts as overflow). The path is written only
+ * if sigma is below saturation, r < sigma and cap >= L+1. */
+int32_t orc_path128(const orc_graph* g, int32_t s, int32_t t, uint64_t r_lo, uint64_t r_hi, int32_t* path,
+                    int32_t cap, uint64_t* sigma_lo, uint64_t* sigma_hi)
 {
     orc_work* wk = work_new(g->n);
     int32_t L = truncated_bfs(g, s, t, wk);
     u128 sg = L >= 0 ? wk->sigma[t] : 0;
+    u128 r = (u128)r_lo | ((u128)r_hi << 64);
     if (sigma_lo) *sigma_lo = (uint64_t)sg;
     if (sigma_hi) *sigma_hi = (uint64_t)(sg >> 64);
-    if (L >= 0 && (sg >> 64) == 0 && r < (uint64_t)sg && cap >= L + 1) canonical_walk(g, t, L, r, wk, path);
+    if (L >= 0 && sg != ~(u128)0 && r < sg && cap >= L + 1) canonical_walk(g, t, L, r, wk, path);
     work_free(wk);
     return L;
+}
+
+/* orc_path128 with r < 2^64. */
+int32_t orc_path(const orc_graph* g, int32_t s, int32_t t, uint64_t r, int32_t* path, int32_t cap,
+                 uint64_t* sigma_lo, uint64_t* sigma_hi)
+{
+    return orc_path128(g, s, t, r, 0, path, cap, sigma_lo, sigma_hi);
 }
 
 typedef struct {
@@ -390,7 +450,7 @@ typedef struct {
     uint64_t reachable;        /* samples whose t is reachable from s */
     uint64_t sum_I;            /* sum of |I(tau)| over the samples */
     uint64_t sum_I2;           /* sum of |I(tau)|^2 */
-    uint64_t overflow;         /* samples with sigma_st >= 2^64 */
+    uint64_t overflow;         /* samples with sigma_st >= 2^128 - 1 (saturated) */
     uint64_t first_overflow;   /* smallest such sample index, or UINT64_MAX */
     uint64_t edges;            /* adjacency entries examined */
 } orc_stats;
@@ -398,7 +458,8 @@ typedef struct {
 /* Samples idx = first .. first+count-1 of stream (seed, phase). hits[v] is
  * incremented once for every sampled path that has v as an internal node.
  * If I_out is not NULL, I_out[idx-first] receives |I(tau)| of each sample.
- * A sample with sigma_st >= 2^64 adds no hits and is counted in overflow. */
+ * A sample whose sigma_st saturates (>= 2^128 - 1) adds no hits and is
+ * counted in overflow. */
 void orc_sample_range(const orc_graph* g, const orc_states* st, uint64_t first, uint64_t count,
                       uint64_t seed, uint64_t phase, uint32_t* hits, orc_stats* stats, int32_t* I_out)
 {
@@ -414,13 +475,12 @@ void orc_sample_range(const orc_graph* g, const orc_states* st, uint64_t first, 
         if (I_out) I_out[q] = 0;
         if (L < 0) continue;
         u128 sg = wk->sigma[t];
-        if ((sg >> 64) != 0) {
+        if (sg == ~(u128)0) {
             S.overflow++;
             if (idx < S.first_overflow) S.first_overflow = idx;
             continue;
         }
-        uint64_t r = orc_bounded(seed, phase, idx, 2, (uint64_t)sg, NULL);
-        canonical_walk(g, t, L, r, wk, path);
+        canonical_walk(g, t, L, draw_r(seed, phase, idx, sg), wk, path);
         for (int32_t i = 1; i < L; i++) hits[path[i]]++;
         uint64_t I = (uint64_t)(L - 1);
         S.reachable++;
@@ -575,9 +635,8 @@ static void phase_estimate(const orc_graph* g, const orc_states* st, uint64_t co
         int32_t L = truncated_bfs(g, s, t, wk);
         if (L < 0) continue;
         u128 sg = wk->sigma[t];
-        if ((sg >> 64) != 0) { S.overflow++; if (idx < S.first_overflow) S.first_overflow = idx; continue; }
-        uint64_t r = orc_bounded(seed, phase, idx, 2, (uint64_t)sg, NULL);
-        canonical_walk(g, t, L, r, wk, path);
+        if (sg == ~(u128)0) { S.overflow++; if (idx < S.first_overflow) S.first_overflow = idx; continue; }
+        canonical_walk(g, t, L, draw_r(seed, phase, idx, sg), wk, path);
         double R = (double)st->k[s] - (double)st->k[t];
         double kappa_tilde = R / (double)st->C;
         for (int32_t i = 1; i < L; i++) {

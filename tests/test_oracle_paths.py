@@ -47,22 +47,54 @@ def test_sigma_and_canonical_walk_vs_enumeration(gi):
 
 
 def test_grid_sigma_closed_form_and_overflow():
-    for a, b, want in GOLD["grid_sigma"]["cases"]:
+    """Corner-to-corner counts C(a+b-2, a-1), exact below 2^128 - 1 (a path is
+    given at both ends of r), saturated (overflow) beyond."""
+    cases = [(a, b, int(want)) for a, b, want in GOLD["grid_sigma"]["cases"]]
+    cases += [(66, 66, comb(130, 65)), (70, 70, comb(138, 69))]
+    for a, b, want in cases:
         g = W.grid_graph(a, b)
         og = O.Graph(g.n, g.row_ptr, g.col)
         L, sigma, p = O.path(og, 0, a * b - 1, 0)
         assert L == a + b - 2
-        assert sigma == comb(a + b - 2, a - 1) == int(want)
-        assert (p is not None) == (sigma < 2 ** 64)
+        assert want == comb(a + b - 2, a - 1)
+        if want < O.SIGMA_SATURATED:
+            assert sigma == want and p is not None
+            # walking back from t, r = 0 keeps the smallest-id predecessor
+            # (the node above), so the path runs along row 0 first; r = sigma - 1
+            # keeps the largest (the node to the left): down column 0 first
+            assert p[:b] == list(range(b))
+            q = O.path(og, 0, a * b - 1, want - 1)[2]
+            assert q[:a] == [i * b for i in range(a)]
+        else:
+            assert sigma == O.SIGMA_SATURATED and p is None
+
+
+def diamond_path(k, r):
+    """The canonical path of r in a chain of k diamonds: walking back from
+    h_k, bit i of r picks the second middle node of diamond i."""
+    out = [0]
+    for i in range(k):
+        out.append(k + 1 + 2 * i + ((r >> i) & 1))
+        out.append(i + 1)
+    return out
 
 
 def test_diamond_chain_sigma():
-    for k in GOLD["diamond_sigma"]["cases"]:
+    ks = list(GOLD["diamond_sigma"]["cases"]) + [100, 127, 128]
+    rng = np.random.default_rng(9)
+    for k in ks:
         g = W.diamond_chain(k)
         og = O.Graph(g.n, g.row_ptr, g.col)
-        L, sigma, p = O.path(og, 0, k, 2 ** 63 - 1 if k == 63 else 0)
-        assert L == 2 * k and sigma == 2 ** k
-        assert (p is not None) == (k < 64)
+        L, sigma, p = O.path(og, 0, k, 0)
+        assert L == 2 * k
+        if k < 128:
+            assert sigma == 2 ** k
+            rs = {0, 2 ** k - 1, 2 ** (k - 1)} | {int(rng.integers(0, 2 ** 62)) << max(0, k - 62) for _ in range(5)}
+            for r in rs:
+                r %= 2 ** k
+                assert O.path(og, 0, k, r)[2] == diamond_path(k, r), (k, r)
+        else:
+            assert sigma == O.SIGMA_SATURATED and p is None
 
 
 def test_simple_sigmas():

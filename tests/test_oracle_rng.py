@@ -2,6 +2,7 @@
 independent implementation, and the bounded draw against properties that
 a correct multiply-and-reject (Lemire 2019) must have."""
 import json
+import math
 import os
 
 import numpy as np
@@ -102,3 +103,40 @@ def test_bounded_is_high_word_of_product_when_accepted():
         if used == 1:
             x = O.word(9, 0, idx, 0, 0)
             assert v == (x * N) >> 64
+
+
+def test_bounded128_powers_of_two_and_range():
+    """Lemire at 128 bits: a power-of-two range never rejects and returns the
+    top bits of the 128-bit word (word 1 high, word 0 low); every value is
+    in range."""
+    for e in (64, 65, 100, 127):
+        N = 1 << e
+        for idx in range(20):
+            r, used = O.bounded128(3, 2, idx, 2, N)
+            x = (O.word(3, 2, idx, 2, 0) | (_word1(3, 2, idx, 2, 0) << 64))
+            assert used == 1 and r == x >> (128 - e)
+    for N in ((1 << 64) + 1, 3 << 100, (1 << 128) - 3):
+        for idx in range(200):
+            r, _ = O.bounded128(5, 1, idx, 2, N)
+            assert 0 <= r < N
+
+
+def test_bounded128_rejection_is_exact():
+    """N = floor(2^128 * 2/3) + 1: multiply-shift without rejection would make
+    even values twice as likely as odd ones (P(even) = 2/3); the rejection
+    zone is a third of the words, so the mean number of attempts is 1.5."""
+    N = (1 << 128) * 2 // 3 + 1
+    even, attempts, M = 0, 0, 4000
+    for idx in range(M):
+        r, used = O.bounded128(11, 0, idx, 2, N)
+        even += (r % 2 == 0)
+        attempts += used
+    p = even / M
+    assert abs(p - 0.5) < 4 * math.sqrt(0.25 / M)
+    assert abs(attempts / M - 1.5) < 0.08
+
+
+def _word1(seed, phase, idx, variate, attempt):
+    ctr = np.array([idx, variate, attempt, 0], dtype=np.uint64)
+    key = np.array([seed, phase], dtype=np.uint64)
+    return int(O.philox4x64_10(ctr, key)[1])
