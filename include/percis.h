@@ -49,7 +49,7 @@ extern "C" {
 #define PERCIS_E_DEVICE          -4  /* HIP runtime error */
 #define PERCIS_E_DEGENERATE      -5  /* all states equal: kappa~ undefined */
 #define PERCIS_E_TOO_LARGE       -6  /* n > 2^25, or 2^32 or more samples in one call */
-#define PERCIS_E_SIGMA_OVERFLOW  -7  /* a sampled pair has 2^64 or more shortest paths */
+#define PERCIS_E_SIGMA_OVERFLOW  -7  /* a sampled pair has 2^128 - 1 or more shortest paths */
 
 /* ---- flags ---- */
 #define PERCIS_DIRECTED     0x1u  /* load_csr: arcs are directed */
@@ -69,7 +69,7 @@ typedef struct {
     uint64_t reachable;
     uint64_t sum_I;
     uint64_t sum_I2;
-    uint64_t overflow;          /* samples with sigma_st >= 2^64 */
+    uint64_t overflow;          /* samples with sigma_st >= 2^128 - 1 (their counts saturate) */
     uint64_t first_overflow;    /* smallest such sample index, or UINT64_MAX */
     uint64_t edges;
     uint64_t sigma_adds;
@@ -137,8 +137,10 @@ int percis_set_states(percis_ctx* ctx, const uint16_t* k, uint32_t flags);
  * index ranges add up. The random stream is Philox4x64-10 with key
  * (seed, phase) and counter (sample index, variate, attempt, 0), so results do
  * not depend on launch configuration. Requires count < 2^32. Returns
- * PERCIS_E_SIGMA_OVERFLOW if any sampled pair has sigma_st >= 2^64 (such
- * samples add no hits; st reports the count and first index).
+ * PERCIS_E_SIGMA_OVERFLOW if any sampled pair has sigma_st >= 2^128 - 1
+ * (such samples add no hits; st reports the count and first index). Pairs
+ * with 2^64 <= sigma_st < 2^128 - 1 take a 128-bit path (r drawn at 128 bits,
+ * the same stream) and count like any other.
  * st may be NULL. flags: PERCIS_DEVICE_PTRS (hits is device memory),
  * PERCIS_ACCUMULATE. */
 int percis_sample_range(percis_ctx* ctx, uint64_t first, uint64_t count, uint64_t seed, uint32_t phase,
@@ -211,11 +213,20 @@ int percis_graph_set_vertex_diameter(percis_ctx* ctx, int32_t graph, int64_t D);
 int percis_set_vertex_diameter(percis_ctx* ctx, int64_t D);
 
 /* Test hook: runs RandomSP on the device for a given pair (s, t) and path
- * index r. Writes L = d(s,t) (-1 if unreachable) and sigma_st (saturated at
- * 2^64 - 1 when *overflow is set); if reachable, not overflowed, r < sigma_st
- * and cap >= L + 1, writes the path s, ..., t into path[] (host). */
+ * index r < 2^64, with 64-bit counts. Writes L = d(s,t) (-1 if unreachable)
+ * and sigma_st (2^64 - 1 with *overflow = 1 when sigma_st >= 2^64: then see
+ * percis_debug_path_wide); if reachable, not overflowed, r < sigma_st and
+ * cap >= L + 1, writes the path s, ..., t into path[] (host). */
 int percis_debug_path(percis_ctx* ctx, int32_t s, int32_t t, uint64_t r, int32_t* path, int32_t cap,
                       int32_t* L, uint64_t* sigma, int32_t* overflow);
+
+/* Test hook of the 128-bit path that sampling calls take for pairs with
+ * sigma_st >= 2^64: RandomSP for (s, t) and r = r_lo + 2^64 r_hi with exact
+ * 128-bit counts. Writes L (-1 if unreachable), sigma_st as two halves
+ * (2^128 - 1 and *overflow = 1 when it saturates) and, if reachable, not
+ * overflowed, r < sigma_st and cap >= L + 1, the path s, ..., t. */
+int percis_debug_path_wide(percis_ctx* ctx, int32_t s, int32_t t, uint64_t r_lo, uint64_t r_hi, int32_t* path,
+                           int32_t cap, int32_t* L, uint64_t* sigma_lo, uint64_t* sigma_hi, int32_t* overflow);
 
 /* Exact percolation centrality of graph `graph` (Definition 1, Eq. 1) on the
  * device, by Brandes-style dependency accumulation from every source (the

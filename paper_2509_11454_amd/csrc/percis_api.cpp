@@ -292,6 +292,10 @@ static DevCdf dev_cdf(const GraphData& G) {
 
 static void free_slots(percis_ctx* c) {
     if (c->slot_mem) (void)hipFree(c->slot_mem);
+    if (c->wide_mem) (void)hipFree(c->wide_mem);
+    c->wide_mem = nullptr;
+    c->wide_slots = 0;
+    c->wslots = WideSlots{};
     c->slot_mem = nullptr;
     c->nslots = 0;
     c->slot_act = 0;
@@ -303,6 +307,8 @@ constexpr int64_t kLdsPerCu = 160 * 1024;
 constexpr int64_t kBitmapPlanes = 2;  // s-side and t-side visited
 constexpr int64_t kArcsPerSlot = 4096;  // DAG arcs a sample may record for its walk
 constexpr uint64_t kPairChunk = 1ull << 22;  // samples per pair-kernel chunk (16 bytes each listed)
+constexpr int64_t kWideSlots = 16;           // workgroups of the 128-bit path
+constexpr int64_t kWideBytesPerNode = 4 + 16 + 4;
 
 static int64_t bitmap_words(int64_t act) { return ((std::max<int64_t>(act, 1) + 31) / 32 + 63) / 64 * 64; }
 
@@ -387,11 +393,41 @@ static int ensure_slots(percis_ctx* c, int64_t act) {
     s.bm = (uint32_t*)p; p += ns * kBitmapPlanes * words * 4;
     s.arcs = (DagArc*)p;
     s.acap = (int32_t)kArcsPerSlot;
+    // scratch of the 128-bit path: distances -1, counts 0
+    const int64_t wbudget = std::max<int64_t>(budget / 8, stride * kWideBytesPerNode);
+    int64_t nw = std::max<int64_t>(1, std::min<int64_t>(kWideSlots, wbudget / (stride * kWideBytesPerNode)));
+    void* wmem = nullptr;
+    while (nw >= 1) {
+        e = hipMalloc(&wmem, (size_t)(nw * stride * kWideBytesPerNode));
+        if (e == hipSuccess) break;
+        (void)hipGetLastError();
+        nw /= 2;
+    }
+    if (e != hipSuccess || !wmem) {
+        (void)hipFree(mem);
+        return fail(c, PERCIS_E_NOMEM, "cannot allocate the 128-bit path's scratch");
+    }
+    WideSlots w{};
+    w.stride = stride;
+    char* wp = (char*)wmem;
+    w.sigma = (unsigned __int128*)wp; wp += nw * stride * 16;
+    w.dist = (int32_t*)wp; wp += nw * stride * 4;
+    w.queue = (int32_t*)wp;
+    w.work = c->d_work + 3;
+    if (launch_fill_u8(w.sigma, nw * stride * 16, c->stream) != hipSuccess ||
+        launch_fill_u32((uint32_t*)w.dist, 0xFFFFFFFFu, nw * stride, c->stream) != hipSuccess) {
+        (void)hipFree(mem);
+        (void)hipFree(wmem);
+        return fail(c, PERCIS_E_DEVICE, "scratch clear failed");
+    }
     c->slot_mem = mem;
     c->slots = s;
     c->nslots = (int)ns;
     c->slot_act = act;
     c->shape = sh;
+    c->wide_mem = wmem;
+    c->wide_slots = (int)nw;
+    c->wslots = w;
     return PERCIS_OK;
 }
 
@@ -568,6 +604,7 @@ int run_tasks(percis_ctx* c, const std::vector<TaskSpec>& tasks, std::vector<per
     if (chunk > c->pair_cap) {
         if (c->stream) HIPCHK(c, hipStreamSynchronize(c->stream));
         if ((rc = dalloc(c, c->d_pairs, (size_t)chunk))) return rc;
+        if ((rc = dalloc(c, c->d_wide, (size_t)chunk))) return rc;
         c->pair_cap = chunk;
     }
     const size_t nchunks = (size_t)((total + chunk - 1) / chunk);
@@ -584,6 +621,8 @@ int run_tasks(percis_ctx* c, const std::vector<TaskSpec>& tasks, std::vector<per
     a.npairs = c->d_work + 1;
     a.stats = c->d_stats;
     a.slots = (int)std::min<uint64_t>((uint64_t)c->nslots, chunk);
+    a.wide = c->d_wide;
+    a.nwide = c->d_work + 2;
     for (size_t i = 0; i < nchunks; i++) {
         a.base = (uint64_t)i * chunk;
         a.count = std::min<uint64_t>(chunk, total - a.base);
@@ -591,6 +630,7 @@ int run_tasks(percis_ctx* c, const std::vector<TaskSpec>& tasks, std::vector<per
         HIPCHK(c, launch_pairs(a, c->stream));
         HIPCHK(c, hipEventRecord(c->chunk_ev[3 * i + 1], c->stream));
         HIPCHK(c, launch_sampler(c->slots, a, c->shape, c->stream));
+        HIPCHK(c, launch_wide(a, c->wslots, c->wide_slots, c->stream));
         HIPCHK(c, hipEventRecord(c->chunk_ev[3 * i + 2], c->stream));
     }
     std::vector<DevStats> hts(nt);
@@ -771,7 +811,7 @@ int percis_create(int device, void* hip_stream, percis_ctx** out) {
         if (hipDeviceGetAttribute(&wall_khz, hipDeviceAttributeWallClockRate, device) == hipSuccess)
             c->wall_hz = wall_khz * 1e3;
         if (hipMalloc((void**)&c->d_stats, sizeof(DevStats)) != hipSuccess ||
-            hipMalloc((void**)&c->d_work, 2 * sizeof(unsigned long long)) != hipSuccess ||
+            hipMalloc((void**)&c->d_work, 4 * sizeof(unsigned long long)) != hipSuccess ||
             hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess) {
             percis_destroy(c);
             return PERCIS_E_DEVICE;
@@ -803,6 +843,8 @@ void percis_destroy(percis_ctx* c) {
     dfree(c->d_stats);
     dfree(c->d_work);
     dfree(c->d_pairs);
+    dfree(c->d_wide);
+    dfree(c->d_wdbg);
     for (hipEvent_t e : c->chunk_ev) (void)hipEventDestroy(e);
     c->chunk_ev.clear();
     dfree(c->d_dbg);
@@ -986,6 +1028,46 @@ int percis_debug_path(percis_ctx* c, int32_t s, int32_t t, uint64_t r, int32_t* 
     if (o->overflow == 2) return fail(c, PERCIS_E_DEVICE, "canonical walk found no predecessor");
     if (path && o->L >= 0 && !o->overflow && r < o->sigma && o->L + 1 <= cap)
         for (int32_t i = 0; i <= o->L; i++) path[i] = G.h_orig[o->path[i]];
+    return PERCIS_OK;
+}
+
+int percis_debug_path_wide(percis_ctx* c, int32_t s, int32_t t, uint64_t r_lo, uint64_t r_hi, int32_t* path,
+                           int32_t cap, int32_t* L, uint64_t* sigma_lo, uint64_t* sigma_hi, int32_t* overflow) {
+    if (!c) return PERCIS_E_INVAL;
+    GraphData& G = *c->graphs[0];
+    if (!G.has_graph) return fail(c, PERCIS_E_STATE, "load a graph first");
+    if (s < 0 || s >= G.n || t < 0 || t >= G.n || s == t || cap < 0 || (cap > 0 && !path))
+        return fail(c, PERCIS_E_INVAL, "bad debug_path_wide arguments");
+    int rc = graph_upload(c, G, false);
+    if (rc) return rc;
+    if ((rc = ensure_slots(c, std::max<int64_t>(G.n_act, max_active(c))))) return rc;
+    const int32_t need = std::max<int32_t>(cap, 1);
+    if (need > c->wdbg_cap) {
+        dfree(c->d_wdbg);
+        void* p = nullptr;
+        HIPCHK(c, hipMalloc(&p, sizeof(WideDebug) + sizeof(int32_t) * need));
+        c->d_wdbg = (WideDebug*)p;
+        c->wdbg_cap = need;
+    }
+    WideDebug req{};
+    req.s = G.h_newid[s];
+    req.t = G.h_newid[t];
+    req.r = (unsigned __int128)r_lo | ((unsigned __int128)r_hi << 64);
+    req.cap = cap;
+    req.path = (int32_t*)(c->d_wdbg + 1);
+    HIPCHK(c, hipMemcpyAsync(c->d_wdbg, &req, sizeof req, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, launch_wide_debug(dev_graph(G), c->wslots, c->d_wdbg, c->stream));
+    std::vector<int32_t> dpath(need);
+    HIPCHK(c, hipMemcpyAsync(&req, c->d_wdbg, sizeof req, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(dpath.data(), c->d_wdbg + 1, sizeof(int32_t) * need, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (L) *L = req.L;
+    if (sigma_lo) *sigma_lo = (uint64_t)req.sigma;
+    if (sigma_hi) *sigma_hi = (uint64_t)(req.sigma >> 64);
+    if (overflow) *overflow = req.overflow;
+    if (req.overflow == 2) return fail(c, PERCIS_E_DEVICE, "canonical walk found no predecessor");
+    if (path && req.L >= 0 && !req.overflow && req.r < req.sigma && req.L + 1 <= cap)
+        for (int32_t i = 0; i <= req.L; i++) path[i] = G.h_orig[dpath[i]];
     return PERCIS_OK;
 }
 

@@ -68,8 +68,15 @@ struct percis_ctx {
     percis::SamplerShape shape{};
 
     percis::DevStats* d_stats = nullptr;   // launch-wide counters
-    unsigned long long* d_work = nullptr;  // [2]: next list entry (or source), listed pairs
+    unsigned long long* d_work = nullptr;  // [4]: next list entry (or source), listed pairs, listed wide samples,
+                                           //      next wide entry
     percis::PairRec* d_pairs = nullptr;    // pair list of one chunk
+    percis::PairRec* d_wide = nullptr;     // samples of one chunk with sigma_st >= 2^64
+    void* wide_mem = nullptr;              // scratch of the 128-bit path
+    int wide_slots = 0;
+    percis::WideSlots wslots{};
+    percis::WideDebug* d_wdbg = nullptr;   // debug request of the 128-bit path, followed by its path
+    int32_t wdbg_cap = 0;
     uint64_t pair_cap = 0;
     std::vector<hipEvent_t> chunk_ev;      // 3 per chunk: pairs, sampler, end
     percis::DevTask* d_tasks = nullptr;

@@ -108,6 +108,28 @@ struct SampleLaunch {
     unsigned long long* work;        // next unclaimed list entry
     DevStats* stats;                 // launch-wide work counters and phase times
     int slots;                       // sampler grid size
+    PairRec* wide;                   // [count] capacity: samples with sigma_st >= 2^64
+    unsigned long long* nwide;       // entries listed (written by the sampler)
+};
+
+// Scratch of the 128-bit path (samples with sigma_st >= 2^64): per slot, a
+// distance (-1 = unreached), a 128-bit count and a queue entry per active node.
+struct WideSlots {
+    int32_t* dist;               // [slots][stride], all -1 between samples
+    unsigned __int128* sigma;    // [slots][stride], all 0 between samples
+    int32_t* queue;              // [slots][stride]
+    int64_t stride;
+    unsigned long long* work;    // next unclaimed wide-list entry
+};
+
+// Debug request of the 128-bit path.
+struct WideDebug {
+    int32_t s, t;
+    unsigned __int128 r;
+    int32_t L, overflow;         // overflow: sigma_st saturated (>= 2^128 - 1)
+    unsigned __int128 sigma;
+    int32_t cap;
+    int32_t* path;               // device, cap entries
 };
 
 // Debug request: one (s, t, r) path; output written to `out`.
@@ -131,8 +153,13 @@ hipError_t launch_fill_u8(void* p, int64_t bytes, hipStream_t stream);
 hipError_t launch_init_stats(DevStats* st, unsigned long long* work, hipStream_t stream);
 // Zeroes every task's statistics and, where asked, its hits (one launch).
 hipError_t launch_clear_tasks(const DevTask* tasks, int ntasks, int64_t max_n, hipStream_t stream);
-// Zeroes *work and *npairs, then draws the chunk's pairs (one lane per sample).
+// Zeroes *work, *npairs and *nwide, then draws the chunk's pairs (one lane per sample).
 hipError_t launch_pairs(const SampleLaunch& a, hipStream_t stream);
+// The chunk's listed wide samples (a.wide[0 .. *a.nwide)) on `slots`
+// workgroups (an empty list costs one short launch).
+hipError_t launch_wide(const SampleLaunch& a, const WideSlots& w, int slots, hipStream_t stream);
+// One (s, t, r) through the 128-bit path, on graph g, using slot 0 of w.
+hipError_t launch_wide_debug(const DevGraph& g, const WideSlots& w, WideDebug* dbg, hipStream_t stream);
 hipError_t launch_sampler(const DevSlots& slots, const SampleLaunch& a, const SamplerShape& shape,
                           hipStream_t stream);
 hipError_t launch_debug_path(const DevGraph& g, const DevSlots& slots, int32_t s, int32_t t, uint64_t r,

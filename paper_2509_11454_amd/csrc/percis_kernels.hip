@@ -651,7 +651,7 @@ __device__ void claim_next(const SampleLaunch& L, unsigned long long npairs, Sam
 template <int BSZ, bool LDS>
 __device__ void run_sample(const DevGraph& g, const DevSlots& sl, int64_t so, const Vis<LDS>& V, uint64_t idx,
                            const DevTask& T, int32_t s, int32_t t, const SampleLaunch* next,
-                           unsigned long long npairs, SampleShared& sh,
+                           unsigned long long npairs, uint32_t q_rel, int32_t task, SampleShared& sh,
                            Counters& cn, DebugOut* dbg, uint64_t dbg_r, int32_t dbg_cap) {
     using B = Bits;
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
@@ -941,7 +941,12 @@ __device__ void run_sample(const DevGraph& g, const DevSlots& sl, int64_t so, co
         if (!dbg) {
             sh.acc_samples++;
             if (sh.status == 1) {
-                if (sh.ovf || sh.walk_err) {
+                if (sh.ovf && !sh.walk_err) {
+                    // sigma_st >= 2^64: listed for the 128-bit path, which
+                    // adds the sample's statistics and hits
+                    const unsigned long long at = atomicAdd(next->nwide, 1ull);
+                    next->wide[at] = PairRec{q_rel, s, t, task};
+                } else if (sh.walk_err) {
                     sh.acc_ovf++;
                     sh.acc_first = idx < sh.acc_first ? idx : sh.acc_first;
                 } else {
@@ -1057,7 +1062,8 @@ __global__ __launch_bounds__(BSZ) SAMPLER_OCCUPANCY void sampler_kernel(DevSlots
             flush_task_stats(sh, L);
             sh.acc_task = k;
         }
-        run_sample<BSZ, LDS>(T.g, sl, so, V, T.first + (q - T.offset), T, s, t, &L, npairs, sh, cn, nullptr, 0, 0);
+        run_sample<BSZ, LDS>(T.g, sl, so, V, T.first + (q - T.offset), T, s, t, &L, npairs, (uint32_t)(q - L.base), k,
+                             sh, cn, nullptr, 0, 0);
     }
     flush_counters(cn, L.stats);
     if (tid == 0) {
@@ -1080,7 +1086,7 @@ __global__ __launch_bounds__(BSZ) void debug_path_kernel(DevGraph g, DevSlots sl
     }
     __syncthreads();
     DevTask T = {};
-    run_sample<BSZ, LDS>(g, sl, 0, V, 0, T, s, t, nullptr, 0, sh, cn, out, r, cap);
+    run_sample<BSZ, LDS>(g, sl, 0, V, 0, T, s, t, nullptr, 0, 0, -1, sh, cn, out, r, cap);
 }
 
 __global__ void fill_u32_kernel(uint32_t* p, uint32_t v, int64_t count) {
@@ -1150,11 +1156,216 @@ __global__ __launch_bounds__(256) void pair_kernel(SampleLaunch L) {
     }
 }
 
-__global__ void init_chunk_kernel(unsigned long long* work, unsigned long long* npairs) {
+__global__ void init_chunk_kernel(unsigned long long* work, unsigned long long* npairs, unsigned long long* nwide) {
     if (threadIdx.x == 0) {
         *work = 0;
         *npairs = 0;
+        *nwide = 0;
     }
+}
+
+// ------------------------------------------------------- 128-bit path
+// Samples whose sigma_st reaches 2^64 are redone here with exact 128-bit
+// counts (saturating at 2^128 - 1, which is an overflow): a plain
+// level-synchronous BFS from s in which each new node pulls its count from
+// its in-neighbours one level up (no atomics on counts), stopped at t's
+// level, then r in [0, sigma_st) by Lemire's method at 128 bits and the
+// canonical backward walk with 128-bit weights. Rare, so kept simple.
+typedef unsigned __int128 u128;
+constexpr int WB = 256;
+
+__device__ __forceinline__ u128 sat_add128(u128 a, u128 b) {
+    const u128 c = a + b;
+    return c < a ? ~(u128)0 : c;
+}
+
+// Words 0 and 1 of the Philox4x64-10 block (the 64-bit path uses word 0).
+__device__ void philox_words01(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3, uint64_t k0, uint64_t k1,
+                               uint64_t& w0, uint64_t& w1) {
+    for (int i = 0; i < 10; i++) {
+        const uint64_t m0 = 0xD2E7470EE14C6C93ull, m1 = 0xCA5A826395121157ull;
+        const uint64_t hi0 = __umul64hi(m0, c0), lo0 = m0 * c0;
+        const uint64_t hi1 = __umul64hi(m1, c2), lo1 = m1 * c2;
+        const uint64_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+        c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
+        k0 += 0x9E3779B97F4A7C15ull;
+        k1 += 0xBB67AE8584CAA73Bull;
+    }
+    w0 = c0;
+    w1 = c1;
+}
+
+// a * b as 256 bits (hi, lo) from 64-bit partial products.
+__device__ __forceinline__ void mul_128x128(u128 a, u128 b, u128& hi, u128& lo) {
+    const uint64_t a0 = (uint64_t)a, a1 = (uint64_t)(a >> 64), b0 = (uint64_t)b, b1 = (uint64_t)(b >> 64);
+    const u128 p00 = (u128)a0 * b0, p01 = (u128)a0 * b1, p10 = (u128)a1 * b0, p11 = (u128)a1 * b1;
+    const u128 mid = (p00 >> 64) + (uint64_t)p01 + (uint64_t)p10;
+    lo = (u128)(uint64_t)p00 | (mid << 64);
+    hi = p11 + (p01 >> 64) + (p10 >> 64) + (mid >> 64);
+}
+
+// r uniform in [0, N): the 64-bit draw of the sampler for N < 2^64, else
+// Lemire at 128 bits on x = word 0 + 2^64 word 1.
+__device__ u128 draw_r_wide(uint64_t seed, uint64_t phase, uint64_t idx, u128 N) {
+    if ((N >> 64) == 0) return draw_bounded(seed, phase, idx, 2, (uint64_t)N);
+    for (uint64_t attempt = 0;; attempt++) {
+        uint64_t w0, w1;
+        philox_words01(idx, 2, attempt, 0, seed, phase, w0, w1);
+        const u128 x = (u128)w0 | ((u128)w1 << 64);
+        u128 hi, lo;
+        mul_128x128(x, N, hi, lo);
+        if (lo < N) {
+            const u128 thr = (u128)(0 - N) % N;
+            if (lo < thr) continue;
+        }
+        return hi;
+    }
+}
+
+struct WideShared {
+    int32_t lo, hi, tail, level;
+    unsigned long long q;
+};
+
+// BFS of one (s, t) on this workgroup's wide slot; returns d(s,t) or -1 (all
+// threads), with sigma[t] complete. Leaves every reached node in q[0, tail).
+__device__ int32_t wide_bfs(const DevGraph& g, int32_t* dist, u128* sig, int32_t* q, int32_t s, int32_t t,
+                            WideShared& sh) {
+    const int tid = threadIdx.x;
+    if (tid == 0) {
+        dist[s] = 0;
+        sig[s] = 1;
+        q[0] = s;
+        sh.lo = 0; sh.hi = 1; sh.tail = 1; sh.level = 0;
+    }
+    __syncthreads();
+    for (;;) {
+        const int lo = sh.lo, hi = sh.hi, level = sh.level;
+        if (__hip_atomic_load(dist + t, __ATOMIC_RELAXED, WGS) >= 0) return level;
+        for (int i = lo + tid; i < hi; i += WB) {
+            const int32_t u = q[i];
+            for (int32_t e = g.rp[u]; e < g.rp[u + 1]; e++) {
+                const int32_t v = g.col[e];
+                int32_t expect = -1;
+                if (__hip_atomic_load(dist + v, __ATOMIC_RELAXED, WGS) == -1 &&
+                    __hip_atomic_compare_exchange_strong(dist + v, &expect, level + 1, __ATOMIC_RELAXED,
+                                                         __ATOMIC_RELAXED, WGS))
+                    q[atomicAdd(&sh.tail, 1)] = v;
+            }
+        }
+        __syncthreads();
+        const int nhi = sh.tail;
+        if (nhi == hi) return -1;
+        const bool t_new = __hip_atomic_load(dist + t, __ATOMIC_RELAXED, WGS) == level + 1;
+        // counts of the new level (only t's once t is reached)
+        for (int i = hi + tid; i < nhi; i += WB) {
+            const int32_t v = q[i];
+            if (t_new && v != t) continue;
+            u128 acc = 0;
+            for (int32_t e = g.irp[v]; e < g.irp[v + 1]; e++) {
+                const int32_t u = g.icol[e];
+                if (__hip_atomic_load(dist + u, __ATOMIC_RELAXED, WGS) == level) acc = sat_add128(acc, sig[u]);
+            }
+            sig[v] = acc;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            sh.lo = hi;
+            sh.hi = nhi;
+            sh.level = level + 1;
+        }
+        __syncthreads();
+    }
+}
+
+// Canonical walk with 128-bit weights (one thread), from t down to s: adds a
+// hit to every internal node when hits is given, writes path[L] = t ..
+// path[0] = s when path is given (cap entries); false if a step finds no
+// predecessor.
+__device__ bool wide_walk(const DevGraph& g, const int32_t* dist, const u128* sig, int32_t t, int32_t L, u128 r,
+                          uint32_t* hits, int32_t* path, int32_t cap) {
+    int32_t w = t;
+    if (path && L < cap) path[L] = t;
+    for (int32_t pos = L; pos >= 1; pos--) {
+        int32_t next = -1;
+        for (int32_t e = g.irp[w]; e < g.irp[w + 1]; e++) {
+            const int32_t u = g.icol[e];
+            if (dist[u] != pos - 1) continue;
+            if (r < sig[u]) { next = u; break; }
+            r -= sig[u];
+        }
+        if (next < 0) return false;
+        if (path && pos - 1 < cap) path[pos - 1] = next;
+        if (hits && pos - 1 >= 1) atomicAdd(hits + g.orig[next], 1u);
+        w = next;
+    }
+    return true;
+}
+
+__device__ void wide_clear(int32_t* dist, u128* sig, const int32_t* q, int tail) {
+    for (int i = threadIdx.x; i < tail; i += WB) {
+        const int32_t v = q[i];
+        dist[v] = -1;
+        sig[v] = 0;
+    }
+}
+
+__global__ __launch_bounds__(WB) void wide_kernel(SampleLaunch L, WideSlots W) {
+    __shared__ WideShared sh;
+    const int tid = threadIdx.x;
+    const unsigned long long nwide = *L.nwide;
+    int32_t* dist = W.dist + (int64_t)blockIdx.x * W.stride;
+    u128* sig = W.sigma + (int64_t)blockIdx.x * W.stride;
+    int32_t* q = W.queue + (int64_t)blockIdx.x * W.stride;
+    for (;;) {
+        if (tid == 0) sh.q = atomicAdd(W.work, 1ull);
+        __syncthreads();
+        const unsigned long long i = sh.q;
+        if (i >= nwide) break;
+        const PairRec rec = L.wide[i];
+        const DevTask& T = L.tasks[rec.task];
+        const unsigned long long lq = L.base + rec.q;
+        const uint64_t idx = T.first + (lq - T.offset);
+        const int32_t Ld = wide_bfs(T.g, dist, sig, q, rec.s, rec.t, sh);
+        if (tid == 0 && Ld >= 0) {
+            DevStats* st = T.stats;
+            const u128 sg = sig[rec.t];
+            if (sg == ~(u128)0) {
+                atomicAdd(&st->overflow, 1ull);
+                atomicMin(&st->first_overflow, (unsigned long long)idx);
+            } else {
+                const u128 r = draw_r_wide(T.seed, T.phase, idx, sg);
+                if (wide_walk(T.g, dist, sig, rec.t, Ld, r, T.hits, nullptr, 0)) {
+                    const unsigned long long I = (unsigned long long)(Ld - 1);
+                    atomicAdd(&st->reachable, 1ull);
+                    atomicAdd(&st->sum_I, I);
+                    atomicAdd(&st->sum_I2, I * I);
+                } else {
+                    atomicAdd(&st->overflow, 1ull);
+                    atomicMin(&st->first_overflow, (unsigned long long)idx);
+                }
+            }
+        }
+        __syncthreads();
+        wide_clear(dist, sig, q, sh.tail);
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(WB) void wide_debug_kernel(DevGraph g, WideSlots W, WideDebug* dbg) {
+    __shared__ WideShared sh;
+    const int32_t s = dbg->s, t = dbg->t;
+    const int32_t Ld = wide_bfs(g, W.dist, W.sigma, W.queue, s, t, sh);
+    if (threadIdx.x == 0) {
+        dbg->L = Ld;
+        dbg->sigma = Ld >= 0 ? W.sigma[t] : 0;
+        dbg->overflow = (Ld >= 0 && dbg->sigma == ~(u128)0) ? 1 : 0;
+        if (Ld >= 0 && !dbg->overflow && dbg->r < dbg->sigma && Ld + 1 <= dbg->cap) {
+            if (!wide_walk(g, W.dist, W.sigma, t, Ld, dbg->r, nullptr, dbg->path, dbg->cap)) dbg->overflow = 2;
+        }
+    }
+    __syncthreads();
+    wide_clear(W.dist, W.sigma, W.queue, sh.tail);
 }
 
 __global__ void init_stats_kernel(DevStats* st, unsigned long long* work) {
@@ -1203,8 +1414,22 @@ hipError_t launch_fill_u8(void* p, int64_t bytes, hipStream_t stream) {
     return hipGetLastError();
 }
 
+hipError_t launch_wide(const SampleLaunch& a, const WideSlots& w, int slots, hipStream_t stream) {
+    if (slots <= 0) return hipSuccess;
+    hipLaunchKernelGGL(init_chunk_kernel, dim3(1), dim3(64), 0, stream, w.work, w.work, w.work);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(wide_kernel, dim3(slots), dim3(WB), 0, stream, a, w);
+    return hipGetLastError();
+}
+
+hipError_t launch_wide_debug(const DevGraph& g, const WideSlots& w, WideDebug* dbg, hipStream_t stream) {
+    hipLaunchKernelGGL(wide_debug_kernel, dim3(1), dim3(WB), 0, stream, g, w, dbg);
+    return hipGetLastError();
+}
+
 hipError_t launch_pairs(const SampleLaunch& a, hipStream_t stream) {
-    hipLaunchKernelGGL(init_chunk_kernel, dim3(1), dim3(64), 0, stream, a.work, a.npairs);
+    hipLaunchKernelGGL(init_chunk_kernel, dim3(1), dim3(64), 0, stream, a.work, a.npairs, a.nwide);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || a.count == 0) return e;
     int64_t blocks = ((int64_t)a.count + 255) / 256;

@@ -84,6 +84,9 @@ _SIGS = {
     "percis_set_vertex_diameter": (C.c_int, [_P, C.c_int64]),
     "percis_debug_path": (C.c_int, [_P, C.c_int32, C.c_int32, C.c_uint64, _P, C.c_int32,
                                     C.POINTER(C.c_int32), C.POINTER(C.c_uint64), C.POINTER(C.c_int32)]),
+    "percis_debug_path_wide": (C.c_int, [_P, C.c_int32, C.c_int32, C.c_uint64, C.c_uint64, _P, C.c_int32,
+                                         C.POINTER(C.c_int32), C.POINTER(C.c_uint64), C.POINTER(C.c_uint64),
+                                         C.POINTER(C.c_int32)]),
     "percis_add_graph": (C.c_int, [_P, C.c_int32, C.c_int64, _P, _P, _P, C.c_uint32, C.POINTER(C.c_int32)]),
     "percis_graph_info": (C.c_int, [_P, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int64),
                                     C.POINTER(C.c_int32)]),
@@ -232,6 +235,19 @@ class Context:
         self._check(_lib.percis_debug_path(self._h, int(s), int(t), int(r), _np_ptr(buf), int(cap),
                                            C.byref(L), C.byref(sig), C.byref(ovf)))
         L, sig, ovf = int(L.value), int(sig.value), int(ovf.value)
+        path = [int(v) for v in buf[:L + 1]] if (L >= 0 and not ovf and r < sig and L + 1 <= cap) else None
+        return L, sig, ovf, path
+
+    def debug_path_wide(self, s, t, r, cap=None):
+        """The 128-bit path for (s, t, r): returns (L, sigma, overflow, path)
+        with r and sigma Python ints."""
+        cap = self.n + 1 if cap is None else cap
+        buf = np.zeros(max(cap, 1), np.int32)
+        L, lo, hi, ovf = C.c_int32(), C.c_uint64(), C.c_uint64(), C.c_int32()
+        self._check(_lib.percis_debug_path_wide(self._h, int(s), int(t), int(r) & ((1 << 64) - 1), int(r) >> 64,
+                                                _np_ptr(buf), int(cap), C.byref(L), C.byref(lo), C.byref(hi),
+                                                C.byref(ovf)))
+        L, sig, ovf = int(L.value), (int(hi.value) << 64) | int(lo.value), int(ovf.value)
         path = [int(v) for v in buf[:L + 1]] if (L >= 0 and not ovf and r < sig and L + 1 <= cap) else None
         return L, sig, ovf, path
 

@@ -235,25 +235,93 @@ def test_special_graph_parity(ci):
     same_stats(so, sg)
 
 
-def test_overflow_parity():
+def test_wide_sigma_parity():
     """35 x 35 grid with the corner pair likely: the pair (0, far corner) has
-    C(68, 34) >= 2^64 shortest paths; those samples are counted, add no hits,
-    and the call reports PERCIS_E_SIGMA_OVERFLOW with the first index."""
-    from paper_2509_11454_amd import percis as P
+    C(68, 34) >= 2^64 shortest paths, so its samples take the 128-bit path (r
+    drawn at 128 bits); hits and statistics are bit-identical to the oracle,
+    and nothing overflows."""
     g = W.grid_graph(35, 35)
     k = np.full(g.n, 32768, np.uint16)
     k[0], k[g.n - 1] = 65535, 0
     og, st = oracle_objects(g, k)
     ho, so = oracle_hits(og, st, 0, 6000, 2)
+    assert so["overflow"] == 0
+    # the corner pair is among the samples
+    assert any(O.draw_pair(st, 2, 0, i)[:2] in ((0, g.n - 1), (g.n - 1, 0)) for i in range(6000))
+    c = gpu_context(g, k)
+    hg, sg = gpu_hits(c, 0, 6000, 2)
+    assert np.array_equal(ho, hg)
+    same_stats(so, sg)
+
+
+def test_overflow_parity():
+    """70 x 70 grid with the corner pair likely: C(138, 69) >= 2^128 shortest
+    paths saturate even the 128-bit counts; those samples are counted, add no
+    hits, and the call reports PERCIS_E_SIGMA_OVERFLOW with the first index."""
+    from paper_2509_11454_amd import percis as P
+    g = W.grid_graph(70, 70)
+    k = np.full(g.n, 32768, np.uint16)
+    k[0], k[g.n - 1] = 65535, 0
+    og, st = oracle_objects(g, k)
+    ho, so = oracle_hits(og, st, 0, 1500, 2)
     assert so["overflow"] > 0
     c = gpu_context(g, k)
     h = np.zeros(g.n, np.uint32)
     with pytest.raises(P.PercisError) as e:
-        c.sample_range(0, 6000, 2, 0, hits=h)
+        c.sample_range(0, 1500, 2, 0, hits=h)
     assert e.value.status == P.E_SIGMA_OVERFLOW
-    hg, sg = gpu_hits(c, 0, 6000, 2, allow_overflow=True)
+    hg, sg = gpu_hits(c, 0, 1500, 2, allow_overflow=True)
     assert np.array_equal(ho, hg)
     same_stats(so, sg)
+
+
+def diamond_path(k, r):
+    out = [0]
+    for i in range(k):
+        out.append(k + 1 + 2 * i + ((r >> i) & 1))
+        out.append(i + 1)
+    return out
+
+
+def test_debug_path_wide():
+    """The 128-bit path: diamond chains (sigma = 2^k, the path is the binary
+    expansion of r, k up to 127; k = 128 saturates), grid corners on both
+    sides of 2^128 against the oracle, and agreement with the 64-bit path
+    below 2^64."""
+    from paper_2509_11454_amd import percis as P
+    rng = np.random.default_rng(17)
+    c = P.Context(0)
+    for k in (64, 100, 127, 128):
+        g = W.diamond_chain(k)
+        c.load_csr(g.n, g.row_ptr, g.col)
+        if k == 128:
+            L, sig, ovf, p = c.debug_path_wide(0, k, 0)
+            assert L == 256 and ovf == 1 and p is None
+            continue
+        for r in [0, 1, 2 ** k - 1, 2 ** (k - 1)] + [int(rng.integers(0, 2 ** 62)) << (k - 62) for _ in range(4)]:
+            L, sig, ovf, p = c.debug_path_wide(0, k, r)
+            assert (L, sig, ovf) == (2 * k, 2 ** k, 0)
+            assert p == diamond_path(k, r)
+    for a in (35, 66, 70):
+        g = W.grid_graph(a, a)
+        c.load_csr(g.n, g.row_ptr, g.col)
+        og = O.Graph(g.n, g.row_ptr, g.col)
+        L0, sig0, _ = O.path(og, 0, g.n - 1, 0)
+        if sig0 == O.SIGMA_SATURATED:
+            L, sig, ovf, p = c.debug_path_wide(0, g.n - 1, 0)
+            assert (L, ovf, p) == (L0, 1, None)
+            continue
+        for r in (0, 1, sig0 // 3, sig0 - 1):
+            L, sig, ovf, p = c.debug_path_wide(0, g.n - 1, r)
+            assert (L, sig, ovf) == (L0, sig0, 0)
+            assert p == O.path(og, 0, g.n - 1, r)[2]
+    for g in small_graphs()[:6]:
+        c.load_csr(g.n, g.row_ptr, g.col, directed=g.directed)
+        for s_, t_ in ((0, g.n - 1), (1, 2), (g.n - 1, 0)):
+            a64 = c.debug_path(s_, t_, 0)
+            a128 = c.debug_path_wide(s_, t_, 0)
+            assert a64 == a128
+    c.close()
 
 
 def test_rmat18_subrange_parity_and_full_run():
