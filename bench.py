@@ -107,8 +107,9 @@ def main():
     ap.add_argument("--no-estimate", action="store_true")
     ap.add_argument("--one-per-launch", type=int, default=2000, metavar="N",
                     help="also time N samples drawn one per launch (0 = skip)")
-    ap.add_argument("--mode", default="single", choices=["single", "batch", "serve"],
-                    help="single: one graph (default); batch: 64 BA graphs in one launch; serve: query stream")
+    ap.add_argument("--mode", default="single", choices=["single", "batch", "serve", "setup"],
+                    help="single: one graph (default); batch: 64 BA graphs in one launch; serve: query stream; "
+                         "setup: state-only updates and VertexDiamUB on the device")
     ap.add_argument("--queries", type=int, default=120, help="serve: queries per load level")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (reference for HBM counters)")
@@ -122,6 +123,9 @@ def main():
         return
     if args.mode == "serve":
         run_serve(args)
+        return
+    if args.mode == "setup":
+        run_setup(args)
         return
 
     if args.gpus != 1:
@@ -327,6 +331,69 @@ def run_batch(args):
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "sampler_kernel",
                      "kernel_ms": avg_kernel_s * 1e3, "algorithmic_bytes_per_launch": b_alg},
     }
+    print(json.dumps(out), flush=True)
+
+
+def run_setup(args):
+    """Device-side setup on one workload: the first percis_set_states (graph
+    upload included), state-only updates from a host array and from a device
+    tensor (the pair distribution rebuilt on the device each time), and
+    VertexDiamUB on the device; the oracle's serial preprocessing and
+    VertexDiamUB on the host beside them."""
+    import numpy as np
+    import torch
+    import workloads as W
+    from paper_2509_11454_amd import percis as P
+
+    builder, _, desc = WORKLOADS[args.workload]
+    g, k = getattr(W, builder)(args.seed)
+    rng = np.random.default_rng(args.seed + 1)
+    c = P.Context(0)
+    t0 = time.perf_counter()
+    c.load_csr(g.n, g.row_ptr, g.col, directed=g.directed)
+    load_ms = (time.perf_counter() - t0) * 1e3
+    t0 = time.perf_counter()
+    c.set_states(k)
+    first_ms = (time.perf_counter() - t0) * 1e3
+    new_k = [W.beta_states(g.n, rng) for _ in range(args.steps + args.warmup)]
+    host_ms, dev_ms = [], []
+    for i, kk in enumerate(new_k):
+        t0 = time.perf_counter()
+        c.set_states(kk)
+        if i >= args.warmup:
+            host_ms.append((time.perf_counter() - t0) * 1e3)
+    dev_k = [torch.from_numpy(kk.view(np.int16)).cuda() for kk in new_k]
+    torch.cuda.synchronize()
+    for i, kk in enumerate(dev_k):
+        t0 = time.perf_counter()
+        c.set_states(kk)
+        if i >= args.warmup:
+            dev_ms.append((time.perf_counter() - t0) * 1e3)
+    t0 = time.perf_counter()
+    D = c.vertex_diameter()
+    diam_ms = (time.perf_counter() - t0) * 1e3
+    t0 = time.perf_counter()
+    D2 = c.vertex_diameter()
+    cached_ms = (time.perf_counter() - t0) * 1e3
+    assert D2 == D
+    out = {"metric": "state_update_ms", "value": float(np.median(dev_ms)), "unit": "ms", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "higher_is_better": False, "data": "synthetic",
+           "config": {"workload": args.workload + ": " + desc, "n": g.n, "m_arcs": g.m},
+           "load_csr_ms": load_ms, "first_set_states_ms": first_ms,
+           "state_update_host_k_ms": float(np.median(host_ms)), "state_update_device_k_ms": float(np.median(dev_ms)),
+           "vertex_diam_ub": {"D": D, "first_ms": diam_ms, "cached_ms": cached_ms}}
+    if not args.no_cpu_baseline:
+        import oracle as O
+        t0 = time.perf_counter()
+        st = O.States(new_k[-1])
+        o_states = (time.perf_counter() - t0) * 1e3
+        og = O.Graph(g.n, g.row_ptr, g.col, g.directed)
+        t0 = time.perf_counter()
+        Do = O.vertex_diam_ub(og)
+        o_diam = (time.perf_counter() - t0) * 1e3
+        assert Do == D, (Do, D)
+        del st
+        out["cpu_baseline"] = {"kind": "oracle", "cores": 1, "states_ms": o_states, "vertex_diam_ub_ms": o_diam}
     print(json.dumps(out), flush=True)
 
 

@@ -103,9 +103,9 @@ typedef struct {
  * (NULL = null stream) that every later call enqueues on; it must outlive the
  * context or be replaced with percis_set_stream. device = PERCIS_HOST_ONLY
  * creates a context that makes no HIP call at all: it validates graphs and
- * states and builds their host-side structures, and every call that needs
- * the device returns PERCIS_E_STATE. The device copies of the graph and of
- * the pair distribution are uploaded by the first call that needs them. */
+ * states, and every call that needs the device returns PERCIS_E_STATE. The
+ * device copy of the graph is uploaded by the first call that needs it
+ * (percis_set_states does). */
 #define PERCIS_HOST_ONLY (-1)
 int percis_create(int device, void* hip_stream, percis_ctx** out);
 void percis_destroy(percis_ctx* ctx);
@@ -122,11 +122,16 @@ int percis_load_csr(percis_ctx* ctx, int32_t n, int64_t m, const int32_t* row_pt
                     const int32_t* col, uint32_t flags);
 
 /* Sets the percolation states x_v = k[v] / 65535 (k[n] uint16) and builds the
- * exact integer pair distribution: ranks sorted by (k non-increasing, node id
- * increasing) (Section II-A, "up to a relabelling"), then the preprocessing of
- * Algorithm 2 (appendix) in units of 1/65535. Returns PERCIS_E_DEGENERATE if
- * all states are equal (the total weight C is 0, Definition 1 undefined).
- * flags: PERCIS_DEVICE_PTRS. */
+ * exact integer pair distribution on the device: ranks sorted by
+ * (k non-increasing, node id increasing) (Section II-A, "up to a
+ * relabelling"), then the preprocessing of Algorithm 2 (appendix) in units of
+ * 1/65535, and the weights d_v = C / S_v. The graph stays on the device: a
+ * state-only update moves k (2n bytes) and nothing else, and with
+ * PERCIS_DEVICE_PTRS k is device memory and never leaves the device. Only C
+ * and d_hat come back to the host. Returns PERCIS_E_DEGENERATE if all states
+ * are equal (the total weight C is 0, Definition 1 undefined); the graph then
+ * has no states until the next successful call. Synchronises the context's
+ * stream. flags: PERCIS_DEVICE_PTRS. */
 int percis_set_states(percis_ctx* ctx, const uint16_t* k, uint32_t flags);
 
 /* Draws samples first .. first+count-1 of the stream (seed, phase): for each,
@@ -212,6 +217,15 @@ int percis_graph_set_vertex_diameter(percis_ctx* ctx, int32_t graph, int64_t D);
  * component's size minus 2 for directed ones). */
 int percis_set_vertex_diameter(percis_ctx* ctx, int64_t D);
 
+/* VertexDiamUB of Algorithm 1 (Section III-B) for graph `graph` into *D: the
+ * override if one is set, else computed on the device once per loaded graph
+ * (connected components by min-label hooking; for an undirected graph, per
+ * component, a BFS from its smallest node u gives min(|comp| - 2,
+ * 2 ecc(u) - 1); for a directed graph the largest weakly connected
+ * component's size minus 2; components of one node give 0). Synchronises the
+ * context's stream. */
+int percis_graph_vertex_diameter(percis_ctx* ctx, int32_t graph, int64_t* D);
+
 /* Test hook: runs RandomSP on the device for a given pair (s, t) and path
  * index r < 2^64, with 64-bit counts. Writes L = d(s,t) (-1 if unreachable)
  * and sigma_st (2^64 - 1 with *overflow = 1 when sigma_st >= 2^64: then see
@@ -227,6 +241,18 @@ int percis_debug_path(percis_ctx* ctx, int32_t s, int32_t t, uint64_t r, int32_t
  * overflowed, r < sigma_st and cap >= L + 1, the path s, ..., t. */
 int percis_debug_path_wide(percis_ctx* ctx, int32_t s, int32_t t, uint64_t r_lo, uint64_t r_hi, int32_t* path,
                            int32_t cap, int32_t* L, uint64_t* sigma_lo, uint64_t* sigma_hi, int32_t* overflow);
+
+/* Test hook: copies the device-built pair distribution of graph `graph`
+ * (Algorithm 2's preprocessing in units of 1/65535) to host arrays, each may
+ * be NULL: perm[n+1] (rank -> caller's node id, ranks sorted by k
+ * non-increasing then id increasing; perm[0] = -1), kr[n+2] (k of rank i;
+ * kr[0] = kr[n+1] = 0), W[n+2] (W[i] = sum_{j >= i} kr[j]), P[n+1]
+ * (P[i] = sum_{j <= i} ((n-j+1) kr[j] - W[j]), so P[n] = C), d_v[n] and
+ * S_v[n] by node id (S_v = the weight of the pairs that avoid v,
+ * d_v = C / S_v or 0), and the scalars C and d_hat = max(1, max_v d_v).
+ * Synchronises the context's stream. */
+int percis_debug_states(percis_ctx* ctx, int32_t graph, int32_t* perm, uint32_t* kr, uint64_t* W, uint64_t* P,
+                        double* d_v, double* S_v, uint64_t* C, double* d_hat);
 
 /* Exact percolation centrality of graph `graph` (Definition 1, Eq. 1) on the
  * device, by Brandes-style dependency accumulation from every source (the

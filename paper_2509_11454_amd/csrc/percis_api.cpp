@@ -21,6 +21,7 @@
 #include "percis.h"
 #include "percis_host.h"
 #include "percis_internal.h"
+#include "percis_setup.h"
 
 using namespace percis;
 
@@ -36,40 +37,36 @@ int fail(percis_ctx* c, int code, const char* fmt, ...) {
     return code;
 }
 
+static void graph_free_states(GraphData& G) {
+    dfree(G.d_k);
+    dfree(G.d_perm);
+    dfree(G.d_kr);
+    dfree(G.d_W);
+    dfree(G.d_P);
+    dfree(G.d_dv);
+    dfree(G.d_Sv);
+    dfree(G.d_p);
+    dfree(G.d_red);
+    if (G.build_mem) (void)hipFree(G.build_mem);
+    G.build_mem = nullptr;
+    G.has_states = false;
+    G.states_on_device = false;
+}
+
 static void graph_free_device(GraphData& G) {
     if (G.d_irp != G.d_rp) dfree(G.d_irp); else G.d_irp = nullptr;
     if (G.d_icol != G.d_col) dfree(G.d_icol); else G.d_icol = nullptr;
     dfree(G.d_rp);
     dfree(G.d_col);
     dfree(G.d_orig);
+    dfree(G.d_newid);
     dfree(G.d_hits);
-    dfree(G.d_perm);
-    dfree(G.d_kr);
-    dfree(G.d_W);
-    dfree(G.d_P);
+    graph_free_states(G);
     G.graph_on_device = false;
-    G.states_on_device = false;
-}
-
-static void graph_clear_states(GraphData& G) {
-    dfree(G.d_perm);
-    dfree(G.d_kr);
-    dfree(G.d_W);
-    dfree(G.d_P);
-    G.has_states = false;
-    G.states_on_device = false;
-    G.d_v.clear();
-    G.S_v.clear();
-    G.h_k.clear();
-    G.h_perm.clear();
-    G.h_kr.clear();
-    G.h_W.clear();
-    G.h_P.clear();
 }
 
 static void graph_clear(GraphData& G) {
     graph_free_device(G);
-    graph_clear_states(G);
     G.h_rp.clear();
     G.h_col.clear();
     G.h_irp.clear();
@@ -79,6 +76,7 @@ static void graph_clear(GraphData& G) {
     G.has_graph = false;
     G.n = G.n_act = 0;
     G.m = 0;
+    G.D_cached = -1;
 }
 
 static int graph_load(percis_ctx* c, GraphData& G, int32_t n, int64_t m, const int32_t* row_ptr, const int32_t* col,
@@ -163,59 +161,68 @@ static int graph_load(percis_ctx* c, GraphData& G, int32_t n, int64_t m, const i
     return PERCIS_OK;
 }
 
+// Sets the states of G. On a device context the pair distribution of
+// Algorithm 2 (preprocessing) and the weights d_v, S_v are built on the
+// device from k (a state-only update re-uses the graph's device copy and its
+// arrays); the host receives C and d_hat. A host-only context only checks the
+// states: C = 0 exactly when all states are equal.
 static int graph_set_states(percis_ctx* c, GraphData& G, const uint16_t* k_in, uint32_t flags) {
     if (!G.has_graph) return fail(c, PERCIS_E_STATE, "load a graph first");
     if (!k_in) return fail(c, PERCIS_E_INVAL, "null states");
     if ((flags & PERCIS_DEVICE_PTRS) && c->host_only) return fail(c, PERCIS_E_INVAL, "device pointers on a host-only context");
     const int32_t n = G.n;
-    std::vector<uint16_t> k(n);
-    if (flags & PERCIS_DEVICE_PTRS) HIPCHK(c, hipMemcpy(k.data(), k_in, sizeof(uint16_t) * n, hipMemcpyDeviceToHost));
-    else std::memcpy(k.data(), k_in, sizeof(uint16_t) * n);
-
-    // ranks: counting sort on (65535 - k), stable in the caller's node id
-    std::vector<int64_t> start(65537, 0);
-    for (int32_t v = 0; v < n; v++) start[65535 - k[v] + 1]++;
-    for (int i = 0; i < 65536; i++) start[i + 1] += start[i];
-    std::vector<int32_t> perm(n + 1, -1);
-    for (int32_t v = 0; v < n; v++) perm[1 + start[65535 - k[v]]++] = v;
-    std::vector<uint32_t> kr(n + 2, 0);
-    for (int32_t i = 1; i <= n; i++) kr[i] = k[perm[i]];
-    for (int32_t i = 1; i <= n; i++) perm[i] = G.h_newid[perm[i]];  // the device works in internal ids
-    std::vector<uint64_t> W(n + 2, 0), P(n + 1, 0);
-    for (int32_t i = n; i >= 1; i--) W[i] = W[i + 1] + kr[i];
-    for (int32_t i = 1; i <= n; i++) {
-        const uint64_t ci = (uint64_t)(n - i + 1) * kr[i] - W[i];
-        P[i] = P[i - 1] + ci;
+    if (c->host_only) {
+        bool equal = true;
+        for (int32_t v = 1; v < n && equal; v++) equal = k_in[v] == k_in[0];
+        G.has_states = false;
+        if (equal) return fail(c, PERCIS_E_DEGENERATE, "all percolation states are equal");
+        G.has_states = true;
+        return PERCIS_OK;
     }
-    const uint64_t C = P[n];
-    if (C == 0) return fail(c, PERCIS_E_DEGENERATE, "all percolation states are equal");
-
-    // d_v = C / S_v with S_v = C - sum_u |k_v - k_u| (the pairs that avoid v)
-    std::vector<uint64_t> cnt(65537, 0), sum(65537, 0);
-    for (int32_t v = 0; v < n; v++) { cnt[k[v] + 1]++; sum[k[v] + 1] += k[v]; }
-    for (int i = 0; i < 65536; i++) { cnt[i + 1] += cnt[i]; sum[i + 1] += sum[i]; }
-    std::vector<double> dv(n, 0.0), Svv(n, 0.0);
-    double dh = 1.0;
-    for (int32_t v = 0; v < n; v++) {
-        const uint64_t kv = k[v];
-        const uint64_t lo = cnt[kv] * kv - sum[kv];
-        const uint64_t hi = (sum[65536] - sum[kv + 1]) - (cnt[65536] - cnt[kv + 1]) * kv;
-        const uint64_t Sv = C - (lo + hi);
-        Svv[v] = (double)Sv;
-        dv[v] = Sv ? (double)C / (double)Sv : 0.0;
-        dh = std::max(dh, dv[v]);
+    int rc = graph_upload(c, G, false);
+    if (rc) return rc;
+    G.has_states = false;
+    G.states_on_device = false;
+    if (!G.d_k) {
+        if ((rc = dalloc(c, G.d_k, (size_t)n)) || (rc = dalloc(c, G.d_perm, (size_t)n + 1)) ||
+            (rc = dalloc(c, G.d_kr, (size_t)n + 2)) || (rc = dalloc(c, G.d_W, (size_t)n + 2)) ||
+            (rc = dalloc(c, G.d_P, (size_t)n + 1)) || (rc = dalloc(c, G.d_dv, (size_t)n)) ||
+            (rc = dalloc(c, G.d_Sv, (size_t)n)) || (rc = dalloc(c, G.d_p, (size_t)n)) ||
+            (rc = dalloc(c, G.d_red, 2))) {
+            graph_free_states(G);
+            return rc;
+        }
+        if (hipMalloc(&G.build_mem, (size_t)state_build_bytes(n)) != hipSuccess) {
+            (void)hipGetLastError();
+            G.build_mem = nullptr;
+            graph_free_states(G);
+            return fail(c, PERCIS_E_NOMEM, "cannot allocate the state-build scratch");
+        }
     }
-    graph_clear_states(G);
-    G.d_v.swap(dv);
-    G.S_v.swap(Svv);
-    G.h_k.swap(k);
-    G.d_hat = dh;
-    G.C = C;
-    G.h_perm.swap(perm);
-    G.h_kr.swap(kr);
-    G.h_W.swap(W);
-    G.h_P.swap(P);
+    HIPCHK(c, hipMemcpyAsync(G.d_k, k_in, sizeof(uint16_t) * n,
+                             (flags & PERCIS_DEVICE_PTRS) ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, c->stream));
+    StateArrays a;
+    a.n = n;
+    a.k = G.d_k;
+    a.newid = G.d_newid;
+    a.perm = G.d_perm;
+    a.kr = G.d_kr;
+    a.W = G.d_W;
+    a.P = G.d_P;
+    a.d_v = G.d_dv;
+    a.S_v = G.d_Sv;
+    const uint64_t* res = nullptr;
+    HIPCHK(c, launch_state_build(a, G.build_mem, &res, c->stream));
+    uint64_t h[2] = {0, 0};
+    HIPCHK(c, hipMemcpyAsync(h, res, sizeof h, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (h[0] == 0) return fail(c, PERCIS_E_DEGENERATE, "all percolation states are equal");
+    double dmax;
+    std::memcpy(&dmax, &h[1], sizeof dmax);
+    G.C = h[0];
+    G.d_hat = std::max(1.0, dmax);
     G.has_states = true;
+    G.states_on_device = true;
     return PERCIS_OK;
 }
 
@@ -225,8 +232,8 @@ int set_device(percis_ctx* c) {
     return PERCIS_OK;
 }
 
-// Uploads whatever of the graph (and, if `states`, the pair distribution) is
-// not on the device yet.
+// Uploads the graph if it is not on the device yet; with `states`, also
+// checks that the states (built on the device by set_states) are there.
 int graph_upload(percis_ctx* c, GraphData& G, bool states) {
     if (!G.has_graph) return fail(c, PERCIS_E_STATE, "load a graph first");
     if (states && !G.has_states) return fail(c, PERCIS_E_STATE, "set states first");
@@ -250,20 +257,12 @@ int graph_upload(percis_ctx* c, GraphData& G, bool states) {
         }
         if ((rc = dalloc(c, G.d_hits, (size_t)n))) return rc;
         if ((rc = dalloc(c, G.d_orig, (size_t)n))) return rc;
+        if ((rc = dalloc(c, G.d_newid, (size_t)n))) return rc;
         HIPCHK(c, hipMemcpy(G.d_orig, G.h_orig.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice));
+        HIPCHK(c, hipMemcpy(G.d_newid, G.h_newid.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice));
         G.graph_on_device = true;
     }
-    if (states && !G.states_on_device) {
-        if ((rc = dalloc(c, G.d_perm, (size_t)n + 1))) return rc;
-        if ((rc = dalloc(c, G.d_kr, (size_t)n + 2))) return rc;
-        if ((rc = dalloc(c, G.d_W, (size_t)n + 2))) return rc;
-        if ((rc = dalloc(c, G.d_P, (size_t)n + 1))) return rc;
-        HIPCHK(c, hipMemcpy(G.d_perm, G.h_perm.data(), sizeof(int32_t) * (n + 1), hipMemcpyHostToDevice));
-        HIPCHK(c, hipMemcpy(G.d_kr, G.h_kr.data(), sizeof(uint32_t) * (n + 2), hipMemcpyHostToDevice));
-        HIPCHK(c, hipMemcpy(G.d_W, G.h_W.data(), sizeof(uint64_t) * (n + 2), hipMemcpyHostToDevice));
-        HIPCHK(c, hipMemcpy(G.d_P, G.h_P.data(), sizeof(uint64_t) * (n + 1), hipMemcpyHostToDevice));
-        G.states_on_device = true;
-    }
+    if (states && !G.states_on_device) return fail(c, PERCIS_E_STATE, "set states first");
     return PERCIS_OK;
 }
 
@@ -434,51 +433,36 @@ static int ensure_slots(percis_ctx* c, int64_t act) {
 // Undirected: BFS per connected component from its smallest node u; the
 // component's shortest paths have at most min(|comp| - 2, 2 ecc(u) - 1)
 // internal nodes. Directed: largest weakly connected component size - 2.
-int64_t vertex_diam_ub(const GraphData& G) {
-    const int32_t n = G.n;
-    if (!G.directed) {
-        std::vector<int32_t> dist(n, -1), queue(n);
-        int64_t D = 0;
-        for (int32_t u = 0; u < n; u++) {
-            if (dist[u] >= 0) continue;
-            size_t head = 0, tail = 0;
-            dist[u] = 0;
-            queue[tail++] = u;
-            int32_t ecc = 0;
-            while (head < tail) {
-                int32_t x = queue[head++];
-                ecc = std::max(ecc, dist[x]);
-                for (int32_t e = G.h_rp[x]; e < G.h_rp[x + 1]; e++) {
-                    int32_t y = G.h_col[e];
-                    if (dist[y] < 0) {
-                        dist[y] = dist[x] + 1;
-                        queue[tail++] = y;
-                    }
-                }
-            }
-            int64_t Dc = std::min<int64_t>((int64_t)tail - 2, 2 * (int64_t)ecc - 1);
-            D = std::max(D, Dc);
-        }
-        return D;
+// VertexDiamUB (Algorithm 1) on the device, once per graph: D_override if
+// set, else the cached device result (the graph never changes after loading).
+// Undirected: per connected component, a BFS from its smallest node u; the
+// component's shortest paths have at most min(|comp| - 2, 2 ecc(u) - 1)
+// internal nodes. Directed: largest weakly connected component size - 2.
+int vertex_diam_ub(percis_ctx* c, GraphData& G, int64_t* D) {
+    if (G.D_override >= 0) {
+        *D = G.D_override;
+        return PERCIS_OK;
     }
-    std::vector<int32_t> parent(n);
-    for (int32_t v = 0; v < n; v++) parent[v] = v;
-    auto find = [&](int32_t x) {
-        while (parent[x] != x) {
-            parent[x] = parent[parent[x]];
-            x = parent[x];
-        }
-        return x;
-    };
-    for (int32_t u = 0; u < n; u++)
-        for (int32_t e = G.h_rp[u]; e < G.h_rp[u + 1]; e++) {
-            int32_t a = find(u), b = find(G.h_col[e]);
-            if (a != b) parent[std::max(a, b)] = std::min(a, b);
-        }
-    std::vector<int64_t> size(n, 0);
-    int64_t best = 0;
-    for (int32_t v = 0; v < n; v++) best = std::max(best, ++size[find(v)]);
-    return std::max<int64_t>(0, best - 2);
+    if (G.D_cached >= 0) {
+        *D = G.D_cached;
+        return PERCIS_OK;
+    }
+    int rc = graph_upload(c, G, false);
+    if (rc) return rc;
+    void* scratch = nullptr;
+    if (hipMalloc(&scratch, (size_t)diam_scratch_bytes(G.n_act)) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(c, PERCIS_E_NOMEM, "cannot allocate the VertexDiamUB scratch");
+    }
+    int64_t d = 0;
+    int32_t levels = 0, rounds = 0;
+    const hipError_t e =
+        run_vertex_diam_ub(G.d_rp, G.d_col, G.n_act, G.m, G.directed, scratch, &d, &levels, &rounds, c->stream);
+    (void)hipFree(scratch);
+    if (e != hipSuccess) return fail(c, PERCIS_E_DEVICE, "VertexDiamUB: %s", hipGetErrorString(e));
+    G.D_cached = d;
+    *D = d;
+    return PERCIS_OK;
 }
 
 // Theorem 1 with the constants of Algorithm 1, as a function of x.
@@ -520,9 +504,19 @@ static double sample_size_sup(double d, double rho, double v, double eps, double
 }
 
 // Propositions 2 and 3 and Theorem 1 (with the constants of Algorithm 1)
-// from the phase-1 hits and |I| sums; I->D must be set.
-void bounds_from_phase1(const GraphData& G, uint64_t l1u, uint64_t sum_I, uint64_t sum_I2, const uint32_t* h1,
-                        double eps, double delta, percis_estimate_info* I) {
+// from the phase-1 |I| sums and hits (device); I->D must be set. The bound of
+// Proposition 3 is non-decreasing in p1 = d_v h_v / l1 (in floating point
+// too: every operation in it is monotone), so its maximum over v is its value
+// at max_v d_v h_v, which a device reduction provides.
+int phase1_bounds(percis_ctx* c, const GraphData& G, uint64_t l1u, uint64_t sum_I, uint64_t sum_I2,
+                  const uint32_t* d_hits1, double eps, double delta, percis_estimate_info* I) {
+    HIPCHK(c, launch_fill_u32((uint32_t*)G.d_red, 0u, 2, c->stream));
+    HIPCHK(c, launch_hit_weight_max(G.d_dv, d_hits1, G.n, G.d_red, c->stream));
+    uint64_t bits = 0;
+    HIPCHK(c, hipMemcpyAsync(&bits, G.d_red, sizeof bits, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    double hw;
+    std::memcpy(&hw, &bits, sizeof hw);
     const double l1 = (double)l1u;
     I->l1 = l1u;
     I->d_hat = G.d_hat;
@@ -531,14 +525,21 @@ void bounds_from_phase1(const GraphData& G, uint64_t l1u, uint64_t sum_I, uint64
     I->Lambda = (double)num / (l1 * (l1 - 1.0));
     const double L8 = std::log(8.0 / delta), L4 = std::log(4.0 / delta);
     I->rho_hat = I->rho_tilde + std::sqrt(2.0 * I->Lambda * L8 / l1) + 7.0 * (double)I->D * L8 / (3.0 * (l1 - 1.0));
-    double vmax = 0.0;
-    for (int32_t v = 0; v < G.n; v++) {
-        const double p1 = G.d_v[v] * h1[v] / l1;
-        vmax = std::max(vmax, p1 + std::sqrt(2.0 * p1 * L4 / l1) + L4 / (3.0 * l1));
-    }
+    const double p1 = hw / l1;
+    const double vmax = p1 + std::sqrt(2.0 * p1 * L4 / l1) + L4 / (3.0 * l1);
     I->v_hat = G.d_hat * G.d_hat * vmax;
     const double lb = sample_size_sup(G.d_hat, I->rho_hat, I->v_hat, eps, delta, &I->x_hat);
     I->l = lb < 4294967295.0 ? (uint64_t)std::ceil(lb) : ~0ull;
+    return PERCIS_OK;
+}
+
+// p_out[v] = d_v h_v / l (Algorithm 1's estimate), computed on the device and
+// copied to the host array p_out.
+int estimates_to_host(percis_ctx* c, const GraphData& G, const uint32_t* d_hits, uint64_t l, double* p_out) {
+    HIPCHK(c, launch_estimates(G.d_dv, d_hits, G.n, l, G.d_p, c->stream));
+    HIPCHK(c, hipMemcpyAsync(p_out, G.d_p, sizeof(double) * G.n, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return PERCIS_OK;
 }
 
 static void stats_from_dev(const DevStats& hs, percis_stats* st) {
@@ -698,10 +699,8 @@ static int estimate_graph(percis_ctx* c, int32_t id, double eps, double delta, u
     if (rc) return rc;
     auto t0 = std::chrono::steady_clock::now();
     percis_estimate_info I{};
-    const int32_t n = G->n;
-    I.D = G->D_override >= 0 ? G->D_override : vertex_diam_ub(*G);
+    if ((rc = vertex_diam_ub(c, *G, &I.D))) return rc;
     I.d_hat = G->d_hat;
-    std::vector<uint32_t> h(n);
     std::vector<TaskSpec> one(1);
     percis_stats s1{};
     if (di) {
@@ -721,10 +720,9 @@ static int estimate_graph(percis_ctx* c, int32_t id, double eps, double delta, u
             if (info) *info = I;
             return rc;
         }
-        HIPCHK(c, hipMemcpy(h.data(), G->d_hits, sizeof(uint32_t) * n, hipMemcpyDeviceToHost));
         I.phase1_ms = s1.kernel_ms;
         auto tb = std::chrono::steady_clock::now();
-        bounds_from_phase1(*G, I.l1, ts[0].sum_I, ts[0].sum_I2, h.data(), eps, delta, &I);
+        if ((rc = phase1_bounds(c, *G, I.l1, ts[0].sum_I, ts[0].sum_I2, G->d_hits, eps, delta, &I))) return rc;
         auto te = std::chrono::steady_clock::now();
         I.bounds_ms = std::chrono::duration<double, std::milli>(te - tb).count();
     }
@@ -742,8 +740,7 @@ static int estimate_graph(percis_ctx* c, int32_t id, double eps, double delta, u
         if (info) *info = I;
         return rc;
     }
-    HIPCHK(c, hipMemcpy(h.data(), G->d_hits, sizeof(uint32_t) * n, hipMemcpyDeviceToHost));
-    for (int32_t v = 0; v < n; v++) p_out[v] = G->d_v[v] * (double)h[v] / (double)I.l;
+    if ((rc = estimates_to_host(c, *G, G->d_hits, I.l, p_out))) return rc;
     I.total_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     if (info) *info = I;
     return PERCIS_OK;
@@ -980,6 +977,37 @@ int percis_graph_set_vertex_diameter(percis_ctx* c, int32_t graph, int64_t D) {
     return PERCIS_OK;
 }
 
+int percis_graph_vertex_diameter(percis_ctx* c, int32_t graph, int64_t* D) {
+    if (!c || !D) return PERCIS_E_INVAL;
+    GraphData* G = get_graph(c, graph);
+    if (!G || !G->has_graph) return fail(c, PERCIS_E_INVAL, "no graph %d", graph);
+    return vertex_diam_ub(c, *G, D);
+}
+
+int percis_debug_states(percis_ctx* c, int32_t graph, int32_t* perm, uint32_t* kr, uint64_t* W, uint64_t* P,
+                        double* d_v, double* S_v, uint64_t* C, double* d_hat) {
+    if (!c) return PERCIS_E_INVAL;
+    GraphData* G = get_graph(c, graph);
+    if (!G || !G->has_graph || !G->has_states) return fail(c, PERCIS_E_STATE, "graph %d has no states", graph);
+    int rc = graph_upload(c, *G, true);
+    if (rc) return rc;
+    const int32_t n = G->n;
+    if (perm) {
+        HIPCHK(c, hipMemcpyAsync(perm, G->d_perm, sizeof(int32_t) * (n + 1), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        for (int32_t i = 1; i <= n; i++) perm[i] = G->h_orig[perm[i]];
+    }
+    if (kr) HIPCHK(c, hipMemcpyAsync(kr, G->d_kr, sizeof(uint32_t) * (n + 2), hipMemcpyDeviceToHost, c->stream));
+    if (W) HIPCHK(c, hipMemcpyAsync(W, G->d_W, sizeof(uint64_t) * (n + 2), hipMemcpyDeviceToHost, c->stream));
+    if (P) HIPCHK(c, hipMemcpyAsync(P, G->d_P, sizeof(uint64_t) * (n + 1), hipMemcpyDeviceToHost, c->stream));
+    if (d_v) HIPCHK(c, hipMemcpyAsync(d_v, G->d_dv, sizeof(double) * n, hipMemcpyDeviceToHost, c->stream));
+    if (S_v) HIPCHK(c, hipMemcpyAsync(S_v, G->d_Sv, sizeof(double) * n, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (C) *C = G->C;
+    if (d_hat) *d_hat = G->d_hat;
+    return PERCIS_OK;
+}
+
 int percis_estimate(percis_ctx* c, double eps, double delta, uint64_t seed, double* p_out, percis_estimate_info* info) {
     if (!c) return PERCIS_E_INVAL;
     return estimate_graph(c, 0, eps, delta, seed, p_out, info);
@@ -1124,8 +1152,6 @@ int percis_exact(percis_ctx* c, int32_t graph, double* p_out, double* kernel_ms)
     if (rc) return rc;
     const int32_t n = G->n, na = std::max<int32_t>(G->n_act, 1);
     const int64_t stride = ((int64_t)na + 63) / 64 * 64;
-    std::vector<uint16_t> kint(n);
-    for (int32_t v = 0; v < n; v++) kint[G->h_newid[v]] = G->h_k[v];
     uint16_t* d_k = nullptr;
     double* d_out = nullptr;
     void* scratch = nullptr;
@@ -1149,23 +1175,19 @@ int percis_exact(percis_ctx* c, int32_t graph, double* p_out, double* kernel_ms)
         cleanup();
         return fail(c, PERCIS_E_NOMEM, "cannot allocate %lld bytes of scratch", (long long)bytes);
     }
-    hipError_t e = hipMemcpyAsync(d_k, kint.data(), sizeof(uint16_t) * n, hipMemcpyHostToDevice, c->stream);
+    hipError_t e = launch_states_internal(G->d_k, G->d_newid, n, d_k, c->stream);
     if (e == hipSuccess) e = launch_fill_u8(scratch, bytes, c->stream);
     if (e == hipSuccess) e = launch_init_stats(c->d_stats, c->d_work, c->stream);
     if (e == hipSuccess) e = hipEventRecord(c->ev0, c->stream);
     if (e == hipSuccess) e = launch_exact(dev_graph(*G), d_k, scratch, stride, slots, c->d_work, d_out, c->stream);
     if (e == hipSuccess) e = hipEventRecord(c->ev1, c->stream);
-    std::vector<double> num(na);
-    if (e == hipSuccess) e = hipMemcpyAsync(num.data(), d_out, sizeof(double) * na, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = launch_exact_finish(d_out, G->d_Sv, G->d_newid, n, G->n_act, G->d_p, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(p_out, G->d_p, sizeof(double) * n, hipMemcpyDeviceToHost, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     float ms = 0.f;
     if (e == hipSuccess) e = hipEventElapsedTime(&ms, c->ev0, c->ev1);
     cleanup();
     if (e != hipSuccess) return fail(c, PERCIS_E_DEVICE, "exact centrality: %s", hipGetErrorString(e));
-    for (int32_t v = 0; v < n; v++) {
-        const int32_t i = G->h_newid[v];
-        p_out[v] = (i < G->n_act && G->S_v[v] > 0) ? num[i] / G->S_v[v] : 0.0;
-    }
     if (kernel_ms) *kernel_ms = ms;
     return PERCIS_OK;
 }

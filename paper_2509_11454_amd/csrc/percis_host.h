@@ -10,8 +10,9 @@
 
 namespace percis {
 
-// One graph with its states: host copies in internal ids (nodes with arcs
-// first, caller order kept) and their device copies.
+// One graph with its states: the graph's host copy in internal ids (nodes
+// with arcs first, caller order kept) and its device copy; the states and
+// everything derived from them live on the device only.
 struct GraphData {
     bool has_graph = false, directed = false;
     int32_t n = 0, n_act = 0;
@@ -23,21 +24,25 @@ struct GraphData {
     int32_t *d_rp = nullptr, *d_col = nullptr, *d_irp = nullptr, *d_icol = nullptr, *d_orig = nullptr;
     uint32_t* d_hits = nullptr;            // hits buffer owned by the library
 
+    int32_t* d_newid = nullptr;            // caller id -> internal id (device)
+
+    // States and the pair distribution, device-resident (built on the device
+    // from k; a host-only context only validates states).
     bool has_states = false;
-    uint64_t C = 0;
-    std::vector<double> d_v;               // C / S_v by caller id, 0 where S_v = 0
-    std::vector<double> S_v;               // S_v by caller id (units of 1/65535)
-    std::vector<uint16_t> h_k;             // states by caller id
-    double d_hat = 1.0;
-    std::vector<int32_t> h_perm;           // rank -> internal id
-    std::vector<uint32_t> h_kr;
-    std::vector<uint64_t> h_W, h_P;
+    uint64_t C = 0;                        // total pair weight (units of 1/65535)
+    double d_hat = 1.0;                    // max(1, max_v C / S_v)
     bool states_on_device = false;
-    int32_t* d_perm = nullptr;
+    uint16_t* d_k = nullptr;               // states by caller id
+    int32_t* d_perm = nullptr;             // rank -> internal id
     uint32_t* d_kr = nullptr;
     uint64_t *d_W = nullptr, *d_P = nullptr;
+    double *d_dv = nullptr, *d_Sv = nullptr;  // C / S_v and S_v by caller id
+    void* build_mem = nullptr;             // scratch of the state build
+    double* d_p = nullptr;                 // staging of the estimates, by caller id
+    unsigned long long* d_red = nullptr;   // reduction word
 
     int64_t D_override = -1;
+    int64_t D_cached = -1;                 // VertexDiamUB (the graph never changes after loading)
 };
 
 // A task as the host sees it: a sample range of one graph into device hits.
@@ -53,7 +58,7 @@ struct TaskSpec {
 
 struct percis_ctx {
     int device = 0;
-    bool host_only = false;                // created with PERCIS_HOST_ONLY: validation and host math only
+    bool host_only = false;                // created with PERCIS_HOST_ONLY: input validation only
     hipStream_t stream = nullptr;
     std::string err;
     int cu_count = 0;
@@ -122,8 +127,9 @@ int set_device(percis_ctx* c);
 int graph_upload(percis_ctx* c, GraphData& G, bool states);
 GraphData* get_graph(percis_ctx* c, int32_t id);
 int run_tasks(percis_ctx* c, const std::vector<TaskSpec>& tasks, std::vector<percis_stats>* out, percis_stats* launch);
-void bounds_from_phase1(const GraphData& G, uint64_t l1, uint64_t sum_I, uint64_t sum_I2, const uint32_t* h1,
-                        double eps, double delta, percis_estimate_info* I);
-int64_t vertex_diam_ub(const GraphData& G);
+int phase1_bounds(percis_ctx* c, const GraphData& G, uint64_t l1, uint64_t sum_I, uint64_t sum_I2,
+                  const uint32_t* d_hits1, double eps, double delta, percis_estimate_info* I);
+int vertex_diam_ub(percis_ctx* c, GraphData& G, int64_t* D);
+int estimates_to_host(percis_ctx* c, const GraphData& G, const uint32_t* d_hits, uint64_t l, double* p_out);
 
 }  // namespace percis

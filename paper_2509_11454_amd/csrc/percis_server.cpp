@@ -60,7 +60,6 @@ struct percis_server {
     std::deque<Query*> queued;
     std::vector<Query*> active;                     // admission order
     std::unordered_map<int64_t, Query*> by_id;
-    std::unordered_map<int32_t, int64_t> diam;      // VertexDiamUB per graph
     uint64_t samples_done = 0;
     double kernel_ms = 0;
     int64_t peak_in_use = 0;
@@ -74,15 +73,6 @@ void release(percis_server* s, Query* q) {
         q->d_hits = nullptr;
         s->in_use -= q->bytes;
     }
-}
-
-int64_t diameter_of(percis_server* s, int32_t graph) {
-    auto it = s->diam.find(graph);
-    if (it != s->diam.end()) return it->second;
-    GraphData* G = get_graph(s->ctx, graph);
-    const int64_t D = G->D_override >= 0 ? G->D_override : vertex_diam_ub(*G);
-    s->diam[graph] = D;
-    return D;
 }
 
 // Admits queued queries in arrival order while their buffers fit.
@@ -111,7 +101,6 @@ int admit(percis_server* s) {
         s->in_use += q->bytes;
         s->peak_in_use = std::max(s->peak_in_use, s->in_use);
         q->state = PHASE1;
-        q->info.D = diameter_of(s, q->graph);
         q->info.l1 = (uint64_t)std::ceil(std::max(1000.0, std::log(1.0 / q->delta) / q->eps));
         q->target = q->info.l1;
         q->next = 0;
@@ -161,8 +150,11 @@ int percis_server_submit(percis_server* s, int32_t graph, double eps, double del
     if (!(eps > 0 && eps < 1) || !(delta > 0 && delta < 1)) return fail(c, PERCIS_E_INVAL, "need 0 < eps, delta < 1");
     int rc = graph_upload(c, *G, true);
     if (rc) return rc;
+    int64_t D = 0;
+    if ((rc = vertex_diam_ub(c, *G, &D))) return rc;
     Query* q = new (std::nothrow) Query();
     if (!q) return fail(c, PERCIS_E_NOMEM, "out of host memory");
+    q->info.D = D;
     q->id = s->next_id++;
     q->graph = graph;
     q->eps = eps;
@@ -216,14 +208,13 @@ int percis_server_step(percis_server* s, int32_t* completed) {
         q->overflow += ts[i].overflow;
         if (q->next < q->target) continue;
         GraphData& G = *get_graph(c, q->graph);
-        std::vector<uint32_t> h(G.n);
-        HIPCHK(c, hipMemcpy(h.data(), q->d_hits, sizeof(uint32_t) * G.n, hipMemcpyDeviceToHost));
         if (q->overflow) {
             q->state = FAILED;
             q->status = PERCIS_E_SIGMA_OVERFLOW;
             q->info.overflow = q->overflow;
         } else if (q->state == PHASE1) {
-            bounds_from_phase1(G, q->info.l1, q->sum_I, q->sum_I2, h.data(), q->eps, q->delta, &q->info);
+            if ((rc = phase1_bounds(c, G, q->info.l1, q->sum_I, q->sum_I2, q->d_hits, q->eps, q->delta, &q->info)))
+                return rc;
             if (q->info.l >= 4294967295ull) {
                 q->state = FAILED;
                 q->status = PERCIS_E_TOO_LARGE;
@@ -235,7 +226,7 @@ int percis_server_step(percis_server* s, int32_t* completed) {
             }
         } else {
             q->p.resize(G.n);
-            for (int32_t v = 0; v < G.n; v++) q->p[v] = G.d_v[v] * (double)h[v] / (double)q->info.l;
+            if ((rc = estimates_to_host(c, G, q->d_hits, q->info.l, q->p.data()))) return rc;
             q->state = DONE;
             q->info.total_ms =
                 std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - q->t_submit).count();

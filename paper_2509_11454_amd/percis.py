@@ -84,6 +84,8 @@ _SIGS = {
     "percis_set_vertex_diameter": (C.c_int, [_P, C.c_int64]),
     "percis_debug_path": (C.c_int, [_P, C.c_int32, C.c_int32, C.c_uint64, _P, C.c_int32,
                                     C.POINTER(C.c_int32), C.POINTER(C.c_uint64), C.POINTER(C.c_int32)]),
+    "percis_graph_vertex_diameter": (C.c_int, [_P, C.c_int32, _P]),
+    "percis_debug_states": (C.c_int, [_P, C.c_int32, _P, _P, _P, _P, _P, _P, _P, _P]),
     "percis_debug_path_wide": (C.c_int, [_P, C.c_int32, C.c_int32, C.c_uint64, C.c_uint64, _P, C.c_int32,
                                          C.POINTER(C.c_int32), C.POINTER(C.c_uint64), C.POINTER(C.c_uint64),
                                          C.POINTER(C.c_int32)]),
@@ -250,6 +252,28 @@ class Context:
         L, sig, ovf = int(L.value), (int(hi.value) << 64) | int(lo.value), int(ovf.value)
         path = [int(v) for v in buf[:L + 1]] if (L >= 0 and not ovf and r < sig and L + 1 <= cap) else None
         return L, sig, ovf, path
+
+    def vertex_diameter(self, graph=0):
+        """VertexDiamUB of graph `graph` (the override if set, else the
+        device-computed bound)."""
+        D = C.c_int64()
+        self._check(_lib.percis_graph_vertex_diameter(self._h, int(graph), C.byref(D)))
+        return int(D.value)
+
+    def debug_states(self, graph=0):
+        """The device-built pair distribution of graph `graph` as numpy arrays:
+        perm (caller ids), kr, W, P, d_v, S_v, and the scalars C, d_hat."""
+        n = self.graph_info(graph)[0]
+        perm = np.zeros(n + 1, np.int32)
+        kr = np.zeros(n + 2, np.uint32)
+        W = np.zeros(n + 2, np.uint64)
+        P = np.zeros(n + 1, np.uint64)
+        dv = np.zeros(n, np.float64)
+        Sv = np.zeros(n, np.float64)
+        Cv, dh = C.c_uint64(), C.c_double()
+        self._check(_lib.percis_debug_states(self._h, int(graph), _np_ptr(perm), _np_ptr(kr), _np_ptr(W), _np_ptr(P),
+                                             _np_ptr(dv), _np_ptr(Sv), C.byref(Cv), C.byref(dh)))
+        return dict(perm=perm, kr=kr, W=W, P=P, d_v=dv, S_v=Sv, C=int(Cv.value), d_hat=float(dh.value))
 
     def add_graph(self, n, row_ptr, col, k, directed=False):
         """Adds a graph with its states; returns its id."""
