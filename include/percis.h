@@ -264,7 +264,7 @@ int percis_exact(percis_ctx* ctx, int32_t graph, double* p_out, double* kernel_m
 /* Tuning knobs (launch shape only; results never depend on them).
  * PERCIS_OPT_SLOTS: concurrent samples (resident workgroups), 0 = auto.
  * PERCIS_OPT_SCRATCH_MB: cap on the sampler's scratch memory, 0 = auto.
- * PERCIS_OPT_BLOCK: threads per sample (128, 256, 512 or 1024), 0 = auto.
+ * PERCIS_OPT_BLOCK: threads per sample (64, 128, 256, 512 or 1024), 0 = auto.
  * PERCIS_OPT_BITMAPS: how a sample's visited sets are kept: 1 = one bitmap
  * per side in device memory; 2 = an exact hash table per side in LDS (8 KB
  * per sample), moved to the device bitmap if a side grows past 768 nodes;

@@ -1106,8 +1106,8 @@ int percis_set_option(percis_ctx* c, int option, int64_t value) {
         case PERCIS_OPT_SLOTS: c->opt_slots = value; break;
         case PERCIS_OPT_SCRATCH_MB: c->opt_scratch_mb = value; break;
         case PERCIS_OPT_BLOCK:
-            if (value != 0 && value != 128 && value != 256 && value != 512 && value != 1024)
-                return fail(c, PERCIS_E_INVAL, "block must be 128, 256, 512 or 1024");
+            if (value != 0 && value != 64 && value != 128 && value != 256 && value != 512 && value != 1024)
+                return fail(c, PERCIS_E_INVAL, "block must be 64, 128, 256, 512 or 1024");
             c->opt_block = value;
             break;
         case PERCIS_OPT_BITMAPS:

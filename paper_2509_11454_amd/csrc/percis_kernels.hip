@@ -56,32 +56,77 @@ constexpr int KCAP = 64;        // predecessors a walk step gathers from the arc
 // a workgroup-scope atomic: coherent among the workgroup's waves without the
 // device-wide cache maintenance that agent scope costs on a multi-XCD part.
 #define WGS __HIP_MEMORY_SCOPE_WORKGROUP
-__device__ __forceinline__ uint32_t ld32(uint32_t* p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, WGS); }
-__device__ __forceinline__ uint64_t ld64(uint64_t* p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, WGS); }
-__device__ __forceinline__ int32_t ldq(int32_t* p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, WGS); }
-__device__ __forceinline__ uint32_t or32(uint32_t* p, uint32_t v) {
+
+// Device memory through typed global pointers. A pointer loaded from a struct
+// in memory is generic to the compiler, and a generic (flat) access counts
+// against the LDS counter as well, so that every wait for an LDS result would
+// also wait for the outstanding global loads. The sampler converts its graph
+// and slot pointers into these views once.
+template <class T>
+using G = __attribute__((address_space(1))) T;
+template <class T>
+__device__ __forceinline__ G<T>* gptr(T* p) { return (G<T>*)p; }
+// 16-byte records move as one vector access (a class type cannot be copied
+// through an address-space-qualified pointer).
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+template <class T>
+__device__ __forceinline__ const G<T>* gptr(const T* p) { return (const G<T>*)p; }
+
+__device__ __forceinline__ uint32_t ld32(G<uint32_t>* p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, WGS); }
+__device__ __forceinline__ uint64_t ld64(G<uint64_t>* p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, WGS); }
+__device__ __forceinline__ int32_t ldq(G<int32_t>* p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, WGS); }
+__device__ __forceinline__ uint32_t or32(G<uint32_t>* p, uint32_t v) {
     return __hip_atomic_fetch_or(p, v, __ATOMIC_RELAXED, WGS);
 }
-__device__ __forceinline__ uint64_t add64(uint64_t* p, uint64_t v) {
+__device__ __forceinline__ uint64_t add64(G<uint64_t>* p, uint64_t v) {
     return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, WGS);
 }
 
 // Field access by side: 0 = s side, 1 = t side.
 template <int SIDE>
-__device__ __forceinline__ uint32_t* LV(NodeRec* R, int32_t w) { return SIDE ? &R[w].lv_t : &R[w].lv_s; }
+__device__ __forceinline__ G<uint32_t>* LV(G<NodeRec>* R, int32_t w) { return SIDE ? &R[w].lv_t : &R[w].lv_s; }
 template <int SIDE>
-__device__ __forceinline__ uint64_t* SG(NodeRec* R, int32_t w) { return SIDE ? &R[w].sg_t : &R[w].sg_s; }
+__device__ __forceinline__ G<uint64_t>* SG(G<NodeRec>* R, int32_t w) { return SIDE ? &R[w].sg_t : &R[w].sg_s; }
+
+// The graph and a slot's scratch as typed global views.
+struct GGraph {
+    int32_t n, n_act;
+    const G<int32_t>* rp;
+    const G<int32_t>* col;
+    const G<int32_t>* irp;
+    const G<int32_t>* icol;
+    const G<int32_t>* orig;
+};
+__device__ __forceinline__ GGraph gview(const DevGraph& g) {
+    return GGraph{g.n, g.n_act, gptr(g.rp), gptr(g.col), gptr(g.irp), gptr(g.icol), gptr(g.orig)};
+}
+struct GSlots {
+    G<NodeRec>* rec;
+    G<int32_t>* q_s;
+    G<int32_t>* q_t;
+    G<int32_t>* q_d;
+    G<int32_t>* tls;
+    int64_t stride;
+    G<uint32_t>* bm;
+    int64_t words;
+    G<DagArc>* arcs;
+    int32_t acap;
+};
+__device__ __forceinline__ GSlots sview(const DevSlots& s) {
+    return GSlots{gptr(s.rec), gptr(s.q_s), gptr(s.q_t), gptr(s.q_d), gptr(s.tls), s.stride,
+                  gptr(s.bm),  s.words,     gptr(s.arcs), s.acap};
+}
 
 // Bitmap operations on one plane of a slot's device bitmaps.
 struct Bits {
-    __device__ __forceinline__ static uint32_t rd(uint32_t* p, int32_t w) {
+    __device__ __forceinline__ static uint32_t rd(G<uint32_t>* p, int32_t w) {
         return __hip_atomic_load(p + (w >> 5), __ATOMIC_RELAXED, WGS);
     }
-    __device__ __forceinline__ static uint32_t set(uint32_t* p, int32_t w) {
+    __device__ __forceinline__ static uint32_t set(G<uint32_t>* p, int32_t w) {
         return __hip_atomic_fetch_or(p + (w >> 5), 1u << (w & 31), __ATOMIC_RELAXED, WGS);
     }
     __device__ __forceinline__ static bool test(uint32_t word, int32_t w) { return (word >> (w & 31)) & 1u; }
-    __device__ __forceinline__ static void clear_word(uint32_t* p, int32_t w) {
+    __device__ __forceinline__ static void clear_word(G<uint32_t>* p, int32_t w) {
         __hip_atomic_store(p + (w >> 5), 0u, __ATOMIC_RELAXED, WGS);
     }
 };
@@ -93,15 +138,23 @@ struct Bits {
 // the last level keeps only its meeting layer. A side whose table would fill
 // up is spilled to its device bitmap plane (every node of the side is in its
 // queue) and uses the bitmap from then on.
-constexpr int HBITS = 10;
+#ifndef PERCIS_HBITS
+#define PERCIS_HBITS 10
+#endif
+constexpr int HBITS = PERCIS_HBITS;
 constexpr int HCAP = 1 << HBITS;       // table slots per side
 constexpr int HLIMIT = 3 * HCAP / 4;   // most entries a table takes
 constexpr int HADMIT = 5 * HCAP / 8;   // a level decides first visits by the table if it cannot add more
 template <bool LDS>
 struct Vis {
-    uint32_t* bm[2];   // device bitmap planes
-    uint32_t* tab[2];  // LDS tables (LDS = true)
+    G<uint32_t>* bm[2];   // device bitmap planes
 };
+
+// The two LDS tables (LDS = true) lie in the workgroup's dynamic LDS, side 0
+// first; they are addressed from the array itself so that the compiler keeps
+// their accesses in LDS.
+extern __shared__ uint32_t dyn_lds[];
+__device__ __forceinline__ uint32_t* tab(int side) { return dyn_lds + side * HCAP; }
 
 __device__ __forceinline__ uint32_t hslot(int32_t x) { return ((uint32_t)x * 0x9E3779B1u) >> (32 - HBITS); }
 
@@ -242,15 +295,16 @@ struct SampleShared {
 template <bool LDS>
 __device__ __forceinline__ bool member(const Vis<LDS>& V, const SampleShared& sh, int side, int32_t x) {
     if (!LDS || sh.spilled[side]) return Bits::test(Bits::rd(V.bm[side], x), x);
-    return table_has(V.tab[side], x);
+    return table_has(tab(side), x);
 }
 
 // Records the DAG arc tail -> head weighed by sigma_s(tail) = w; arcs past the
 // slot's capacity are dropped (the walk then scans in-rows instead).
-__device__ __forceinline__ void record_arc(DagArc* arcs, int32_t acap, SampleShared& sh, int32_t tail, int32_t head,
+__device__ __forceinline__ void record_arc(G<DagArc>* arcs, int32_t acap, SampleShared& sh, int32_t tail, int32_t head,
                                            uint64_t w) {
     const int i = atomicAdd(&sh.narcs, 1);
-    if (i < acap) arcs[i] = DagArc{tail, head, w};
+    if (i < acap)
+        *reinterpret_cast<G<u32x4>*>(arcs + i) = u32x4{(uint32_t)tail, (uint32_t)head, (uint32_t)w, (uint32_t)(w >> 32)};
 }
 
 // Thread 0 only.
@@ -316,7 +370,7 @@ __device__ __forceinline__ uint64_t wave_incl_scan_u64(uint64_t v) {
 // returns the number of adjacency entries of the chunk. Every thread must
 // call it.
 template <int BSZ, int SIDE>
-__device__ __forceinline__ int stage_chunk(int32_t* q, int base, int cnt, const int32_t* rp, NodeRec* R,
+__device__ __forceinline__ int stage_chunk(G<int32_t>* q, int base, int cnt, const G<int32_t>* rp, G<NodeRec>* R,
                                            bool read_ovf, SampleShared& sh, Counters& cn) {
     const int tid = threadIdx.x;
     int deg = 0, beg = 0;
@@ -383,17 +437,17 @@ __device__ __forceinline__ void wave_sum_wrap(uint64_t& v, uint32_t& wrap) {
 // when that sum reached 2^64. The level's own sum and degree sum (the
 // degrees its expansion will scan) are gathered on the way.
 template <int SIDE, int BSZ, bool LDS>
-__device__ void expand_bfs(const DevGraph& g, const DevSlots& sl, int64_t so, const Vis<LDS>& V, int lo, int hi,
+__device__ void expand_bfs(const GGraph& g, const GSlots& sl, int64_t so, const Vis<LDS>& V, int lo, int hi,
                            uint32_t nl, bool careful, SampleShared& sh, Counters& cn) {
     using B = Bits;
     const int tid = threadIdx.x;
     const bool by_table = LDS && sh.level_table;   // else: bitmap (device mode) or record CAS (LDS mode)
-    DagArc* arcs = sl.arcs + (int64_t)blockIdx.x * sl.acap;
-    const int32_t* rp = SIDE ? g.irp : g.rp;
-    const int32_t* col = SIDE ? g.icol : g.col;
-    int32_t* q = (SIDE ? sl.q_t : sl.q_s) + so;
-    NodeRec* R = sl.rec + so;
-    uint32_t* vis_mine = V.bm[SIDE];
+    G<DagArc>* arcs = sl.arcs + (int64_t)blockIdx.x * sl.acap;
+    const G<int32_t>* rp = SIDE ? g.irp : g.rp;
+    const G<int32_t>* col = SIDE ? g.icol : g.col;
+    G<int32_t>* q = (SIDE ? sl.q_t : sl.q_s) + so;
+    G<NodeRec>* R = sl.rec + so;
+    G<uint32_t>* vis_mine = V.bm[SIDE];
     uint64_t mass = 0, dsum = 0;
     uint32_t wrap = 0;
 
@@ -446,7 +500,7 @@ __device__ void expand_bfs(const DevGraph& g, const DevSlots& sl, int64_t so, co
                         add = lv == 0 || lv == nl;
                     }
                 } else if (by_table) {
-                    fresh = table_visit(V.tab[SIDE], &sh.hcnt[SIDE], x);
+                    fresh = table_visit(tab(SIDE), &sh.hcnt[SIDE], x);
                     if (fresh) {
                         add = true;
                     } else {
@@ -462,7 +516,7 @@ __device__ void expand_bfs(const DevGraph& g, const DevSlots& sl, int64_t so, co
                     lv_written = true;
                     if (fresh) {
                         if (sh.spilled[SIDE]) (void)B::set(vis_mine, x);
-                        else if (!table_put(V.tab[SIDE], &sh.hcnt[SIDE], x)) sh.spill_req[SIDE] = 1;
+                        else if (!table_put(tab(SIDE), &sh.hcnt[SIDE], x)) sh.spill_req[SIDE] = 1;
                     }
                 }
                 if (add) {
@@ -522,12 +576,12 @@ __device__ void expand_bfs(const DevGraph& g, const DevSlots& sl, int64_t so, co
 // want = j + 1). Counts of nodes off the shortest-path DAG are 0, so only
 // DAG arcs add. No count here exceeds sigma_st, known to be below 2^64.
 template <int BSZ, bool LDS>
-__device__ void pull_level(const DevGraph& g, const DevSlots& sl, int64_t so, const Vis<LDS>& V, int lo, int hi,
+__device__ void pull_level(const GGraph& g, const GSlots& sl, int64_t so, const Vis<LDS>& V, int lo, int hi,
                            uint32_t want, SampleShared& sh, Counters& cn) {
     const int tid = threadIdx.x;
-    int32_t* q = sl.q_t + so;
-    NodeRec* R = sl.rec + so;
-    DagArc* arcs = sl.arcs + (int64_t)blockIdx.x * sl.acap;
+    G<int32_t>* q = sl.q_t + so;
+    G<NodeRec>* R = sl.rec + so;
+    G<DagArc>* arcs = sl.arcs + (int64_t)blockIdx.x * sl.acap;
     constexpr int CHK = chunk_len<BSZ>();
     for (int base = lo; base < hi; base += CHK) {
         const int cnt = min(CHK, hi - base);
@@ -554,7 +608,7 @@ __device__ void pull_level(const DevGraph& g, const DevSlots& sl, int64_t so, co
             if (!member<LDS>(V, sh, 1, u)) continue;
             // levels of this level's nodes are final (set before the last
             // barrier); their sigma_s was completed by the previous pull level
-            const uint4 rec = *reinterpret_cast<const uint4*>(&R[u]);
+            const u32x4 rec = *reinterpret_cast<const G<u32x4>*>(&R[u]);
             if ((rec.y & LVMASK) != want) continue;
             const uint64_t su = ((uint64_t)rec.w << 32) | rec.z;
             if (su) {
@@ -572,12 +626,12 @@ __device__ void pull_level(const DevGraph& g, const DevSlots& sl, int64_t so, co
 // of t-level b - 1): every meeting node w adds sigma_s(w) to its
 // out-neighbours at t-level b - 1 (t-level value want = b).
 template <int BSZ, bool LDS>
-__device__ void push_meeting(const DevGraph& g, const DevSlots& sl, int64_t so, const Vis<LDS>& V, int nmeet,
+__device__ void push_meeting(const GGraph& g, const GSlots& sl, int64_t so, const Vis<LDS>& V, int nmeet,
                              uint32_t want, SampleShared& sh, Counters& cn) {
     const int tid = threadIdx.x;
-    NodeRec* R = sl.rec + so;
-    int32_t* qd = sl.q_d + so;
-    DagArc* arcs = sl.arcs + (int64_t)blockIdx.x * sl.acap;
+    G<NodeRec>* R = sl.rec + so;
+    G<int32_t>* qd = sl.q_d + so;
+    G<DagArc>* arcs = sl.arcs + (int64_t)blockIdx.x * sl.acap;
     constexpr int CHK = chunk_len<BSZ>();
     for (int base = 0; base < nmeet; base += CHK) {
         const int cnt = min(CHK, nmeet - base);
@@ -634,7 +688,8 @@ __device__ void claim_next(const SampleLaunch& L, unsigned long long npairs, Sam
         if (lane == 0) sh.nx_ok = 0;
         return;
     }
-    const PairRec rec = L.pairs[q];
+    const u32x4 pv = *reinterpret_cast<const G<u32x4>*>(gptr(L.pairs) + q);
+    const PairRec rec{pv.x, (int32_t)pv.y, (int32_t)pv.z, (int32_t)pv.w};
     if (lane == 0) {
         sh.nx_ok = 1;
         sh.nx_idx = L.base + rec.q;
@@ -649,17 +704,18 @@ __device__ void claim_next(const SampleLaunch& L, unsigned long long npairs, Sam
 // debug mode (dbg != nullptr) the path index is given instead of drawn, hits
 // are not touched and the path is written to dbg (internal ids).
 template <int BSZ, bool LDS>
-__device__ void run_sample(const DevGraph& g, const DevSlots& sl, int64_t so, const Vis<LDS>& V, uint64_t idx,
-                           const DevTask& T, int32_t s, int32_t t, const SampleLaunch* next,
-                           unsigned long long npairs, uint32_t q_rel, int32_t task, SampleShared& sh,
-                           Counters& cn, DebugOut* dbg, uint64_t dbg_r, int32_t dbg_cap) {
+__device__ __forceinline__ void run_sample(const GGraph& g, const GSlots& sl, int64_t so, const Vis<LDS>& V,
+                                           uint64_t idx, const DevTask& T, int32_t s, int32_t t,
+                                           const SampleLaunch* next, unsigned long long npairs, uint32_t q_rel,
+                                           int32_t task, SampleShared& sh, Counters& cn, DebugOut* dbg,
+                                           uint64_t dbg_r, int32_t dbg_cap) {
     using B = Bits;
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-    NodeRec* R = sl.rec + so;
-    int32_t* q_s = sl.q_s + so;
-    int32_t* q_t = sl.q_t + so;
-    int32_t* q_d = sl.q_d + so;
-    int32_t* tls = sl.tls + (int64_t)blockIdx.x * (sl.stride + 2);  // start of each t-level in q_t
+    G<NodeRec>* R = sl.rec + so;
+    G<int32_t>* q_s = sl.q_s + so;
+    G<int32_t>* q_t = sl.q_t + so;
+    G<int32_t>* q_d = sl.q_d + so;
+    G<int32_t>* tls = sl.tls + (int64_t)blockIdx.x * (sl.stride + 2);  // start of each t-level in q_t
 
     // phase timers (thread 0, constant-rate wall clock)
     unsigned long long tm_prev = 0;
@@ -690,8 +746,8 @@ __device__ void run_sample(const DevGraph& g, const DevSlots& sl, int64_t so, co
             } else {
                 sh.status = 0;
                 if (LDS) {
-                    (void)table_put(V.tab[0], &sh.hcnt[0], s);
-                    (void)table_put(V.tab[1], &sh.hcnt[1], t);
+                    (void)table_put(tab(0), &sh.hcnt[0], s);
+                    (void)table_put(tab(1), &sh.hcnt[1], t);
                 } else {
                     B::set(V.bm[0], s);
                     B::set(V.bm[1], t);
@@ -726,7 +782,7 @@ __device__ void run_sample(const DevGraph& g, const DevSlots& sl, int64_t so, co
         if (LDS && sh.spill_req[side]) {
             // the side's table overflowed: its whole ball (its queue) moves to
             // the device bitmap, which answers for the side from now on
-            int32_t* qq = side == 0 ? q_s : q_t;
+            G<int32_t>* qq = side == 0 ? q_s : q_t;
             for (int i = tid; i < nhi; i += BSZ) (void)B::set(V.bm[side], ldq(qq + i));
             __syncthreads();
             if (tid == 0) {
@@ -821,7 +877,7 @@ __device__ void run_sample(const DevGraph& g, const DevSlots& sl, int64_t so, co
             uint64_t r = dbg ? dbg_r : draw_bounded(T.seed, T.phase, idx, 2, sh.sigma);
             const int32_t na = __builtin_amdgcn_readfirstlane(sh.narcs);
             const bool by_arcs = na <= sl.acap;
-            const DagArc* arcs = sl.arcs + (int64_t)blockIdx.x * sl.acap;
+            const G<DagArc>* arcs = sl.arcs + (int64_t)blockIdx.x * sl.acap;
             const unsigned long long below = (1ull << lane) - 1;  // lanes under this one
             int32_t w = sh.t;
             int err = 0;
@@ -839,7 +895,8 @@ __device__ void run_sample(const DevGraph& g, const DevSlots& sl, int64_t so, co
                             const int i = base + k * 64 + lane;
                             m[k] = false;
                             if (i < na) {
-                                a[k] = arcs[i];
+                                const u32x4 av = *reinterpret_cast<const G<u32x4>*>(arcs + i);
+                                a[k] = DagArc{(int32_t)av.x, (int32_t)av.y, ((uint64_t)av.w << 32) | av.z};
                                 m[k] = a[k].head == w;
                             }
                         }
@@ -895,7 +952,7 @@ __device__ void run_sample(const DevGraph& g, const DevSlots& sl, int64_t so, co
                         for (int k = 0; k < WALK_UNROLL; k++) {
                             wt[k] = 0;
                             if (u[k] >= 0 && member<LDS>(V, sh, on_s ? 0 : 1, u[k])) {
-                                const uint4 rec = *reinterpret_cast<const uint4*>(&R[u[k]]);
+                                const u32x4 rec = *reinterpret_cast<const G<u32x4>*>(&R[u[k]]);
                                 const uint32_t lv = on_s ? rec.x : rec.y;
                                 if ((lv & LVMASK) == want) wt[k] = ((uint64_t)rec.w << 32) | rec.z;
                             }
@@ -923,7 +980,8 @@ __device__ void run_sample(const DevGraph& g, const DevSlots& sl, int64_t so, co
                     if (dbg) {
                         if (p < dbg_cap) dbg->path[p] = w;
                     } else {
-                        atomicAdd(T.hits + g.orig[w], 1u);
+                        __hip_atomic_fetch_add(gptr(T.hits) + g.orig[w], 1u, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_AGENT);
                     }
                     cn.V++;
                 }
@@ -931,8 +989,9 @@ __device__ void run_sample(const DevGraph& g, const DevSlots& sl, int64_t so, co
             if (lane == 0) sh.walk_err = err;
         }
     }
-    // ---- the next sample's pair, by wave 1 while wave 0 walks
-    if (next && wid == 1) claim_next(*next, npairs, sh);
+    // ---- the next sample's pair, by wave 1 while wave 0 walks (a one-wave
+    // workgroup claims it after its walk)
+    if (next && wid == (BSZ >= 128 ? 1 : 0)) claim_next(*next, npairs, sh);
     __syncthreads();
     phase_mark(3);
 
@@ -972,16 +1031,20 @@ __device__ void run_sample(const DevGraph& g, const DevSlots& sl, int64_t so, co
     const bool bm_s = !LDS || sh.spilled[0], bm_t = !LDS || sh.spilled[1];
     for (int i = tid; i < ts; i += BSZ) {
         const int32_t w = ldq(q_s + i);
-        R[w] = NodeRec{};
+        G<u32x4>* z = reinterpret_cast<G<u32x4>*>(&R[w]);
+        z[0] = u32x4{0u, 0u, 0u, 0u};
+        z[1] = u32x4{0u, 0u, 0u, 0u};
         if (bm_s) B::clear_word(V.bm[0], w);
     }
     for (int i = tid; i < tt; i += BSZ) {
         const int32_t w = ldq(q_t + i);
-        R[w] = NodeRec{};
+        G<u32x4>* z = reinterpret_cast<G<u32x4>*>(&R[w]);
+        z[0] = u32x4{0u, 0u, 0u, 0u};
+        z[1] = u32x4{0u, 0u, 0u, 0u};
         if (bm_t) B::clear_word(V.bm[1], w);
     }
     if (LDS) {
-        for (int i = tid; i < 2 * HCAP; i += BSZ) __hip_atomic_store(V.tab[0] + i, 0u, __ATOMIC_RELAXED, WGS);
+        for (int i = tid; i < 2 * HCAP; i += BSZ) __hip_atomic_store(dyn_lds + i, 0u, __ATOMIC_RELAXED, WGS);
     }
     level_barrier();
     phase_mark(4);
@@ -1004,16 +1067,12 @@ __device__ void flush_counters(const Counters& cn, DevStats* st) {
     }
 }
 
-extern __shared__ uint32_t dyn_lds[];
-
 template <int BSZ, bool LDS>
-__device__ __forceinline__ Vis<LDS> slot_vis(const DevSlots& sl, int slot) {
+__device__ __forceinline__ Vis<LDS> slot_vis(const GSlots& sl, int slot) {
     Vis<LDS> v;
-    uint32_t* base = sl.bm + (int64_t)slot * 2 * sl.words;
+    G<uint32_t>* base = sl.bm + (int64_t)slot * 2 * sl.words;
     v.bm[0] = base;
     v.bm[1] = base + sl.words;
-    v.tab[0] = dyn_lds;          // the two tables are adjacent
-    v.tab[1] = dyn_lds + HCAP;
     return v;
 }
 
@@ -1031,10 +1090,10 @@ __device__ __forceinline__ Vis<LDS> slot_vis(const DevSlots& sl, int slot) {
 #endif
 
 template <int BSZ, bool LDS>
-__global__ __launch_bounds__(BSZ) SAMPLER_OCCUPANCY void sampler_kernel(DevSlots sl, SampleLaunch L) {
-    static_assert(BSZ >= 128, "wave 1 claims the next sample");
+__global__ __launch_bounds__(BSZ) SAMPLER_OCCUPANCY void sampler_kernel(DevSlots slots, SampleLaunch L) {
     __shared__ SampleShared sh;
     const int tid = threadIdx.x;
+    const GSlots sl = sview(slots);
     const int64_t so = (int64_t)blockIdx.x * sl.stride;
     const Vis<LDS> V = slot_vis<BSZ, LDS>(sl, blockIdx.x);
     Counters cn = {0, 0, 0, 0};
@@ -1062,8 +1121,8 @@ __global__ __launch_bounds__(BSZ) SAMPLER_OCCUPANCY void sampler_kernel(DevSlots
             flush_task_stats(sh, L);
             sh.acc_task = k;
         }
-        run_sample<BSZ, LDS>(T.g, sl, so, V, T.first + (q - T.offset), T, s, t, &L, npairs, (uint32_t)(q - L.base), k,
-                             sh, cn, nullptr, 0, 0);
+        run_sample<BSZ, LDS>(gview(T.g), sl, so, V, T.first + (q - T.offset), T, s, t, &L, npairs,
+                             (uint32_t)(q - L.base), k, sh, cn, nullptr, 0, 0);
     }
     flush_counters(cn, L.stats);
     if (tid == 0) {
@@ -1073,9 +1132,10 @@ __global__ __launch_bounds__(BSZ) SAMPLER_OCCUPANCY void sampler_kernel(DevSlots
 }
 
 template <int BSZ, bool LDS>
-__global__ __launch_bounds__(BSZ) void debug_path_kernel(DevGraph g, DevSlots sl, int32_t s, int32_t t, uint64_t r,
+__global__ __launch_bounds__(BSZ) void debug_path_kernel(DevGraph g, DevSlots slots, int32_t s, int32_t t, uint64_t r,
                                                          DebugOut* out, int32_t cap) {
     __shared__ SampleShared sh;
+    const GSlots sl = sview(slots);
     const Vis<LDS> V = slot_vis<BSZ, LDS>(sl, 0);
     Counters cn = {0, 0, 0, 0};
     if (LDS) {
@@ -1086,7 +1146,7 @@ __global__ __launch_bounds__(BSZ) void debug_path_kernel(DevGraph g, DevSlots sl
     }
     __syncthreads();
     DevTask T = {};
-    run_sample<BSZ, LDS>(g, sl, 0, V, 0, T, s, t, nullptr, 0, 0, -1, sh, cn, out, r, cap);
+    run_sample<BSZ, LDS>(gview(g), sl, 0, V, 0, T, s, t, nullptr, 0, 0, -1, sh, cn, out, r, cap);
 }
 
 __global__ void fill_u32_kernel(uint32_t* p, uint32_t v, int64_t count) {
@@ -1461,6 +1521,7 @@ static const void* sampler_fn() {
 
 static const void* pick_sampler(const SamplerShape& s) {
     switch (s.block) {
+        case 64: return s.lds_sets ? sampler_fn<64, true>() : sampler_fn<64, false>();
         case 128: return s.lds_sets ? sampler_fn<128, true>() : sampler_fn<128, false>();
         case 256: return s.lds_sets ? sampler_fn<256, true>() : sampler_fn<256, false>();
         case 512: return s.lds_sets ? sampler_fn<512, true>() : sampler_fn<512, false>();
@@ -1496,6 +1557,7 @@ hipError_t launch_debug_path(const DevGraph& g, const DevSlots& slots, int32_t s
                              DebugOut* out, int32_t cap, const SamplerShape& shape, hipStream_t stream) {
     const void* fn = nullptr;
     switch (shape.block) {
+        case 64: fn = shape.lds_sets ? (const void*)&debug_path_kernel<64, true> : (const void*)&debug_path_kernel<64, false>; break;
         case 128: fn = shape.lds_sets ? (const void*)&debug_path_kernel<128, true> : (const void*)&debug_path_kernel<128, false>; break;
         case 256: fn = shape.lds_sets ? (const void*)&debug_path_kernel<256, true> : (const void*)&debug_path_kernel<256, false>; break;
         case 512: fn = shape.lds_sets ? (const void*)&debug_path_kernel<512, true> : (const void*)&debug_path_kernel<512, false>; break;

@@ -166,8 +166,27 @@ __global__ void zero_u32_kernel(uint32_t* p, int64_t count) {
     for (int64_t i = gtid(); i < count; i += gstride()) p[i] = 0u;
 }
 
+// State histogram. Skewed states (most nodes at one value) would put most
+// atomics on one bin, so up to four rounds per wave first gather the lanes
+// that share the lowest pending lane's value into a single add.
 __global__ void count_states_kernel(const uint16_t* k, int32_t n, uint32_t* cnt) {
-    for (int64_t v = gtid(); v < n; v += gstride()) atomicAdd(&cnt[k[v]], 1u);
+    const int64_t n_pad = ((int64_t)n + 63) / 64 * 64;
+    for (int64_t v = gtid(); v < n_pad; v += gstride()) {
+        const bool ok = v < n;
+        const int32_t kv = ok ? (int32_t)k[v] : -1;
+        bool pending = ok;
+#pragma unroll
+        for (int round = 0; round < 4; round++) {
+            const uint64_t act = __ballot(pending);
+            if (!act) break;
+            const int leader = __ffsll((unsigned long long)act) - 1;
+            const int32_t kl = __shfl(kv, leader, 64);
+            const uint64_t same = __ballot(pending && kv == kl);
+            if (lane_id() == leader) atomicAdd(&cnt[kl], (uint32_t)__popcll(same));
+            pending = pending && kv != kl;
+        }
+        if (pending) atomicAdd(&cnt[kv], 1u);
+    }
 }
 
 // lt_cnt[x] = #{v : k_v < x}, lt_sum[x] = sum of k_v < x, for x = 0 .. 65536

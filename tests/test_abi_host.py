@@ -125,10 +125,10 @@ def test_status_strings(P):
 
 def test_option_validation(P):
     c = ctx(P)
-    for b in (0, 128, 256, 512, 1024):
+    for b in (0, 64, 128, 256, 512, 1024):
         c.set_option(P.OPT_BLOCK, b)
         assert c.get_option(P.OPT_BLOCK) == b
-    for b in (64, 100, 2048):
+    for b in (32, 100, 2048):
         with pytest.raises(P.PercisError) as e:
             c.set_option(P.OPT_BLOCK, b)
         assert e.value.status == P.E_INVAL

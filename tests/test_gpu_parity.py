@@ -127,7 +127,8 @@ def test_er1000_parity():
 
 
 @pytest.mark.parametrize("slots,block,bitmaps", [(1, 0, 0), (3, 256, 1), (37, 512, 2), (0, 1024, 1),
-                                                  (0, 256, 2), (5, 1024, 2), (0, 128, 1), (7, 128, 2)])
+                                                  (0, 256, 2), (5, 1024, 2), (0, 128, 1), (7, 128, 2),
+                                                  (0, 64, 2), (9, 64, 1), (1, 64, 2)])
 def test_launch_shape_invariance(slots, block, bitmaps):
     """Hit counts and statistics do not depend on the number of slots, the
     threads per sample or where the visited bitmaps live."""
@@ -156,7 +157,7 @@ def test_rmat18_shapes_agree():
     from paper_2509_11454_amd import percis as P
     g, k = W.workload_rmat18()
     ref = None
-    for block, bitmaps in [(1024, 2), (512, 1), (256, 2), (128, 1)]:
+    for block, bitmaps in [(1024, 2), (512, 1), (256, 2), (128, 1), (64, 2), (64, 1)]:
         c = P.Context(0)
         c.set_option(P.OPT_BLOCK, block)
         c.set_option(P.OPT_BITMAPS, bitmaps)
