@@ -1077,11 +1077,12 @@ __device__ __forceinline__ Vis<LDS> slot_vis(const GSlots& sl, int slot) {
 }
 
 // Occupancy target of the sampler (waves per SIMD), a build knob (0 = the
-// compiler's choice, 4 at about 124 registers): the sampler is latency-bound,
-// and 6 waves (80 registers, a few spilled) keeps more samples in flight.
-// Measured on R-MAT 18: 4 waves 26.4M, 5 waves 29.1M, 6 waves 29.5M samples/s.
+// compiler's choice): the sampler is latency-bound, so samples in flight
+// count, but spilled registers cost memory round trips. Measured on R-MAT 18
+// (unroll 8): 4 waves 34.5M, 5 waves (96 registers) 36.7M, 6 waves (80) 35.7M,
+// 7 waves 28.8M samples/s.
 #ifndef PERCIS_SAMPLER_WAVES_PER_EU
-#define PERCIS_SAMPLER_WAVES_PER_EU 6
+#define PERCIS_SAMPLER_WAVES_PER_EU 5
 #endif
 #if PERCIS_SAMPLER_WAVES_PER_EU > 0
 #define SAMPLER_OCCUPANCY __attribute__((amdgpu_waves_per_eu(PERCIS_SAMPLER_WAVES_PER_EU)))
