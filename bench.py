@@ -102,6 +102,10 @@ def main():
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--bitmaps", type=int, default=0,
                     help="visited sets: 0 auto, 1 device bitmaps, 2 LDS hash tables")
+    ap.add_argument("--compact", type=int, default=0,
+                    help="compact slots: 0 auto, 1 off, 2 on (samples outgrowing them go to per-node slots)")
+    ap.add_argument("--defer-block", type=int, default=0,
+                    help="threads per sample of the per-node slots while compact slots are on (0 auto)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-estimate", action="store_true")
@@ -150,6 +154,8 @@ def main():
     c.set_option(P.OPT_SLOTS, args.slots)
     c.set_option(P.OPT_BLOCK, args.block)
     c.set_option(P.OPT_BITMAPS, args.bitmaps)
+    c.set_option(P.OPT_COMPACT, args.compact)
+    c.set_option(P.OPT_DEFER_BLOCK, args.defer_block)
     c.load_csr(g.n, g.row_ptr, g.col, directed=g.directed)
     c.set_states(k)
     hits = torch.zeros(g.n, dtype=torch.int32, device="cuda")
@@ -158,7 +164,8 @@ def main():
         print("[bench] warmup %d: %.1f ms" % (i, st["kernel_ms"]), file=sys.stderr, flush=True)
 
     torch.cuda.synchronize()
-    totals = dict(edges=0, sigma_adds=0, vertices_expanded=0, vertices_discovered=0, sum_I=0, reachable=0)
+    totals = dict(edges=0, sigma_adds=0, vertices_expanded=0, vertices_discovered=0, sum_I=0, reachable=0, spilled=0,
+                  deferred=0)
     phases = {}
     kernel_ms = []
     pair_ms = []
@@ -201,12 +208,15 @@ def main():
         "data": "synthetic",
         "config": {"workload": "%s: %s" % (args.workload, desc), "n": g.n, "m_arcs": g.m,
                    "samples_per_step": samples, "seed": args.seed, "slots": slots,
-                   "threads_per_sample": block, "visited_sets": bitmaps},
+                   "threads_per_sample": block, "visited_sets": bitmaps,
+                   "compact_slots": c.get_option(P.OPT_COMPACT) == 2},
         "gteps": totals["edges"] / elapsed / 1e9,
         "edges_per_sample": totals["edges"] / (samples * args.steps),
         "per_sample": {key: totals[key] / (samples * args.steps)
                        for key in ("sigma_adds", "vertices_expanded", "vertices_discovered", "sum_I")},
         "reachable_fraction": totals["reachable"] / (samples * args.steps),
+        "spilled_fraction": totals["spilled"] / (samples * args.steps),
+        "deferred_fraction": totals["deferred"] / (samples * args.steps),
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "sampler_kernel", "kernel_ms": avg_kernel_s * 1e3,

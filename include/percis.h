@@ -82,6 +82,8 @@ typedef struct {
      * which one wave claims the next sample), and clearing the slot. */
     double   phase_ms[5];
     double   pair_ms;           /* device time of the pair kernel (Algorithm 2 draws) */
+    uint64_t spilled;           /* samples whose visited set on a side outgrew its LDS table */
+    uint64_t deferred;          /* samples a compact slot handed to the per-node slots (PERCIS_OPT_COMPACT) */
 } percis_stats;
 
 /* Result summary of percis_estimate (Algorithm 1). */
@@ -263,6 +265,13 @@ int percis_exact(percis_ctx* ctx, int32_t graph, double* p_out, double* kernel_m
 
 /* Tuning knobs (launch shape only; results never depend on them).
  * PERCIS_OPT_SLOTS: concurrent samples (resident workgroups), 0 = auto.
+ * PERCIS_OPT_COMPACT: compact slots, whose node records are indexed by the
+ * node's place in the side's LDS table (about 150 KB per slot instead of
+ * ~48 bytes per node of the graph): 1 = off; 2 = on, with the per-node slots
+ * redoing every sample that a side's table cannot hold (more than 768 nodes);
+ * 0 = auto (on when LDS tables are used and the per-node slots are too few,
+ * for lack of memory, to fill the device). Reads 1 or 2 once a graph is
+ * loaded. PERCIS_OPT_SLOTS reads the compact slots' count when they are on.
  * PERCIS_OPT_SCRATCH_MB: cap on the sampler's scratch memory, 0 = auto.
  * PERCIS_OPT_BLOCK: threads per sample (64, 128, 256, 512 or 1024), 0 = auto.
  * PERCIS_OPT_BITMAPS: how a sample's visited sets are kept: 1 = one bitmap
@@ -275,6 +284,11 @@ int percis_exact(percis_ctx* ctx, int32_t graph, double* p_out, double* kernel_m
 #define PERCIS_OPT_SCRATCH_MB  2
 #define PERCIS_OPT_BLOCK       3
 #define PERCIS_OPT_BITMAPS     4
+#define PERCIS_OPT_COMPACT     5
+/* PERCIS_OPT_DEFER_BLOCK: threads per sample of the per-node slots while
+ * compact slots are on (they then only run the samples with large balls):
+ * 64 .. 1024, 0 = auto. */
+#define PERCIS_OPT_DEFER_BLOCK 6
 int percis_set_option(percis_ctx* ctx, int option, int64_t value);
 int percis_get_option(percis_ctx* ctx, int option, int64_t* value);
 

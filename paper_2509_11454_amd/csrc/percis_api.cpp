@@ -291,6 +291,10 @@ static DevCdf dev_cdf(const GraphData& G) {
 
 static void free_slots(percis_ctx* c) {
     if (c->slot_mem) (void)hipFree(c->slot_mem);
+    if (c->cslot_mem) (void)hipFree(c->cslot_mem);
+    c->cslot_mem = nullptr;
+    c->ncslots = 0;
+    c->cslots = DevSlots{};
     if (c->wide_mem) (void)hipFree(c->wide_mem);
     c->wide_mem = nullptr;
     c->wide_slots = 0;
@@ -308,6 +312,7 @@ constexpr int64_t kArcsPerSlot = 4096;  // DAG arcs a sample may record for its 
 constexpr uint64_t kPairChunk = 1ull << 22;  // samples per pair-kernel chunk (16 bytes each listed)
 constexpr int64_t kWideSlots = 16;           // workgroups of the 128-bit path
 constexpr int64_t kWideBytesPerNode = 4 + 16 + 4;
+constexpr int kDeferBlock = 512;             // per-node slots' block while compact slots are on
 
 static int64_t bitmap_words(int64_t act) { return ((std::max<int64_t>(act, 1) + 31) / 32 + 63) / 64 * 64; }
 
@@ -318,11 +323,15 @@ static int pick_shape(percis_ctx* c, int64_t act, SamplerShape* out, int* occ_ou
     SamplerShape sh{};
     sh.block = c->opt_block ? (int)c->opt_block : 128;
     (void)words;
-    const int64_t lds_need = sampler_table_lds();
+    const int64_t lds_need = sampler_table_lds(false);
     const bool fits = lds_need + sampler_static_lds() <= kLdsPerCu;
     if (c->opt_bitmaps == 2 && !fits)
         return fail(c, PERCIS_E_INVAL, "visited-set tables do not fit in LDS");
-    if (c->opt_bitmaps == 0) {
+    if (c->opt_compact == 2 && c->opt_bitmaps == 1)
+        return fail(c, PERCIS_E_INVAL, "compact slots need the LDS tables (bitmaps option 0 or 2)");
+    if (c->opt_bitmaps == 0 && c->opt_compact == 2) {
+        sh.lds_sets = fits;  // compact slots index their records by table position
+    } else if (c->opt_bitmaps == 0) {
         // LDS tables unless they cost resident samples: the sampler is
         // latency-bound, so samples in flight per CU matter more than where
         // the visited sets live
@@ -427,12 +436,58 @@ static int ensure_slots(percis_ctx* c, int64_t act) {
     c->wide_mem = wmem;
     c->wide_slots = (int)nw;
     c->wslots = w;
+
+    // Compact slots: records by table position, so a slot costs a fixed
+    // ~150 KB whatever the graph; the per-node slots above then only redo the
+    // samples a table cannot hold. Auto: when the per-node slots are too few
+    // (memory) to fill the device.
+    const bool compact = sh.lds_sets && (c->opt_compact == 2 || (c->opt_compact == 0 && ns < want));
+    if (compact) {
+        SamplerShape cs = sh;
+        cs.compact = true;
+        cs.lds_bytes = sampler_table_lds(true);
+        const int cocc = sampler_occupancy(cs);
+        const int64_t cap = sampler_table_cap(true);
+        const int64_t cper = 2 * cap * (int64_t)sizeof(CRec) + 4 * cap * 4 + (cap + 2) * 4 +
+                             kArcsPerSlot * (int64_t)sizeof(DagArc);
+        int64_t nc = c->opt_slots > 0 ? c->opt_slots : (int64_t)std::max(c->cu_count, 1) * cocc;
+        void* cmem = nullptr;
+        e = hipErrorOutOfMemory;
+        while (cocc > 0 && nc >= 1) {
+            e = hipMalloc(&cmem, (size_t)(nc * cper));
+            if (e == hipSuccess) break;
+            (void)hipGetLastError();
+            nc /= 2;
+        }
+        if (e != hipSuccess || !cmem || launch_fill_u8(cmem, nc * cper, c->stream) != hipSuccess) {
+            if (cmem) (void)hipFree(cmem);
+            (void)hipGetLastError();
+            free_slots(c);
+            return fail(c, PERCIS_E_NOMEM, "cannot allocate compact slots");
+        }
+        char* cp = (char*)cmem;
+        DevSlots d{};
+        d.stride = cap;
+        d.crec = (CRec*)cp; cp += nc * 2 * cap * (int64_t)sizeof(CRec);
+        d.q_s = (int32_t*)cp; cp += nc * cap * 4;
+        d.q_t = (int32_t*)cp; cp += nc * cap * 4;
+        d.q_d = (int32_t*)cp; cp += nc * 2 * cap * 4;
+        d.tls = (int32_t*)cp; cp += nc * (cap + 2) * 4;
+        d.arcs = (DagArc*)cp;
+        d.acap = (int32_t)kArcsPerSlot;
+        c->cslot_mem = cmem;
+        c->cslots = d;
+        c->ncslots = (int)nc;
+        c->cshape = cs;
+        // the per-node slots now see only samples with large balls: more
+        // threads per sample pay off there
+        SamplerShape big = sh;
+        big.block = c->opt_defer_block > 0 ? (int)c->opt_defer_block : kDeferBlock;
+        if (sampler_occupancy(big) > 0) c->shape = big;
+    }
     return PERCIS_OK;
 }
 
-// Undirected: BFS per connected component from its smallest node u; the
-// component's shortest paths have at most min(|comp| - 2, 2 ecc(u) - 1)
-// internal nodes. Directed: largest weakly connected component size - 2.
 // VertexDiamUB (Algorithm 1) on the device, once per graph: D_override if
 // set, else the cached device result (the graph never changes after loading).
 // Undirected: per connected component, a BFS from its smallest node u; the
@@ -606,6 +661,7 @@ int run_tasks(percis_ctx* c, const std::vector<TaskSpec>& tasks, std::vector<per
         if (c->stream) HIPCHK(c, hipStreamSynchronize(c->stream));
         if ((rc = dalloc(c, c->d_pairs, (size_t)chunk))) return rc;
         if ((rc = dalloc(c, c->d_wide, (size_t)chunk))) return rc;
+        if ((rc = dalloc(c, c->d_big, (size_t)chunk))) return rc;
         c->pair_cap = chunk;
     }
     const size_t nchunks = (size_t)((total + chunk - 1) / chunk);
@@ -624,13 +680,28 @@ int run_tasks(percis_ctx* c, const std::vector<TaskSpec>& tasks, std::vector<per
     a.slots = (int)std::min<uint64_t>((uint64_t)c->nslots, chunk);
     a.wide = c->d_wide;
     a.nwide = c->d_work + 2;
+    a.big = c->d_big;
+    a.nbig = c->d_work + 4;
+    a.big_work = c->d_work + 5;
     for (size_t i = 0; i < nchunks; i++) {
         a.base = (uint64_t)i * chunk;
         a.count = std::min<uint64_t>(chunk, total - a.base);
         HIPCHK(c, hipEventRecord(c->chunk_ev[3 * i], c->stream));
         HIPCHK(c, launch_pairs(a, c->stream));
         HIPCHK(c, hipEventRecord(c->chunk_ev[3 * i + 1], c->stream));
-        HIPCHK(c, launch_sampler(c->slots, a, c->shape, c->stream));
+        if (c->ncslots > 0) {
+            // compact slots first; the samples they hand on go to the per-node slots
+            SampleLaunch ca = a;
+            ca.slots = (int)std::min<uint64_t>((uint64_t)c->ncslots, chunk);
+            HIPCHK(c, launch_sampler(c->cslots, ca, c->cshape, c->stream));
+            SampleLaunch da = a;
+            da.pairs = c->d_big;
+            da.npairs = a.nbig;
+            da.work = a.big_work;
+            HIPCHK(c, launch_sampler(c->slots, da, c->shape, c->stream));
+        } else {
+            HIPCHK(c, launch_sampler(c->slots, a, c->shape, c->stream));
+        }
         HIPCHK(c, launch_wide(a, c->wslots, c->wide_slots, c->stream));
         HIPCHK(c, hipEventRecord(c->chunk_ev[3 * i + 2], c->stream));
     }
@@ -670,6 +741,8 @@ int run_tasks(percis_ctx* c, const std::vector<TaskSpec>& tasks, std::vector<per
     agg.sigma_adds = hl.sigma_adds;
     agg.vertices_expanded = hl.vexp;
     agg.vertices_discovered = hl.vdisc;
+    agg.spilled = hl.spills;
+    agg.deferred = hl.deferred;
     agg.kernel_ms = ms;
     agg.pair_ms = pair_ms;
     for (int i = 0; i < 5; i++) agg.phase_ms[i] = c->wall_hz > 0 ? (double)hl.phase_ticks[i] / c->wall_hz * 1e3 : 0.0;
@@ -808,7 +881,7 @@ int percis_create(int device, void* hip_stream, percis_ctx** out) {
         if (hipDeviceGetAttribute(&wall_khz, hipDeviceAttributeWallClockRate, device) == hipSuccess)
             c->wall_hz = wall_khz * 1e3;
         if (hipMalloc((void**)&c->d_stats, sizeof(DevStats)) != hipSuccess ||
-            hipMalloc((void**)&c->d_work, 4 * sizeof(unsigned long long)) != hipSuccess ||
+            hipMalloc((void**)&c->d_work, 6 * sizeof(unsigned long long)) != hipSuccess ||
             hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess) {
             percis_destroy(c);
             return PERCIS_E_DEVICE;
@@ -841,6 +914,7 @@ void percis_destroy(percis_ctx* c) {
     dfree(c->d_work);
     dfree(c->d_pairs);
     dfree(c->d_wide);
+    dfree(c->d_big);
     dfree(c->d_wdbg);
     for (hipEvent_t e : c->chunk_ev) (void)hipEventDestroy(e);
     c->chunk_ev.clear();
@@ -1114,6 +1188,15 @@ int percis_set_option(percis_ctx* c, int option, int64_t value) {
             if (value > 2) return fail(c, PERCIS_E_INVAL, "bitmaps option is 0 (auto), 1 (device bitmaps) or 2 (LDS tables)");
             c->opt_bitmaps = value;
             break;
+        case PERCIS_OPT_COMPACT:
+            if (value > 2) return fail(c, PERCIS_E_INVAL, "compact option is 0 (auto), 1 (off) or 2 (on)");
+            c->opt_compact = value;
+            break;
+        case PERCIS_OPT_DEFER_BLOCK:
+            if (value != 0 && value != 64 && value != 128 && value != 256 && value != 512 && value != 1024)
+                return fail(c, PERCIS_E_INVAL, "block must be 64, 128, 256, 512 or 1024");
+            c->opt_defer_block = value;
+            break;
         default: return fail(c, PERCIS_E_INVAL, "unknown option %d", option);
     }
     if (!c->host_only && sync_ctx(c) == PERCIS_OK) free_slots(c);
@@ -1126,19 +1209,27 @@ int percis_get_option(percis_ctx* c, int option, int64_t* value) {
         *value = c->opt_scratch_mb;
         return PERCIS_OK;
     }
-    if (option != PERCIS_OPT_SLOTS && option != PERCIS_OPT_BLOCK && option != PERCIS_OPT_BITMAPS)
+    if (option != PERCIS_OPT_SLOTS && option != PERCIS_OPT_BLOCK && option != PERCIS_OPT_BITMAPS &&
+        option != PERCIS_OPT_COMPACT && option != PERCIS_OPT_DEFER_BLOCK)
         return fail(c, PERCIS_E_INVAL, "unknown option %d", option);
     const int64_t act = max_active(c);
     if (c->host_only || act == 0) {
-        *value = option == PERCIS_OPT_SLOTS ? c->opt_slots : option == PERCIS_OPT_BLOCK ? c->opt_block : c->opt_bitmaps;
+        *value = option == PERCIS_OPT_SLOTS     ? c->opt_slots
+               : option == PERCIS_OPT_BLOCK     ? c->opt_block
+               : option == PERCIS_OPT_BITMAPS   ? c->opt_bitmaps
+               : option == PERCIS_OPT_COMPACT   ? c->opt_compact
+                                                : c->opt_defer_block;
         return PERCIS_OK;
     }
     int rc = set_device(c);
     if (rc) return rc;
     if ((rc = ensure_slots(c, act))) return rc;
-    *value = option == PERCIS_OPT_SLOTS ? c->nslots
-           : option == PERCIS_OPT_BLOCK ? c->shape.block
-                                        : (c->shape.lds_sets ? 2 : 1);
+    const bool cm = c->ncslots > 0;
+    *value = option == PERCIS_OPT_SLOTS     ? (cm ? c->ncslots : c->nslots)
+           : option == PERCIS_OPT_BLOCK     ? (cm ? c->cshape.block : c->shape.block)
+           : option == PERCIS_OPT_BITMAPS   ? (c->shape.lds_sets ? 2 : 1)
+           : option == PERCIS_OPT_COMPACT   ? (cm ? 2 : 1)
+                                            : (cm ? c->shape.block : c->opt_defer_block);
     return PERCIS_OK;
 }
 
@@ -1206,7 +1297,7 @@ int percis_autotune(percis_ctx* c, int32_t graph, uint64_t probe_samples, uint64
         int64_t block, bitmaps;
     };
     std::vector<Cand> cands;
-    const bool lds_ok = sampler_table_lds() + sampler_static_lds() <= kLdsPerCu;
+    const bool lds_ok = sampler_table_lds(false) + sampler_static_lds() <= kLdsPerCu;
     for (int64_t b : {128, 256, 512, 1024}) {
         if (lds_ok) cands.push_back({b, 2});
         cands.push_back({b, 1});

@@ -73,10 +73,15 @@ struct percis_ctx {
     percis::SamplerShape shape{};
 
     percis::DevStats* d_stats = nullptr;   // launch-wide counters
-    unsigned long long* d_work = nullptr;  // [4]: next list entry (or source), listed pairs, listed wide samples,
-                                           //      next wide entry
+    unsigned long long* d_work = nullptr;  // [6]: next list entry (or source), listed pairs, listed wide samples,
+                                           //      next wide entry, listed handed-on samples, next handed-on entry
     percis::PairRec* d_pairs = nullptr;    // pair list of one chunk
     percis::PairRec* d_wide = nullptr;     // samples of one chunk with sigma_st >= 2^64
+    percis::PairRec* d_big = nullptr;      // samples of one chunk that outgrew a compact slot
+    void* cslot_mem = nullptr;             // compact slots (none when ncslots = 0)
+    int ncslots = 0;
+    percis::DevSlots cslots{};
+    percis::SamplerShape cshape{};
     void* wide_mem = nullptr;              // scratch of the 128-bit path
     int wide_slots = 0;
     percis::WideSlots wslots{};
@@ -91,7 +96,7 @@ struct percis_ctx {
     int32_t dbg_cap = 0;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
 
-    int64_t opt_slots = 0, opt_scratch_mb = 0, opt_block = 0, opt_bitmaps = 0;
+    int64_t opt_slots = 0, opt_scratch_mb = 0, opt_block = 0, opt_bitmaps = 0, opt_compact = 0, opt_defer_block = 0;
 };
 
 namespace percis {

@@ -44,6 +44,19 @@ struct NodeRec {
     uint64_t pad;
 };
 
+// Record of a compact slot, indexed by the node's position in its side's LDS
+// visited table (one array of table size per side): level (+1, 0 =
+// unreached, plus flag bits), then on the s side sigma_s, on the t side the
+// sigma_s pulled through the t-ball (a meeting node's is copied from its s
+// record) and sigma_t.
+struct CRec {
+    uint32_t lv;
+    uint32_t pad;
+    uint64_t ws;
+    uint64_t wt;
+    uint64_t pad2;
+};
+
 // One arc u -> v of a sample's shortest-path DAG with the count sigma_s(u)
 // that weighs u among v's predecessors in the canonical walk.
 struct DagArc {
@@ -52,7 +65,11 @@ struct DagArc {
 };
 
 // Per-slot scratch; the node arrays are [slots][stride] (stride >= n_act) and
-// all-zero between samples (each sample clears what it touched).
+// all-zero between samples (each sample clears what it touched). A compact
+// slot set (crec != nullptr) has no per-node arrays: records are crec
+// [slots][2][table size], the queues hold table positions with stride = table
+// size (q_d: [slots][2][stride], s positions then t positions), and there
+// are no bitmaps.
 struct DevSlots {
     NodeRec* rec;     // per-node records
     int32_t* q_s;     // s-side BFS queue (levels are contiguous segments)
@@ -64,12 +81,15 @@ struct DevSlots {
     int64_t words;    // 32-bit words per bitmap
     DagArc* arcs;     // [slots][acap] arcs of the sample's shortest-path DAG, for the walk
     int32_t acap;     // arcs per slot
+    CRec* crec;       // compact slot set: [slots][2][stride] records
 };
 
 // Device-side accumulators of one sampling call.
 struct DevStats {
     unsigned long long samples, reachable, sum_I, sum_I2, overflow, first_overflow;
     unsigned long long edges, sigma_adds, vexp, vdisc;
+    unsigned long long spills;           // samples whose visited set outgrew an LDS table
+    unsigned long long deferred;         // samples a compact slot handed to the per-node slots
     unsigned long long phase_ticks[5];   // summed over workgroups, wall-clock ticks
 };
 
@@ -110,6 +130,9 @@ struct SampleLaunch {
     int slots;                       // sampler grid size
     PairRec* wide;                   // [count] capacity: samples with sigma_st >= 2^64
     unsigned long long* nwide;       // entries listed (written by the sampler)
+    PairRec* big;                    // [count] capacity: samples whose ball outgrew a compact slot
+    unsigned long long* nbig;        // entries listed (written by the compact sampler)
+    unsigned long long* big_work;    // next unclaimed entry of big (zeroed with the chunk)
 };
 
 // Scratch of the 128-bit path (samples with sigma_st >= 2^64): per slot, a
@@ -143,8 +166,9 @@ struct DebugOut {
 // Launch shape of the sampler: threads per workgroup and whether the
 // visited sets are LDS tables (else device bitmaps).
 struct SamplerShape {
-    int block;        // 128, 256, 512 or 1024
+    int block;        // 64, 128, 256, 512 or 1024 (compact: 64, 128 or 256)
     bool lds_sets;
+    bool compact;     // compact slots (requires lds_sets)
     int64_t lds_bytes;  // dynamic LDS per workgroup (the visited-set tables) when lds_sets
 };
 
@@ -160,6 +184,8 @@ hipError_t launch_pairs(const SampleLaunch& a, hipStream_t stream);
 hipError_t launch_wide(const SampleLaunch& a, const WideSlots& w, int slots, hipStream_t stream);
 // One (s, t, r) through the 128-bit path, on graph g, using slot 0 of w.
 hipError_t launch_wide_debug(const DevGraph& g, const WideSlots& w, WideDebug* dbg, hipStream_t stream);
+// The chunk's pairs on `slots` (per-node slots, or compact slots when
+// slots.crec is set; these defer samples that outgrow them to a.big).
 hipError_t launch_sampler(const DevSlots& slots, const SampleLaunch& a, const SamplerShape& shape,
                           hipStream_t stream);
 hipError_t launch_debug_path(const DevGraph& g, const DevSlots& slots, int32_t s, int32_t t, uint64_t r,
@@ -173,6 +199,9 @@ int64_t exact_scratch_bytes(int64_t stride, int slots);
 // Resident workgroups per CU for a shape (0 if it cannot launch).
 int sampler_occupancy(const SamplerShape& shape);
 int64_t sampler_static_lds();
-int64_t sampler_table_lds();  // dynamic LDS of the visited-set tables (LDS mode)
+// Dynamic LDS of the visited-set tables (LDS mode) and their entries per
+// side (the records per side of a compact slot), for per-node or compact slots.
+int64_t sampler_table_lds(bool compact);
+int sampler_table_cap(bool compact);
 
 }  // namespace percis

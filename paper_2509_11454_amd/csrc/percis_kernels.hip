@@ -111,10 +111,11 @@ struct GSlots {
     int64_t words;
     G<DagArc>* arcs;
     int32_t acap;
+    G<CRec>* crec;
 };
 __device__ __forceinline__ GSlots sview(const DevSlots& s) {
     return GSlots{gptr(s.rec), gptr(s.q_s), gptr(s.q_t), gptr(s.q_d), gptr(s.tls), s.stride,
-                  gptr(s.bm),  s.words,     gptr(s.arcs), s.acap};
+                  gptr(s.bm),  s.words,     gptr(s.arcs), s.acap,       gptr(s.crec)};
 }
 
 // Bitmap operations on one plane of a slot's device bitmaps.
@@ -131,6 +132,23 @@ struct Bits {
     }
 };
 
+// A slot's node records. Per-node slots (CMP = false) index them by node id;
+// compact slots (CMP = true) by the node's position p in its side's LDS
+// table, one record per side. Every accessor takes both; the unused one is
+// dropped by the compiler.
+template <bool CMP>
+struct Recs {
+    G<NodeRec>* R;   // per-node slots: this slot's records
+    G<CRec>* C;      // compact slots: this slot's [2][table size] records (sizes are defined below)
+    template <int SIDE>
+    __device__ __forceinline__ G<uint32_t>* lv(int32_t x, int p) const;
+    template <int SIDE>
+    __device__ __forceinline__ G<uint64_t>* sg(int32_t x, int p) const;
+    __device__ __forceinline__ G<uint64_t>* ws(int side, int32_t x, int p) const;
+    __device__ __forceinline__ void lv_ws(int side, int32_t x, int p, uint32_t& lv, uint64_t& w) const;
+    __device__ __forceinline__ void clear(int side, int32_t x, int p) const;
+};
+
 // Visited sets of a sample's two balls.
 // LDS = false: one bitmap plane per side in the slot's device memory.
 // LDS = true: an exact open-addressing hash table per side in LDS (node id + 1,
@@ -141,10 +159,69 @@ struct Bits {
 #ifndef PERCIS_HBITS
 #define PERCIS_HBITS 10
 #endif
-constexpr int HBITS = PERCIS_HBITS;
-constexpr int HCAP = 1 << HBITS;       // table slots per side
-constexpr int HLIMIT = 3 * HCAP / 4;   // most entries a table takes
-constexpr int HADMIT = 5 * HCAP / 8;   // a level decides first visits by the table if it cannot add more
+// Compact slots may use larger tables: a larger table hands fewer samples
+// on to the per-node slots, but costs resident samples. R-MAT 24 directed:
+// 10 bits 7.2M (10.5 % handed on), 11 bits 7.7M (6.3 %), 12 bits 6.6M
+// samples/s (4.5 %).
+#ifndef PERCIS_HBITS_COMPACT
+#define PERCIS_HBITS_COMPACT 11
+#endif
+constexpr int HBITS = PERCIS_HBITS;           // per-node slots
+constexpr int HBITS_C = PERCIS_HBITS_COMPACT; // compact slots
+template <int TB>
+struct Tab {
+    static constexpr int CAP = 1 << TB;          // table slots per side
+    static constexpr int LIMIT = 3 * CAP / 4;    // most entries a table takes
+    static constexpr int ADMIT = 5 * CAP / 8;    // a level decides first visits by the table if it cannot add more
+};
+template <bool CMP>
+constexpr int tbits() { return CMP ? HBITS_C : HBITS; }
+constexpr int HCAP = Tab<HBITS>::CAP;         // per-node slots' table
+constexpr int HADMIT = Tab<HBITS>::ADMIT;
+constexpr int CCAP = Tab<HBITS_C>::CAP;       // compact slots' table (records per side)
+
+// Level word of x on side SIDE.
+template <bool CMP>
+template <int SIDE>
+__device__ __forceinline__ G<uint32_t>* Recs<CMP>::lv(int32_t x, int p) const {
+    if constexpr (CMP) return &C[SIDE * CCAP + p].lv;
+    else return SIDE ? &R[x].lv_t : &R[x].lv_s;
+}
+// The side's own shortest-path count of x (sigma_s on the s side, sigma_t on
+// the t side).
+template <bool CMP>
+template <int SIDE>
+__device__ __forceinline__ G<uint64_t>* Recs<CMP>::sg(int32_t x, int p) const {
+    if constexpr (CMP) return SIDE ? &C[CCAP + p].wt : &C[p].ws;
+    else return SIDE ? &R[x].sg_t : &R[x].sg_s;
+}
+// sigma_s of x as the sweep and the walk read it, from side `side`'s record
+// (per-node slots have one field for both).
+template <bool CMP>
+__device__ __forceinline__ G<uint64_t>* Recs<CMP>::ws(int side, int32_t x, int p) const {
+    if constexpr (CMP) return &C[side * CCAP + p].ws;
+    else return &R[x].sg_s;
+}
+// Level on side `side` and sigma_s of x in one 16-byte load.
+template <bool CMP>
+__device__ __forceinline__ void Recs<CMP>::lv_ws(int side, int32_t x, int p, uint32_t& lvw, uint64_t& w) const {
+    if constexpr (CMP) {
+        const u32x4 v = *reinterpret_cast<const G<u32x4>*>(&C[side * CCAP + p]);
+        lvw = v.x;
+        w = ((uint64_t)v.w << 32) | v.z;
+    } else {
+        const u32x4 v = *reinterpret_cast<const G<u32x4>*>(&R[x]);
+        lvw = side ? v.y : v.x;
+        w = ((uint64_t)v.w << 32) | v.z;
+    }
+}
+// Zeroes x's record (per-node slots: both sides at once).
+template <bool CMP>
+__device__ __forceinline__ void Recs<CMP>::clear(int side, int32_t x, int p) const {
+    G<u32x4>* z = CMP ? reinterpret_cast<G<u32x4>*>(&C[side * CCAP + p]) : reinterpret_cast<G<u32x4>*>(&R[x]);
+    z[0] = u32x4{0u, 0u, 0u, 0u};
+    z[1] = u32x4{0u, 0u, 0u, 0u};
+}
 template <bool LDS>
 struct Vis {
     G<uint32_t>* bm[2];   // device bitmap planes
@@ -154,36 +231,65 @@ struct Vis {
 // first; they are addressed from the array itself so that the compiler keeps
 // their accesses in LDS.
 extern __shared__ uint32_t dyn_lds[];
-__device__ __forceinline__ uint32_t* tab(int side) { return dyn_lds + side * HCAP; }
+template <int TB = HBITS>
+__device__ __forceinline__ uint32_t* tab(int side) { return dyn_lds + side * Tab<TB>::CAP; }
 
-__device__ __forceinline__ uint32_t hslot(int32_t x) { return ((uint32_t)x * 0x9E3779B1u) >> (32 - HBITS); }
+template <int TB>
+__device__ __forceinline__ uint32_t hslot(int32_t x) { return ((uint32_t)x * 0x9E3779B1u) >> (32 - TB); }
 
-__device__ __forceinline__ bool table_has(uint32_t* T, int32_t x) {
+// Position of x in table T, or -1.
+template <int TB = HBITS>
+__device__ __forceinline__ int table_find(uint32_t* T, int32_t x) {
     const uint32_t key = (uint32_t)x + 1;
-    for (uint32_t i = hslot(x);; i = (i + 1) & (HCAP - 1)) {
+    for (uint32_t i = hslot<TB>(x);; i = (i + 1) & (Tab<TB>::CAP - 1)) {
         const uint32_t v = __hip_atomic_load(T + i, __ATOMIC_RELAXED, WGS);
-        if (v == key) return true;
-        if (v == 0) return false;
+        if (v == key) return (int)i;
+        if (v == 0) return -1;
+    }
+}
+__device__ __forceinline__ bool table_has(uint32_t* T, int32_t x) { return table_find<HBITS>(T, x) >= 0; }
+
+// Inserts x, known to be absent and inserted by this thread only; returns
+// its position, or -1 if the table is full (it then stays without x).
+template <int TB = HBITS>
+__device__ __forceinline__ int table_put(uint32_t* T, int32_t* cnt, int32_t x) {
+    if (atomicAdd(cnt, 1) >= Tab<TB>::LIMIT) return -1;
+    const uint32_t key = (uint32_t)x + 1;
+    for (uint32_t i = hslot<TB>(x);; i = (i + 1) & (Tab<TB>::CAP - 1)) {
+        uint32_t expect = 0;
+        if (__hip_atomic_compare_exchange_strong(T + i, &expect, key, __ATOMIC_RELAXED, __ATOMIC_RELAXED, WGS))
+            return (int)i;
     }
 }
 
-// Inserts x, known to be absent and inserted by this thread only; false if
-// the table is full (it then stays without x).
-__device__ __forceinline__ bool table_put(uint32_t* T, int32_t* cnt, int32_t x) {
-    if (atomicAdd(cnt, 1) >= HLIMIT) return false;
+// Finds or inserts x with a bounded table: returns x's position, *fresh
+// telling whether this call inserted it, or -1 when an insert would take the
+// table past its entry limit (a reservation is taken before each insert
+// try, so the table never holds more). The caller gives the sample up on -1.
+template <int TB>
+__device__ __forceinline__ int table_visit_bounded(uint32_t* T, int32_t* cnt, int32_t x, bool* fresh) {
     const uint32_t key = (uint32_t)x + 1;
-    for (uint32_t i = hslot(x);; i = (i + 1) & (HCAP - 1)) {
-        uint32_t expect = 0;
-        if (__hip_atomic_compare_exchange_strong(T + i, &expect, key, __ATOMIC_RELAXED, __ATOMIC_RELAXED, WGS))
-            return true;
+    *fresh = false;
+    for (uint32_t i = hslot<TB>(x);; i = (i + 1) & (Tab<TB>::CAP - 1)) {
+        uint32_t v = __hip_atomic_load(T + i, __ATOMIC_RELAXED, WGS);
+        if (v == 0) {
+            if (atomicAdd(cnt, 1) >= Tab<TB>::LIMIT) return -1;
+            uint32_t expect = 0;
+            if (__hip_atomic_compare_exchange_strong(T + i, &expect, key, __ATOMIC_RELAXED, __ATOMIC_RELAXED, WGS)) {
+                *fresh = true;
+                return (int)i;
+            }
+            v = expect;
+        }
+        if (v == key) return (int)i;
     }
 }
 
 // Finds or inserts x; true iff this call inserted it. The caller guarantees
-// room (fewer than HCAP entries after every possible insert).
+// room (fewer than HCAP entries after every possible insert). Per-node slots.
 __device__ __forceinline__ bool table_visit(uint32_t* T, int32_t* cnt, int32_t x) {
     const uint32_t key = (uint32_t)x + 1;
-    for (uint32_t i = hslot(x);; i = (i + 1) & (HCAP - 1)) {
+    for (uint32_t i = hslot<HBITS>(x);; i = (i + 1) & (HCAP - 1)) {
         uint32_t v = __hip_atomic_load(T + i, __ATOMIC_RELAXED, WGS);
         if (v == 0) {
             uint32_t expect = 0;
@@ -253,6 +359,7 @@ __device__ __forceinline__ int32_t lane_search(int32_t lo, int32_t hi, Pred pred
 // ------------------------------------------------------------ workgroup state
 struct SampleShared {
     int32_t node[CH];
+    int32_t npos[CH];     // compact slots: the staged node's position in its side's table
     int32_t beg[CH];
     int32_t off[CH];
     uint64_t sig[CH];
@@ -276,7 +383,8 @@ struct SampleShared {
     int32_t hcnt[2];      // entries reserved in each side's table
     int32_t spilled[2];   // the side's visited set lives in its device bitmap
     int32_t spill_req[2]; // the side's table overflowed in the level being built
-    int32_t status;   // 0 running, 1 met, 2 unreachable
+    int32_t status;   // 0 running, 1 met, 2 unreachable, 3 given up (outgrew a compact slot)
+    int32_t abort;    // a table of a compact slot is full
     int32_t side;     // side of the level being built
     int32_t ovf;
     int32_t walk_err;
@@ -285,6 +393,8 @@ struct SampleShared {
     unsigned long long nx_idx;
     int32_t nx_ok, nx_task, nx_s, nx_t;
     unsigned long long phase_ticks[5];  // start, BFS, meeting + DAG, walk (+ next pair), clearing
+    unsigned long long spills;          // samples of this workgroup that spilled a side
+    unsigned long long deferred;        // samples this compact workgroup handed on
     // per-sample statistics of one task, summed here by thread 0 and added to
     // the task's counters when the workgroup moves to another task
     unsigned long long acc_samples, acc_reach, acc_sum_I, acc_sum_I2, acc_ovf, acc_first;
@@ -369,26 +479,34 @@ __device__ __forceinline__ uint64_t wave_incl_scan_u64(uint64_t v) {
 // start, degree prefix sum, shortest-path count and overflow flag of each;
 // returns the number of adjacency entries of the chunk. Every thread must
 // call it.
-template <int BSZ, int SIDE>
-__device__ __forceinline__ int stage_chunk(G<int32_t>* q, int base, int cnt, const G<int32_t>* rp, G<NodeRec>* R,
-                                           bool read_ovf, SampleShared& sh, Counters& cn) {
+template <int BSZ, int SIDE, bool CMP>
+__device__ __forceinline__ int stage_chunk(G<int32_t>* q, int base, int cnt, const G<int32_t>* rp,
+                                           const Recs<CMP>& rc, bool read_ovf, SampleShared& sh, Counters& cn) {
     const int tid = threadIdx.x;
     int deg = 0, beg = 0;
     int32_t u = 0;
+    int p = 0;
     uint64_t su = 0;
     uint32_t of = 0;
     if (tid < cnt) {
-        u = ldq(q + base + tid);
+        const int32_t e = ldq(q + base + tid);
+        if constexpr (CMP) {
+            p = e;  // compact slots queue table positions
+            u = (int32_t)tab<HBITS_C>(SIDE)[p] - 1;
+        } else {
+            u = e;
+        }
         beg = rp[u];
         deg = rp[u + 1] - beg;
-        su = ld64(SG<SIDE>(R, u));
-        if (read_ovf) of = (ld32(LV<SIDE>(R, u)) & OVFBIT) ? 1 : 0;
+        su = ld64(rc.template sg<SIDE>(u, p));
+        if (read_ovf) of = (ld32(rc.template lv<SIDE>(u, p)) & OVFBIT) ? 1 : 0;
         cn.V++;
     }
     int total;
     const int ex = chunk_excl_scan<BSZ>(deg, sh.wsum, total);
     if (tid < chunk_len<BSZ>()) {
         sh.node[tid] = u;
+        if constexpr (CMP) sh.npos[tid] = p;
         sh.beg[tid] = beg;
         sh.off[tid] = ex;
         sh.sig[tid] = su;
@@ -436,9 +554,9 @@ __device__ __forceinline__ void wave_sum_wrap(uint64_t& v, uint32_t& wrap) {
 // (no parallel arcs), so the adds are checked for wrapping (`careful`) only
 // when that sum reached 2^64. The level's own sum and degree sum (the
 // degrees its expansion will scan) are gathered on the way.
-template <int SIDE, int BSZ, bool LDS>
-__device__ void expand_bfs(const GGraph& g, const GSlots& sl, int64_t so, const Vis<LDS>& V, int lo, int hi,
-                           uint32_t nl, bool careful, SampleShared& sh, Counters& cn) {
+template <int SIDE, int BSZ, bool LDS, bool CMP>
+__device__ void expand_bfs(const GGraph& g, const GSlots& sl, int64_t so, const Vis<LDS>& V, const Recs<CMP>& rc,
+                           int lo, int hi, uint32_t nl, bool careful, SampleShared& sh, Counters& cn) {
     using B = Bits;
     const int tid = threadIdx.x;
     const bool by_table = LDS && sh.level_table;   // else: bitmap (device mode) or record CAS (LDS mode)
@@ -446,7 +564,6 @@ __device__ void expand_bfs(const GGraph& g, const GSlots& sl, int64_t so, const 
     const G<int32_t>* rp = SIDE ? g.irp : g.rp;
     const G<int32_t>* col = SIDE ? g.icol : g.col;
     G<int32_t>* q = (SIDE ? sl.q_t : sl.q_s) + so;
-    G<NodeRec>* R = sl.rec + so;
     G<uint32_t>* vis_mine = V.bm[SIDE];
     uint64_t mass = 0, dsum = 0;
     uint32_t wrap = 0;
@@ -454,7 +571,7 @@ __device__ void expand_bfs(const GGraph& g, const GSlots& sl, int64_t so, const 
     constexpr int CHK = chunk_len<BSZ>();
     for (int base = lo; base < hi; base += CHK) {
         const int cnt = min(CHK, hi - base);
-        const int total = stage_chunk<BSZ, SIDE>(q, base, cnt, rp, R, careful, sh, cn);
+        const int total = stage_chunk<BSZ, SIDE, CMP>(q, base, cnt, rp, rc, careful, sh, cn);
         for (int b0 = 0; b0 < total; b0 += BSZ * UNROLL) {
             int32_t w[UNROLL];
             int jj[UNROLL];
@@ -469,9 +586,18 @@ __device__ void expand_bfs(const GGraph& g, const GSlots& sl, int64_t so, const 
                     w[k] = col[sh.beg[jj[k]] + (e - sh.off[jj[k]])];
                 }
             }
+            int po[UNROLL];  // compact slots: the arc's head in the other side's table
 #pragma unroll
-            for (int k = 0; k < UNROLL; k++)
-                if (jj[k] >= 0 && member<LDS>(V, sh, 1 - SIDE, w[k])) into_other |= 1u << k;
+            for (int k = 0; k < UNROLL; k++) {
+                po[k] = -1;
+                if (jj[k] < 0) continue;
+                if constexpr (CMP) {
+                    po[k] = table_find<HBITS_C>(tab<HBITS_C>(1 - SIDE), w[k]);
+                    if (po[k] >= 0) into_other |= 1u << k;
+                } else if (member<LDS>(V, sh, 1 - SIDE, w[k])) {
+                    into_other |= 1u << k;
+                }
+            }
             // A level with an arc into the other ball is the last one, and of
             // its new nodes only the meeting layer is used again: once any
             // thread has seen such an arc, arcs to other nodes are skipped.
@@ -491,12 +617,26 @@ __device__ void expand_bfs(const GGraph& g, const GSlots& sl, int64_t so, const 
                 const int32_t x = w[k];
                 const int j = jj[k];
                 bool add, fresh = false, lv_written = false;
-                if (!LDS) {
+                int p = 0;  // compact slots: x's position in this side's table
+                if constexpr (CMP) {
+                    // the bounded table decides; a full table gives the sample up
+                    p = table_visit_bounded<HBITS_C>(tab<HBITS_C>(SIDE), &sh.hcnt[SIDE], x, &fresh);
+                    if (p < 0) {
+                        sh.abort = 1;
+                        continue;
+                    }
+                    if (fresh) {
+                        add = true;
+                    } else {
+                        const uint32_t lv = ld32(rc.template lv<SIDE>(x, p)) & LVMASK;
+                        add = lv == 0 || lv == nl;
+                    }
+                } else if (!LDS) {
                     if (!B::test(B::rd(vis_mine, x), x)) {
                         fresh = !B::test(B::set(vis_mine, x), x);
                         add = true;
                     } else {
-                        const uint32_t lv = ld32(LV<SIDE>(R, x)) & LVMASK;
+                        const uint32_t lv = ld32(rc.template lv<SIDE>(x, p)) & LVMASK;
                         add = lv == 0 || lv == nl;
                     }
                 } else if (by_table) {
@@ -504,31 +644,31 @@ __device__ void expand_bfs(const GGraph& g, const GSlots& sl, int64_t so, const 
                     if (fresh) {
                         add = true;
                     } else {
-                        const uint32_t lv = ld32(LV<SIDE>(R, x)) & LVMASK;
+                        const uint32_t lv = ld32(rc.template lv<SIDE>(x, p)) & LVMASK;
                         add = lv == 0 || lv == nl;
                     }
                 } else {
                     // the record's level field decides: 0 = not reached yet
                     uint32_t old = 0;
-                    fresh = __hip_atomic_compare_exchange_strong(LV<SIDE>(R, x), &old, nl, __ATOMIC_RELAXED,
-                                                                 __ATOMIC_RELAXED, WGS);
+                    fresh = __hip_atomic_compare_exchange_strong(rc.template lv<SIDE>(x, p), &old, nl,
+                                                                 __ATOMIC_RELAXED, __ATOMIC_RELAXED, WGS);
                     add = fresh || (old & LVMASK) == nl;
                     lv_written = true;
                     if (fresh) {
                         if (sh.spilled[SIDE]) (void)B::set(vis_mine, x);
-                        else if (!table_put(tab(SIDE), &sh.hcnt[SIDE], x)) sh.spill_req[SIDE] = 1;
+                        else if (table_put(tab(SIDE), &sh.hcnt[SIDE], x) < 0) sh.spill_req[SIDE] = 1;
                     }
                 }
                 if (add) {
                     const uint64_t addv = sh.sig[j];
                     if (careful) {
-                        const uint64_t old = add64(SG<SIDE>(R, x), addv);
+                        const uint64_t old = add64(rc.template sg<SIDE>(x, p), addv);
                         if (old + addv < old || sh.of[j]) {
-                            or32(LV<SIDE>(R, x), OVFBIT);
+                            or32(rc.template lv<SIDE>(x, p), OVFBIT);
                             wrap = 1u;
                         }
                     } else {
-                        (void)add64(SG<SIDE>(R, x), addv);
+                        (void)add64(rc.template sg<SIDE>(x, p), addv);
                     }
                     const uint64_t nm = mass + addv;
                     wrap |= nm < mass ? 1u : 0u;
@@ -541,20 +681,26 @@ __device__ void expand_bfs(const GGraph& g, const GSlots& sl, int64_t so, const 
                     // t-level b - 1, one of its out-neighbours: this is the
                     // first step of the sigma_s pull, done while the arc is
                     // at hand
-                    const uint64_t ss = ld64(&R[x].sg_s);
-                    (void)add64(&R[sh.node[j]].sg_s, ss);
+                    const uint64_t ss = ld64(rc.ws(0, x, po[k]));
+                    (void)add64(rc.ws(1, sh.node[j], CMP ? sh.npos[j] : 0), ss);
                     record_arc(arcs, sl.acap, sh, x, sh.node[j], ss);
                     cn.A++;
                 }
                 if (fresh) {
-                    if (!lv_written) or32(LV<SIDE>(R, x), nl);
+                    if (!lv_written) or32(rc.template lv<SIDE>(x, p), nl);
                     const int pos = atomicAdd(&sh.tail, 1);
-                    q[pos] = x;
+                    q[pos] = CMP ? p : x;
                     cn.Vd++;
                     dsum += (uint64_t)(rp[x + 1] - rp[x]);
                     if ((into_other >> k) & 1u) {
                         const int mp = atomicAdd(&sh.nmeet, 1);
-                        sl.q_d[so + mp] = x;
+                        if constexpr (CMP) {
+                            // the meeting node's position on each side
+                            sl.q_d[2 * so + mp] = SIDE ? po[k] : p;
+                            sl.q_d[2 * so + CCAP + mp] = SIDE ? p : po[k];
+                        } else {
+                            sl.q_d[so + mp] = x;
+                        }
                     }
                 }
             }
@@ -575,20 +721,26 @@ __device__ void expand_bfs(const GGraph& g, const GSlots& sl, int64_t so, const 
 // adds the sigma_s of its in-neighbours at t-level j (t-level value
 // want = j + 1). Counts of nodes off the shortest-path DAG are 0, so only
 // DAG arcs add. No count here exceeds sigma_st, known to be below 2^64.
-template <int BSZ, bool LDS>
-__device__ void pull_level(const GGraph& g, const GSlots& sl, int64_t so, const Vis<LDS>& V, int lo, int hi,
-                           uint32_t want, SampleShared& sh, Counters& cn) {
+template <int BSZ, bool LDS, bool CMP>
+__device__ void pull_level(const GGraph& g, const GSlots& sl, int64_t so, const Vis<LDS>& V, const Recs<CMP>& rc,
+                           int lo, int hi, uint32_t want, SampleShared& sh, Counters& cn) {
     const int tid = threadIdx.x;
     G<int32_t>* q = sl.q_t + so;
-    G<NodeRec>* R = sl.rec + so;
     G<DagArc>* arcs = sl.arcs + (int64_t)blockIdx.x * sl.acap;
     constexpr int CHK = chunk_len<BSZ>();
     for (int base = lo; base < hi; base += CHK) {
         const int cnt = min(CHK, hi - base);
         int deg = 0, beg = 0;
         int32_t x = 0;
+        int px = 0;
         if (tid < cnt) {
-            x = ldq(q + base + tid);
+            const int32_t e = ldq(q + base + tid);
+            if constexpr (CMP) {
+                px = e;
+                x = (int32_t)tab<HBITS_C>(1)[px] - 1;
+            } else {
+                x = e;
+            }
             beg = g.irp[x];
             deg = g.irp[x + 1] - beg;
             cn.V++;
@@ -599,21 +751,30 @@ __device__ void pull_level(const GGraph& g, const GSlots& sl, int64_t so, const 
             sh.beg[tid] = beg;
             sh.off[tid] = ex;
             sh.sig[tid] = (uint64_t)(uint32_t)x;
+            if constexpr (CMP) sh.npos[tid] = px;
         }
         __syncthreads();
         for (int e = tid; e < total; e += BSZ) {
             const int j = chunk_owner(sh, cnt, e);
             const int32_t u = g.icol[sh.beg[j] + (e - sh.off[j])];
             cn.E++;
-            if (!member<LDS>(V, sh, 1, u)) continue;
+            int pu = 0;
+            if constexpr (CMP) {
+                pu = table_find<HBITS_C>(tab<HBITS_C>(1), u);
+                if (pu < 0) continue;
+            } else if (!member<LDS>(V, sh, 1, u)) {
+                continue;
+            }
             // levels of this level's nodes are final (set before the last
             // barrier); their sigma_s was completed by the previous pull level
-            const u32x4 rec = *reinterpret_cast<const G<u32x4>*>(&R[u]);
-            if ((rec.y & LVMASK) != want) continue;
-            const uint64_t su = ((uint64_t)rec.w << 32) | rec.z;
+            uint32_t lvu;
+            uint64_t su;
+            rc.lv_ws(1, u, pu, lvu, su);
+            if ((lvu & LVMASK) != want) continue;
             if (su) {
-                (void)add64(&R[(int32_t)sh.sig[j]].sg_s, su);
-                record_arc(arcs, sl.acap, sh, u, (int32_t)sh.sig[j], su);
+                const int32_t xj = (int32_t)sh.sig[j];
+                (void)add64(rc.ws(1, xj, CMP ? sh.npos[j] : 0), su);
+                record_arc(arcs, sl.acap, sh, u, xj, su);
                 cn.A++;
             }
         }
@@ -625,24 +786,29 @@ __device__ void pull_level(const GGraph& g, const GSlots& sl, int64_t so, const 
 // expanded last and the meeting layer's out-rows are shorter than the in-rows
 // of t-level b - 1): every meeting node w adds sigma_s(w) to its
 // out-neighbours at t-level b - 1 (t-level value want = b).
-template <int BSZ, bool LDS>
-__device__ void push_meeting(const GGraph& g, const GSlots& sl, int64_t so, const Vis<LDS>& V, int nmeet,
-                             uint32_t want, SampleShared& sh, Counters& cn) {
+template <int BSZ, bool LDS, bool CMP>
+__device__ void push_meeting(const GGraph& g, const GSlots& sl, int64_t so, const Vis<LDS>& V, const Recs<CMP>& rc,
+                             int nmeet, uint32_t want, SampleShared& sh, Counters& cn) {
     const int tid = threadIdx.x;
-    G<NodeRec>* R = sl.rec + so;
-    G<int32_t>* qd = sl.q_d + so;
+    G<int32_t>* qd = sl.q_d + (CMP ? 2 * so : so);  // compact: the meeting nodes' s positions
     G<DagArc>* arcs = sl.arcs + (int64_t)blockIdx.x * sl.acap;
     constexpr int CHK = chunk_len<BSZ>();
     for (int base = 0; base < nmeet; base += CHK) {
         const int cnt = min(CHK, nmeet - base);
-        const int total = stage_chunk<BSZ, 0>(qd, base, cnt, g.rp, R, false, sh, cn);
+        const int total = stage_chunk<BSZ, 0, CMP>(qd, base, cnt, g.rp, rc, false, sh, cn);
         for (int e = tid; e < total; e += BSZ) {
             const int j = chunk_owner(sh, cnt, e);
             const int32_t x = g.col[sh.beg[j] + (e - sh.off[j])];
             cn.E++;
-            if (!member<LDS>(V, sh, 1, x)) continue;
-            if ((ld32(&R[x].lv_t) & LVMASK) != want) continue;
-            (void)add64(&R[x].sg_s, sh.sig[j]);
+            int px = 0;
+            if constexpr (CMP) {
+                px = table_find<HBITS_C>(tab<HBITS_C>(1), x);
+                if (px < 0) continue;
+            } else if (!member<LDS>(V, sh, 1, x)) {
+                continue;
+            }
+            if ((ld32(rc.template lv<1>(x, px)) & LVMASK) != want) continue;
+            (void)add64(rc.ws(1, x, px), sh.sig[j]);
             record_arc(arcs, sl.acap, sh, sh.node[j], x, sh.sig[j]);
             cn.A++;
         }
@@ -703,7 +869,7 @@ __device__ void claim_next(const SampleLaunch& L, unsigned long long npairs, Sam
 // a launch given, wave 1 claims and draws the next sample during the walk. In
 // debug mode (dbg != nullptr) the path index is given instead of drawn, hits
 // are not touched and the path is written to dbg (internal ids).
-template <int BSZ, bool LDS>
+template <int BSZ, bool LDS, bool CMP>
 __device__ __forceinline__ void run_sample(const GGraph& g, const GSlots& sl, int64_t so, const Vis<LDS>& V,
                                            uint64_t idx, const DevTask& T, int32_t s, int32_t t,
                                            const SampleLaunch* next, unsigned long long npairs, uint32_t q_rel,
@@ -711,10 +877,11 @@ __device__ __forceinline__ void run_sample(const GGraph& g, const GSlots& sl, in
                                            uint64_t dbg_r, int32_t dbg_cap) {
     using B = Bits;
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-    G<NodeRec>* R = sl.rec + so;
+    constexpr int TB = tbits<CMP>();
+    const Recs<CMP> rc{CMP ? nullptr : sl.rec + so, CMP ? sl.crec + (int64_t)blockIdx.x * 2 * CCAP : nullptr};
     G<int32_t>* q_s = sl.q_s + so;
     G<int32_t>* q_t = sl.q_t + so;
-    G<int32_t>* q_d = sl.q_d + so;
+    G<int32_t>* q_d = sl.q_d + (CMP ? 2 * so : so);  // compact: s positions, then t positions at + CCAP
     G<int32_t>* tls = sl.tls + (int64_t)blockIdx.x * (sl.stride + 2);  // start of each t-level in q_t
 
     // phase timers (thread 0, constant-rate wall clock)
@@ -739,21 +906,27 @@ __device__ __forceinline__ void run_sample(const GGraph& g, const GSlots& sl, in
             sh.hcnt[0] = sh.hcnt[1] = 0;
             sh.spilled[0] = sh.spilled[1] = 0;
             sh.spill_req[0] = sh.spill_req[1] = 0;
+            sh.abort = 0;
             if (s >= g.n_act || t >= g.n_act) {
                 // a node without arcs reaches nothing and is reached by nothing
                 sh.status = 2;
                 sh.tail_s = 0; sh.tail_t = 0;
             } else {
                 sh.status = 0;
+                int ps = 0, pt = 0;
                 if (LDS) {
-                    (void)table_put(tab(0), &sh.hcnt[0], s);
-                    (void)table_put(tab(1), &sh.hcnt[1], t);
+                    ps = table_put<TB>(tab<TB>(0), &sh.hcnt[0], s);
+                    pt = table_put<TB>(tab<TB>(1), &sh.hcnt[1], t);
                 } else {
                     B::set(V.bm[0], s);
                     B::set(V.bm[1], t);
                 }
-                or32(&R[s].lv_s, 1u); R[s].sg_s = 1; q_s[0] = s;
-                or32(&R[t].lv_t, 1u); R[t].sg_t = 1; q_t[0] = t;
+                or32(rc.template lv<0>(s, ps), 1u);
+                *rc.template sg<0>(s, ps) = 1;
+                q_s[0] = CMP ? ps : s;
+                or32(rc.template lv<1>(t, pt), 1u);
+                *rc.template sg<1>(t, pt) = 1;
+                q_t[0] = CMP ? pt : t;
                 tls[0] = 0; tls[1] = 1;
                 sh.lo_s = 0; sh.hi_s = 1; sh.lo_t = 0; sh.hi_t = 1;
                 sh.deg_s = (unsigned long long)(g.rp[s + 1] - g.rp[s]);
@@ -775,11 +948,13 @@ __device__ __forceinline__ void run_sample(const GGraph& g, const GSlots& sl, in
         const int side = sh.side;
         const int nlo = side == 0 ? sh.hi_s : sh.hi_t;
         const bool careful = (side == 0 ? sh.wide_s : sh.wide_t) != 0;
-        if (side == 0) expand_bfs<0, BSZ, LDS>(g, sl, so, V, sh.lo_s, sh.hi_s, (uint32_t)sh.a + 2, careful, sh, cn);
-        else expand_bfs<1, BSZ, LDS>(g, sl, so, V, sh.lo_t, sh.hi_t, (uint32_t)sh.b + 2, careful, sh, cn);
+        if (side == 0)
+            expand_bfs<0, BSZ, LDS, CMP>(g, sl, so, V, rc, sh.lo_s, sh.hi_s, (uint32_t)sh.a + 2, careful, sh, cn);
+        else
+            expand_bfs<1, BSZ, LDS, CMP>(g, sl, so, V, rc, sh.lo_t, sh.hi_t, (uint32_t)sh.b + 2, careful, sh, cn);
         level_barrier();
         const int nhi = sh.tail;
-        if (LDS && sh.spill_req[side]) {
+        if (!CMP && LDS && sh.spill_req[side]) {
             // the side's table overflowed: its whole ball (its queue) moves to
             // the device bitmap, which answers for the side from now on
             G<int32_t>* qq = side == 0 ? q_s : q_t;
@@ -800,7 +975,8 @@ __device__ __forceinline__ void run_sample(const GGraph& g, const GSlots& sl, in
                 sh.deg_t = sh.deg_next; sh.wide_t = sh.wide_next;
                 tls[sh.b + 1] = nhi;
             }
-            if (sh.nmeet > 0) sh.status = 1;
+            if (CMP && sh.abort) sh.status = 3;
+            else if (sh.nmeet > 0) sh.status = 1;
             else if (nhi == nlo) sh.status = 2;
             else plan_level(sh);
         }
@@ -818,11 +994,20 @@ __device__ __forceinline__ void run_sample(const GGraph& g, const GSlots& sl, in
             uint64_t acc = 0, pc = 0;
             int of = 0;
             for (int i = lane; i < sh.nmeet; i += 64) {
-                const int32_t w = ldq(q_d + i);
+                int32_t w;
+                int ps = 0, pt = 0;
+                if constexpr (CMP) {
+                    ps = ldq(q_d + i);
+                    pt = ldq(q_d + CCAP + i);
+                    w = (int32_t)tab<HBITS_C>(0)[ps] - 1;
+                } else {
+                    w = ldq(q_d + i);
+                }
                 pc += (uint64_t)(g.rp[w + 1] - g.rp[w]);
-                const uint32_t ls = ld32(&R[w].lv_s), lt = ld32(&R[w].lv_t);
+                const uint32_t ls = ld32(rc.template lv<0>(w, ps)), lt = ld32(rc.template lv<1>(w, pt));
                 of |= ((ls | lt) & OVFBIT) ? 1 : 0;
-                const uint64_t x = ld64(&R[w].sg_s), y = ld64(&R[w].sg_t);
+                const uint64_t x = ld64(rc.template sg<0>(w, ps)), y = ld64(rc.template sg<1>(w, pt));
+                if constexpr (CMP) *rc.ws(1, w, pt) = x;  // the t record carries sigma_s for the sweep
                 if (__umul64hi(x, y) != 0) of = 1;
                 const uint64_t p = x * y;
                 const uint64_t na = acc + p;
@@ -855,12 +1040,12 @@ __device__ __forceinline__ void run_sample(const GGraph& g, const GSlots& sl, in
             if (sh.side == 1) {
                 j--;
             } else if (j >= 1 && sh.push_cost < sh.deg_t_prev) {
-                push_meeting<BSZ, LDS>(g, sl, so, V, sh.nmeet, (uint32_t)j, sh, cn);
+                push_meeting<BSZ, LDS, CMP>(g, sl, so, V, rc, sh.nmeet, (uint32_t)j, sh, cn);
                 level_barrier();
                 j--;
             }
             for (; j >= 1; j--) {
-                pull_level<BSZ, LDS>(g, sl, so, V, ldq(tls + j - 1), ldq(tls + j), (uint32_t)j + 1, sh, cn);
+                pull_level<BSZ, LDS, CMP>(g, sl, so, V, rc, ldq(tls + j - 1), ldq(tls + j), (uint32_t)j + 1, sh, cn);
                 level_barrier();
             }
         }
@@ -951,10 +1136,21 @@ __device__ __forceinline__ void run_sample(const GGraph& g, const GSlots& sl, in
 #pragma unroll
                         for (int k = 0; k < WALK_UNROLL; k++) {
                             wt[k] = 0;
-                            if (u[k] >= 0 && member<LDS>(V, sh, on_s ? 0 : 1, u[k])) {
-                                const u32x4 rec = *reinterpret_cast<const G<u32x4>*>(&R[u[k]]);
-                                const uint32_t lv = on_s ? rec.x : rec.y;
-                                if ((lv & LVMASK) == want) wt[k] = ((uint64_t)rec.w << 32) | rec.z;
+                            int pu = 0;
+                            bool in_ball = false;
+                            if (u[k] >= 0) {
+                                if constexpr (CMP) {
+                                    pu = table_find<HBITS_C>(tab<HBITS_C>(on_s ? 0 : 1), u[k]);
+                                    in_ball = pu >= 0;
+                                } else {
+                                    in_ball = member<LDS>(V, sh, on_s ? 0 : 1, u[k]);
+                                }
+                            }
+                            if (in_ball) {
+                                uint32_t lvu;
+                                uint64_t su;
+                                rc.lv_ws(on_s ? 0 : 1, u[k], pu, lvu, su);
+                                if ((lvu & LVMASK) == want) wt[k] = su;
                             }
                             if (u[k] >= 0) cn.E++;
                         }
@@ -998,7 +1194,16 @@ __device__ __forceinline__ void run_sample(const GGraph& g, const GSlots& sl, in
     // ---- per-sample statistics
     if (tid == 0) {
         if (!dbg) {
-            sh.acc_samples++;
+            if (sh.status == 3) {
+                // outgrew the compact slot: listed for the per-node slots,
+                // which count the sample
+                const unsigned long long at = atomicAdd(next->nbig, 1ull);
+                next->big[at] = PairRec{q_rel, s, t, task};
+                sh.deferred++;
+            } else {
+                sh.acc_samples++;
+            }
+            if (sh.spilled[0] | sh.spilled[1]) sh.spills++;
             if (sh.status == 1) {
                 if (sh.ovf && !sh.walk_err) {
                     // sigma_st >= 2^64: listed for the 128-bit path, which
@@ -1029,22 +1234,19 @@ __device__ __forceinline__ void run_sample(const GGraph& g, const GSlots& sl, in
     // ---- clear what this sample touched (every node reached is in q_s or q_t)
     const int ts = sh.tail_s, tt = sh.tail_t;
     const bool bm_s = !LDS || sh.spilled[0], bm_t = !LDS || sh.spilled[1];
+    // (queue entries are node ids, or table positions in compact slots)
     for (int i = tid; i < ts; i += BSZ) {
-        const int32_t w = ldq(q_s + i);
-        G<u32x4>* z = reinterpret_cast<G<u32x4>*>(&R[w]);
-        z[0] = u32x4{0u, 0u, 0u, 0u};
-        z[1] = u32x4{0u, 0u, 0u, 0u};
-        if (bm_s) B::clear_word(V.bm[0], w);
+        const int32_t e = ldq(q_s + i);
+        rc.clear(0, e, e);
+        if (!CMP && bm_s) B::clear_word(V.bm[0], e);
     }
     for (int i = tid; i < tt; i += BSZ) {
-        const int32_t w = ldq(q_t + i);
-        G<u32x4>* z = reinterpret_cast<G<u32x4>*>(&R[w]);
-        z[0] = u32x4{0u, 0u, 0u, 0u};
-        z[1] = u32x4{0u, 0u, 0u, 0u};
-        if (bm_t) B::clear_word(V.bm[1], w);
+        const int32_t e = ldq(q_t + i);
+        rc.clear(1, e, e);
+        if (!CMP && bm_t) B::clear_word(V.bm[1], e);
     }
     if (LDS) {
-        for (int i = tid; i < 2 * HCAP; i += BSZ) __hip_atomic_store(dyn_lds + i, 0u, __ATOMIC_RELAXED, WGS);
+        for (int i = tid; i < 2 * Tab<TB>::CAP; i += BSZ) __hip_atomic_store(dyn_lds + i, 0u, __ATOMIC_RELAXED, WGS);
     }
     level_barrier();
     phase_mark(4);
@@ -1090,7 +1292,9 @@ __device__ __forceinline__ Vis<LDS> slot_vis(const GSlots& sl, int slot) {
 #define SAMPLER_OCCUPANCY
 #endif
 
-template <int BSZ, bool LDS>
+// CMP: compact slots (records by table position; a sample that outgrows them
+// is listed in L.big for per-node slots).
+template <int BSZ, bool LDS, bool CMP>
 __global__ __launch_bounds__(BSZ) SAMPLER_OCCUPANCY void sampler_kernel(DevSlots slots, SampleLaunch L) {
     __shared__ SampleShared sh;
     const int tid = threadIdx.x;
@@ -1099,10 +1303,12 @@ __global__ __launch_bounds__(BSZ) SAMPLER_OCCUPANCY void sampler_kernel(DevSlots
     const Vis<LDS> V = slot_vis<BSZ, LDS>(sl, blockIdx.x);
     Counters cn = {0, 0, 0, 0};
     if (LDS) {
-        for (int i = tid; i < 2 * HCAP; i += BSZ) dyn_lds[i] = 0;
+        for (int i = tid; i < 2 * Tab<tbits<CMP>()>::CAP; i += BSZ) dyn_lds[i] = 0;
     }
     if (tid == 0) {
         for (int i = 0; i < 5; i++) sh.phase_ticks[i] = 0;
+        sh.spills = 0;
+        sh.deferred = 0;
         sh.acc_task = -1;
         flush_task_stats(sh, L);
     }
@@ -1122,13 +1328,15 @@ __global__ __launch_bounds__(BSZ) SAMPLER_OCCUPANCY void sampler_kernel(DevSlots
             flush_task_stats(sh, L);
             sh.acc_task = k;
         }
-        run_sample<BSZ, LDS>(gview(T.g), sl, so, V, T.first + (q - T.offset), T, s, t, &L, npairs,
-                             (uint32_t)(q - L.base), k, sh, cn, nullptr, 0, 0);
+        run_sample<BSZ, LDS, CMP>(gview(T.g), sl, so, V, T.first + (q - T.offset), T, s, t, &L, npairs,
+                                  (uint32_t)(q - L.base), k, sh, cn, nullptr, 0, 0);
     }
     flush_counters(cn, L.stats);
     if (tid == 0) {
         flush_task_stats(sh, L);
         for (int i = 0; i < 5; i++) atomicAdd(&L.stats->phase_ticks[i], sh.phase_ticks[i]);
+        atomicAdd(&L.stats->spills, sh.spills);
+        if (CMP) atomicAdd(&L.stats->deferred, sh.deferred);
     }
 }
 
@@ -1147,7 +1355,7 @@ __global__ __launch_bounds__(BSZ) void debug_path_kernel(DevGraph g, DevSlots sl
     }
     __syncthreads();
     DevTask T = {};
-    run_sample<BSZ, LDS>(gview(g), sl, 0, V, 0, T, s, t, nullptr, 0, 0, -1, sh, cn, out, r, cap);
+    run_sample<BSZ, LDS, false>(gview(g), sl, 0, V, 0, T, s, t, nullptr, 0, 0, -1, sh, cn, out, r, cap);
 }
 
 __global__ void fill_u32_kernel(uint32_t* p, uint32_t v, int64_t count) {
@@ -1217,11 +1425,14 @@ __global__ __launch_bounds__(256) void pair_kernel(SampleLaunch L) {
     }
 }
 
-__global__ void init_chunk_kernel(unsigned long long* work, unsigned long long* npairs, unsigned long long* nwide) {
+__global__ void init_chunk_kernel(unsigned long long* work, unsigned long long* npairs, unsigned long long* nwide,
+                                  unsigned long long* nbig, unsigned long long* big_work) {
     if (threadIdx.x == 0) {
         *work = 0;
         *npairs = 0;
         *nwide = 0;
+        *nbig = 0;
+        *big_work = 0;
     }
 }
 
@@ -1433,7 +1644,7 @@ __global__ void init_stats_kernel(DevStats* st, unsigned long long* work) {
     if (threadIdx.x == 0) {
         st->samples = st->reachable = st->sum_I = st->sum_I2 = st->overflow = 0;
         st->first_overflow = ~0ull;
-        st->edges = st->sigma_adds = st->vexp = st->vdisc = 0;
+        st->edges = st->sigma_adds = st->vexp = st->vdisc = st->spills = st->deferred = 0;
         for (int i = 0; i < 5; i++) st->phase_ticks[i] = 0;
         *work = 0;
     }
@@ -1447,7 +1658,7 @@ __global__ void clear_tasks_kernel(const DevTask* tasks, int ntasks) {
         DevStats* st = T.stats;
         st->samples = st->reachable = st->sum_I = st->sum_I2 = st->overflow = 0;
         st->first_overflow = ~0ull;
-        st->edges = st->sigma_adds = st->vexp = st->vdisc = 0;
+        st->edges = st->sigma_adds = st->vexp = st->vdisc = st->spills = st->deferred = 0;
         for (int i = 0; i < 5; i++) st->phase_ticks[i] = 0;
     }
     if (T.clear_hits) {
@@ -1477,7 +1688,7 @@ hipError_t launch_fill_u8(void* p, int64_t bytes, hipStream_t stream) {
 
 hipError_t launch_wide(const SampleLaunch& a, const WideSlots& w, int slots, hipStream_t stream) {
     if (slots <= 0) return hipSuccess;
-    hipLaunchKernelGGL(init_chunk_kernel, dim3(1), dim3(64), 0, stream, w.work, w.work, w.work);
+    hipLaunchKernelGGL(init_chunk_kernel, dim3(1), dim3(64), 0, stream, w.work, w.work, w.work, w.work, w.work);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(wide_kernel, dim3(slots), dim3(WB), 0, stream, a, w);
@@ -1490,7 +1701,7 @@ hipError_t launch_wide_debug(const DevGraph& g, const WideSlots& w, WideDebug* d
 }
 
 hipError_t launch_pairs(const SampleLaunch& a, hipStream_t stream) {
-    hipLaunchKernelGGL(init_chunk_kernel, dim3(1), dim3(64), 0, stream, a.work, a.npairs, a.nwide);
+    hipLaunchKernelGGL(init_chunk_kernel, dim3(1), dim3(64), 0, stream, a.work, a.npairs, a.nwide, a.nbig, a.big_work);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || a.count == 0) return e;
     int64_t blocks = ((int64_t)a.count + 255) / 256;
@@ -1513,14 +1724,24 @@ hipError_t launch_clear_tasks(const DevTask* tasks, int ntasks, int64_t max_n, h
 }
 
 int64_t sampler_static_lds() { return (int64_t)sizeof(SampleShared); }
-int64_t sampler_table_lds() { return (int64_t)2 * HCAP * sizeof(uint32_t); }
+int64_t sampler_table_lds(bool compact) { return (int64_t)2 * (compact ? CCAP : HCAP) * sizeof(uint32_t); }
+int sampler_table_cap(bool compact) { return compact ? CCAP : HCAP; }
 
 template <int BSZ, bool LDS>
 static const void* sampler_fn() {
-    return reinterpret_cast<const void*>(&sampler_kernel<BSZ, LDS>);
+    return reinterpret_cast<const void*>(&sampler_kernel<BSZ, LDS, false>);
 }
 
 static const void* pick_sampler(const SamplerShape& s) {
+    if (s.compact) {
+        if (!s.lds_sets) return nullptr;
+        switch (s.block) {
+            case 64: return reinterpret_cast<const void*>(&sampler_kernel<64, true, true>);
+            case 128: return reinterpret_cast<const void*>(&sampler_kernel<128, true, true>);
+            case 256: return reinterpret_cast<const void*>(&sampler_kernel<256, true, true>);
+            default: return nullptr;
+        }
+    }
     switch (s.block) {
         case 64: return s.lds_sets ? sampler_fn<64, true>() : sampler_fn<64, false>();
         case 128: return s.lds_sets ? sampler_fn<128, true>() : sampler_fn<128, false>();

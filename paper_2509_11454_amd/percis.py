@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(_HERE, "lib", "libpercis.so")
 HOST_ONLY = -1
 OK, E_INVAL, E_STATE, E_NOMEM, E_DEVICE, E_DEGENERATE, E_TOO_LARGE, E_SIGMA_OVERFLOW = 0, -1, -2, -3, -4, -5, -6, -7
 DIRECTED, DEVICE_PTRS, ACCUMULATE = 0x1, 0x2, 0x4
-OPT_SLOTS, OPT_SCRATCH_MB, OPT_BLOCK, OPT_BITMAPS = 1, 2, 3, 4
+OPT_SLOTS, OPT_SCRATCH_MB, OPT_BLOCK, OPT_BITMAPS, OPT_COMPACT, OPT_DEFER_BLOCK = 1, 2, 3, 4, 5, 6
 
 if not os.path.exists(LIB_PATH):
     raise ImportError("libpercis.so is not built (%s); run __graft_entry__.build() or "
@@ -31,7 +31,7 @@ class Stats(C.Structure):
                 ("sum_I2", C.c_uint64), ("overflow", C.c_uint64), ("first_overflow", C.c_uint64),
                 ("edges", C.c_uint64), ("sigma_adds", C.c_uint64), ("vertices_expanded", C.c_uint64),
                 ("vertices_discovered", C.c_uint64), ("kernel_ms", C.c_double), ("phase_ms", C.c_double * 5),
-                ("pair_ms", C.c_double)]
+                ("pair_ms", C.c_double), ("spilled", C.c_uint64), ("deferred", C.c_uint64)]
 
     PHASES = ("start", "bfs", "dag", "walk", "clear")
 
