@@ -136,3 +136,14 @@ def test_option_validation(P):
         c.set_option(P.OPT_BITMAPS, 3)
     with pytest.raises(P.PercisError):
         c.set_option(P.OPT_SLOTS, -1)
+    for v in (0, 1, 2):
+        c.set_option(P.OPT_COMPACT, v)
+        assert c.get_option(P.OPT_COMPACT) == v
+    with pytest.raises(P.PercisError) as e:
+        c.set_option(P.OPT_COMPACT, 3)
+    assert e.value.status == P.E_INVAL
+    for b in (0, 64, 128, 256, 512, 1024):
+        c.set_option(P.OPT_DEFER_BLOCK, b)
+        assert c.get_option(P.OPT_DEFER_BLOCK) == b
+    with pytest.raises(P.PercisError):
+        c.set_option(P.OPT_DEFER_BLOCK, 96)
