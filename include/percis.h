@@ -25,7 +25,9 @@
  *    context's device (for instance the data of torch tensors).
  *  - All device work is enqueued on the context's HIP stream (the null
  *    stream unless one was given); calls that return host results
- *    synchronise that stream before returning.
+ *    synchronise that stream before returning. Captured batches
+ *    (percis_batch_*) replay on a private stream of the context, after its
+ *    stream has drained, and return when they have finished.
  *  - Percolation states are quantised: x_v = k_v / 65535 with k_v in
  *    0..65535; all sampling arithmetic is exact integer arithmetic.
  *  - Graphs are unweighted, given as CSR with int32 node ids; undirected
@@ -199,6 +201,25 @@ typedef struct {
  * NULL) receives the sums over all tasks plus the launch-wide work counters
  * and phase times. Returns PERCIS_E_SIGMA_OVERFLOW if any task overflowed. */
 int percis_sample_tasks(percis_ctx* ctx, int32_t ntasks, const percis_task* tasks, percis_stats* launch_stats);
+
+/* The same launch as a HIP graph, for callers that run one task set again and
+ * again (a batch step): percis_batch_capture uploads the task table, makes
+ * sure the device copies, slots and list buffers exist, and captures the
+ * launch's kernels (task clearing, then per chunk of at most 2^22 samples the
+ * pair kernel, the sampler and the 128-bit path) on a private stream into a
+ * graph owned by *batch. percis_batch_replay launches the graph, waits, and
+ * fills each task's stats (the pointers given at capture) and launch_stats
+ * (may be NULL) as percis_sample_tasks does; kernel_ms is the graph's device
+ * time and pair_ms 0. A replay gives exactly the hits and statistics of
+ * percis_sample_tasks on the same tasks. The capture holds device addresses
+ * and each graph's total weight: after percis_load_csr, percis_set_states,
+ * percis_set_option, or a launch with a larger chunk than any before on this
+ * context, a replay returns PERCIS_E_STATE (capture again). Destroy batches
+ * before their context. Replays of one context run one at a time. */
+typedef struct percis_batch percis_batch;
+int percis_batch_capture(percis_ctx* ctx, int32_t ntasks, const percis_task* tasks, percis_batch** batch);
+int percis_batch_replay(percis_batch* batch, percis_stats* launch_stats);
+void percis_batch_destroy(percis_batch* batch);
 
 /* Algorithm 1 on graph `graph` (percis_estimate is this with graph 0). */
 int percis_graph_estimate(percis_ctx* ctx, int32_t graph, double eps, double delta, uint64_t seed, double* p_out,

@@ -223,6 +223,7 @@ static int graph_set_states(percis_ctx* c, GraphData& G, const uint16_t* k_in, u
     G.d_hat = std::max(1.0, dmax);
     G.has_states = true;
     G.states_on_device = true;
+    c->generation++;  // a captured launch holds the old total weight
     return PERCIS_OK;
 }
 
@@ -290,6 +291,7 @@ static DevCdf dev_cdf(const GraphData& G) {
 }
 
 static void free_slots(percis_ctx* c) {
+    c->generation++;
     if (c->slot_mem) (void)hipFree(c->slot_mem);
     if (c->cslot_mem) (void)hipFree(c->cslot_mem);
     c->cslot_mem = nullptr;
@@ -607,11 +609,19 @@ static void stats_from_dev(const DevStats& hs, percis_stats* st) {
     st->first_overflow = hs.first_overflow;
 }
 
-// Runs `tasks` in one persistent launch on the context's stream and waits for
-// it. `out` (optional) receives each task's sample statistics; `launch`
-// (optional) their sums with the launch-wide work counters, phase times and
-// kernel time.
-int run_tasks(percis_ctx* c, const std::vector<TaskSpec>& tasks, std::vector<percis_stats>* out, percis_stats* launch) {
+// What a launch over a task list needs before its kernels are enqueued:
+// graphs and slots on the device, the task table uploaded to `table` (stats
+// to `tstats`) from `ht`, which must outlive the copy (the caller's stream
+// synchronisation), list buffers of one chunk.
+struct LaunchPlan {
+    int nt = 0;
+    int64_t max_n = 1;
+    uint64_t total = 0, chunk = 1;
+    size_t nchunks = 0;
+};
+
+static int plan_tasks(percis_ctx* c, const std::vector<TaskSpec>& tasks, DevTask* table, DevStats* tstats,
+                      std::vector<DevTask>& ht, LaunchPlan* lp) {
     int rc = set_device(c);
     if (rc) return rc;
     const int nt = (int)tasks.size();
@@ -625,13 +635,7 @@ int run_tasks(percis_ctx* c, const std::vector<TaskSpec>& tasks, std::vector<per
         total += t.count;
     }
     if ((rc = ensure_slots(c, max_act))) return rc;
-    if (nt > c->task_cap) {
-        if (c->stream) HIPCHK(c, hipStreamSynchronize(c->stream));
-        if ((rc = dalloc(c, c->d_tasks, (size_t)nt))) return rc;
-        if ((rc = dalloc(c, c->d_task_stats, (size_t)nt))) return rc;
-        c->task_cap = nt;
-    }
-    std::vector<DevTask> ht(nt);
+    ht.assign(nt, DevTask{});
     uint64_t off = 0;
     for (int i = 0; i < nt; i++) {
         const TaskSpec& t = tasks[i];
@@ -645,14 +649,12 @@ int run_tasks(percis_ctx* c, const std::vector<TaskSpec>& tasks, std::vector<per
         d.seed = t.seed;
         d.phase = t.phase;
         d.hits = t.d_hits;
-        d.stats = c->d_task_stats + i;
+        d.stats = tstats + i;
         d.offset = off;
         d.clear_hits = t.accumulate ? 0u : 1u;
         off += t.count;
     }
-    HIPCHK(c, hipMemcpyAsync(c->d_tasks, ht.data(), sizeof(DevTask) * nt, hipMemcpyHostToDevice, c->stream));
-    HIPCHK(c, launch_clear_tasks(c->d_tasks, nt, max_n, c->stream));
-    HIPCHK(c, launch_init_stats(c->d_stats, c->d_work, c->stream));
+    HIPCHK(c, hipMemcpyAsync(table, ht.data(), sizeof(DevTask) * nt, hipMemcpyHostToDevice, c->stream));
     // The launch runs in chunks of at most kPairChunk samples: the pair kernel
     // draws a chunk's pairs and lists those that need a search, then the
     // sampler works through the list.
@@ -663,61 +665,78 @@ int run_tasks(percis_ctx* c, const std::vector<TaskSpec>& tasks, std::vector<per
         if ((rc = dalloc(c, c->d_wide, (size_t)chunk))) return rc;
         if ((rc = dalloc(c, c->d_big, (size_t)chunk))) return rc;
         c->pair_cap = chunk;
+        c->generation++;
     }
-    const size_t nchunks = (size_t)((total + chunk - 1) / chunk);
-    while (c->chunk_ev.size() < 3 * nchunks) {
-        hipEvent_t e;
-        HIPCHK(c, hipEventCreate(&e));
-        c->chunk_ev.push_back(e);
+    lp->nt = nt;
+    lp->max_n = max_n;
+    lp->total = total;
+    lp->chunk = chunk;
+    lp->nchunks = (size_t)((total + chunk - 1) / chunk);
+    return PERCIS_OK;
+}
+
+// Enqueues the launch's kernels on `stream`: task clearing, then per chunk
+// the pair kernel, the sampler (compact slots first when they are on), the
+// 128-bit path. Kernels only, so that the sequence can be captured; with
+// `timed`, per-chunk events bracket the pair kernel and the rest.
+static int enqueue_tasks(percis_ctx* c, const LaunchPlan& lp, const DevTask* table, hipStream_t stream, bool timed) {
+    if (timed) {
+        while (c->chunk_ev.size() < 3 * lp.nchunks) {
+            hipEvent_t e;
+            HIPCHK(c, hipEventCreate(&e));
+            c->chunk_ev.push_back(e);
+        }
     }
+    HIPCHK(c, launch_clear_tasks(table, lp.nt, lp.max_n, stream));
+    HIPCHK(c, launch_init_stats(c->d_stats, c->d_work, stream));
     SampleLaunch a{};
-    a.tasks = c->d_tasks;
-    a.ntasks = nt;
+    a.tasks = table;
+    a.ntasks = lp.nt;
     a.pairs = c->d_pairs;
     a.work = c->d_work;
     a.npairs = c->d_work + 1;
     a.stats = c->d_stats;
-    a.slots = (int)std::min<uint64_t>((uint64_t)c->nslots, chunk);
+    a.slots = (int)std::min<uint64_t>((uint64_t)c->nslots, lp.chunk);
     a.wide = c->d_wide;
     a.nwide = c->d_work + 2;
     a.big = c->d_big;
     a.nbig = c->d_work + 4;
     a.big_work = c->d_work + 5;
-    for (size_t i = 0; i < nchunks; i++) {
-        a.base = (uint64_t)i * chunk;
-        a.count = std::min<uint64_t>(chunk, total - a.base);
-        HIPCHK(c, hipEventRecord(c->chunk_ev[3 * i], c->stream));
-        HIPCHK(c, launch_pairs(a, c->stream));
-        HIPCHK(c, hipEventRecord(c->chunk_ev[3 * i + 1], c->stream));
+    for (size_t i = 0; i < lp.nchunks; i++) {
+        a.base = (uint64_t)i * lp.chunk;
+        a.count = std::min<uint64_t>(lp.chunk, lp.total - a.base);
+        if (timed) HIPCHK(c, hipEventRecord(c->chunk_ev[3 * i], stream));
+        HIPCHK(c, launch_pairs(a, stream));
+        if (timed) HIPCHK(c, hipEventRecord(c->chunk_ev[3 * i + 1], stream));
         if (c->ncslots > 0) {
             // compact slots first; the samples they hand on go to the per-node slots
             SampleLaunch ca = a;
-            ca.slots = (int)std::min<uint64_t>((uint64_t)c->ncslots, chunk);
-            HIPCHK(c, launch_sampler(c->cslots, ca, c->cshape, c->stream));
+            ca.slots = (int)std::min<uint64_t>((uint64_t)c->ncslots, lp.chunk);
+            HIPCHK(c, launch_sampler(c->cslots, ca, c->cshape, stream));
             SampleLaunch da = a;
             da.pairs = c->d_big;
             da.npairs = a.nbig;
             da.work = a.big_work;
-            HIPCHK(c, launch_sampler(c->slots, da, c->shape, c->stream));
+            HIPCHK(c, launch_sampler(c->slots, da, c->shape, stream));
         } else {
-            HIPCHK(c, launch_sampler(c->slots, a, c->shape, c->stream));
+            HIPCHK(c, launch_sampler(c->slots, a, c->shape, stream));
         }
-        HIPCHK(c, launch_wide(a, c->wslots, c->wide_slots, c->stream));
-        HIPCHK(c, hipEventRecord(c->chunk_ev[3 * i + 2], c->stream));
+        HIPCHK(c, launch_wide(a, c->wslots, c->wide_slots, stream));
+        if (timed) HIPCHK(c, hipEventRecord(c->chunk_ev[3 * i + 2], stream));
     }
+    return PERCIS_OK;
+}
+
+// Reads a finished launch's statistics (`tstats`, per task, and the
+// launch-wide counters) and checks that every task ran all its samples.
+static int collect_tasks(percis_ctx* c, const std::vector<TaskSpec>& tasks, const DevStats* tstats, double ms,
+                         double pair_ms, std::vector<percis_stats>* out, percis_stats* launch) {
+    const int nt = (int)tasks.size();
     std::vector<DevStats> hts(nt);
     DevStats hl{};
-    HIPCHK(c, hipMemcpyAsync(hts.data(), c->d_task_stats, sizeof(DevStats) * nt, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(hts.data(), tstats, sizeof(DevStats) * nt, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipMemcpyAsync(&hl, c->d_stats, sizeof hl, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    double ms = 0.0, pair_ms = 0.0;
-    for (size_t i = 0; i < nchunks; i++) {
-        float a_ms = 0.f, b_ms = 0.f;
-        HIPCHK(c, hipEventElapsedTime(&a_ms, c->chunk_ev[3 * i], c->chunk_ev[3 * i + 1]));
-        HIPCHK(c, hipEventElapsedTime(&b_ms, c->chunk_ev[3 * i + 1], c->chunk_ev[3 * i + 2]));
-        pair_ms += a_ms;
-        ms += b_ms;
-    }
     percis_stats agg{};
     agg.first_overflow = ~0ull;
     if (out) out->resize(nt);
@@ -751,6 +770,36 @@ int run_tasks(percis_ctx* c, const std::vector<TaskSpec>& tasks, std::vector<per
         return fail(c, PERCIS_E_SIGMA_OVERFLOW, "%llu sample(s) with sigma_st >= 2^64, first index %llu",
                     (unsigned long long)agg.overflow, (unsigned long long)agg.first_overflow);
     return PERCIS_OK;
+}
+
+// Runs `tasks` in one persistent launch on the context's stream and waits for
+// it. `out` (optional) receives each task's sample statistics; `launch`
+// (optional) their sums with the launch-wide work counters, phase times and
+// kernel time.
+int run_tasks(percis_ctx* c, const std::vector<TaskSpec>& tasks, std::vector<percis_stats>* out, percis_stats* launch) {
+    const int nt = (int)tasks.size();
+    int rc = set_device(c);
+    if (rc) return rc;
+    if (nt > c->task_cap) {
+        if (c->stream) HIPCHK(c, hipStreamSynchronize(c->stream));
+        if ((rc = dalloc(c, c->d_tasks, (size_t)nt))) return rc;
+        if ((rc = dalloc(c, c->d_task_stats, (size_t)nt))) return rc;
+        c->task_cap = nt;
+    }
+    LaunchPlan lp;
+    std::vector<DevTask> ht;
+    if ((rc = plan_tasks(c, tasks, c->d_tasks, c->d_task_stats, ht, &lp))) return rc;
+    if ((rc = enqueue_tasks(c, lp, c->d_tasks, c->stream, true))) return rc;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    double ms = 0.0, pair_ms = 0.0;
+    for (size_t i = 0; i < lp.nchunks; i++) {
+        float a_ms = 0.f, b_ms = 0.f;
+        HIPCHK(c, hipEventElapsedTime(&a_ms, c->chunk_ev[3 * i], c->chunk_ev[3 * i + 1]));
+        HIPCHK(c, hipEventElapsedTime(&b_ms, c->chunk_ev[3 * i + 1], c->chunk_ev[3 * i + 2]));
+        pair_ms += a_ms;
+        ms += b_ms;
+    }
+    return collect_tasks(c, tasks, c->d_task_stats, ms, pair_ms, out, launch);
 }
 
 GraphData* get_graph(percis_ctx* c, int32_t id) {
@@ -910,6 +959,8 @@ void percis_destroy(percis_ctx* c) {
     }
     c->graphs.clear();
     free_slots(c);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+    c->cap_stream = nullptr;
     dfree(c->d_stats);
     dfree(c->d_work);
     dfree(c->d_pairs);
@@ -946,6 +997,7 @@ int percis_load_csr(percis_ctx* c, int32_t n, int64_t m, const int32_t* row_ptr,
         return rc;
     }
     tmp->D_override = c->graphs[0]->D_override;
+    c->generation++;
     graph_clear(*c->graphs[0]);
     delete c->graphs[0];
     c->graphs[0] = tmp;
@@ -1035,6 +1087,119 @@ int percis_sample_tasks(percis_ctx* c, int32_t ntasks, const percis_task* tasks,
     for (int32_t i = 0; i < ntasks; i++)
         if (tasks[i].stats) *tasks[i].stats = ts[i];
     return rc;
+}
+
+}  // extern "C"
+
+struct percis_batch {
+    percis_ctx* ctx = nullptr;
+    std::vector<TaskSpec> tasks;
+    std::vector<percis_stats*> task_stats;   // host, from the capture's task list (may be null)
+    DevTask* d_tasks = nullptr;
+    DevStats* d_task_stats = nullptr;
+    hipGraphExec_t exec = nullptr;
+    uint64_t generation = 0;
+};
+
+static void batch_free(percis_batch* b) {
+    if (!b) return;
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    dfree(b->d_tasks);
+    dfree(b->d_task_stats);
+    delete b;
+}
+
+extern "C" {
+
+int percis_batch_capture(percis_ctx* c, int32_t ntasks, const percis_task* tasks, percis_batch** out) {
+    if (!c || !out) return PERCIS_E_INVAL;
+    *out = nullptr;
+    if (ntasks < 1 || !tasks) return fail(c, PERCIS_E_INVAL, "need at least one task");
+    int rc = set_device(c);
+    if (rc) return rc;
+    percis_batch* b = new (std::nothrow) percis_batch();
+    if (!b) return fail(c, PERCIS_E_NOMEM, "out of host memory");
+    b->ctx = c;
+    for (int32_t i = 0; i < ntasks; i++) {
+        const percis_task& t = tasks[i];
+        GraphData* G = get_graph(c, t.graph);
+        rc = !G ? fail(c, PERCIS_E_INVAL, "task %d: no graph %d", i, t.graph)
+           : (!G->has_graph || !G->has_states) ? fail(c, PERCIS_E_STATE, "task %d: graph %d has no states", i, t.graph)
+           : !t.hits ? fail(c, PERCIS_E_INVAL, "task %d: null hits", i)
+           : t.count >= (1ull << 32) ? fail(c, PERCIS_E_TOO_LARGE, "task %d: at most 2^32 - 1 samples", i)
+                                     : PERCIS_OK;
+        if (rc) {
+            batch_free(b);
+            return rc;
+        }
+        b->tasks.push_back(TaskSpec{t.graph, t.phase, t.first, t.count, t.seed, t.hits, (t.flags & PERCIS_ACCUMULATE) != 0});
+        b->task_stats.push_back(t.stats);
+    }
+    if (!c->cap_stream && hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+        c->cap_stream = nullptr;
+        batch_free(b);
+        return fail(c, PERCIS_E_DEVICE, "cannot create the capture stream");
+    }
+    LaunchPlan lp;
+    std::vector<DevTask> ht;
+    if ((rc = dalloc(c, b->d_tasks, (size_t)ntasks)) || (rc = dalloc(c, b->d_task_stats, (size_t)ntasks)) ||
+        (rc = plan_tasks(c, b->tasks, b->d_tasks, b->d_task_stats, ht, &lp))) {
+        batch_free(b);
+        return rc;
+    }
+    if (hipStreamSynchronize(c->stream) != hipSuccess ||
+        hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeRelaxed) != hipSuccess) {
+        batch_free(b);
+        return fail(c, PERCIS_E_DEVICE, "cannot begin a stream capture");
+    }
+    rc = enqueue_tasks(c, lp, b->d_tasks, c->cap_stream, false);
+    hipGraph_t graph = nullptr;
+    const hipError_t e = hipStreamEndCapture(c->cap_stream, &graph);
+    if (rc == PERCIS_OK && e != hipSuccess) rc = fail(c, PERCIS_E_DEVICE, "stream capture: %s", hipGetErrorString(e));
+    if (rc == PERCIS_OK && hipGraphInstantiate(&b->exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+        b->exec = nullptr;
+        rc = fail(c, PERCIS_E_DEVICE, "cannot instantiate the captured launch");
+    }
+    if (graph) (void)hipGraphDestroy(graph);
+    (void)hipGetLastError();
+    if (rc) {
+        batch_free(b);
+        return rc;
+    }
+    b->generation = c->generation;
+    *out = b;
+    return PERCIS_OK;
+}
+
+int percis_batch_replay(percis_batch* b, percis_stats* launch_stats) {
+    if (!b || !b->ctx) return PERCIS_E_INVAL;
+    percis_ctx* c = b->ctx;
+    if (b->generation != c->generation)
+        return fail(c, PERCIS_E_STATE, "graphs, states, options or buffers changed since the capture; capture again");
+    int rc = set_device(c);
+    if (rc) return rc;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, hipEventRecord(c->ev0, c->cap_stream));
+    HIPCHK(c, hipGraphLaunch(b->exec, c->cap_stream));
+    HIPCHK(c, hipEventRecord(c->ev1, c->cap_stream));
+    HIPCHK(c, hipStreamSynchronize(c->cap_stream));
+    float ms = 0.f;
+    HIPCHK(c, hipEventElapsedTime(&ms, c->ev0, c->ev1));
+    std::vector<percis_stats> ts;
+    rc = collect_tasks(c, b->tasks, b->d_task_stats, ms, 0.0, &ts, launch_stats);
+    if (rc != PERCIS_OK && rc != PERCIS_E_SIGMA_OVERFLOW) return rc;
+    for (size_t i = 0; i < b->task_stats.size() && i < ts.size(); i++)
+        if (b->task_stats[i]) *b->task_stats[i] = ts[i];
+    return rc;
+}
+
+void percis_batch_destroy(percis_batch* b) {
+    if (!b) return;
+    if (b->ctx && !b->ctx->host_only) {
+        (void)hipSetDevice(b->ctx->device);
+        if (b->ctx->cap_stream) (void)hipStreamSynchronize(b->ctx->cap_stream);
+    }
+    batch_free(b);
 }
 
 int percis_set_vertex_diameter(percis_ctx* c, int64_t D) {

@@ -95,6 +95,8 @@ struct percis_ctx {
     percis::DebugOut* d_dbg = nullptr;
     int32_t dbg_cap = 0;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    hipStream_t cap_stream = nullptr;      // private stream for capturing and replaying batches
+    uint64_t generation = 0;               // bumped whenever a captured launch's buffers or inputs change
 
     int64_t opt_slots = 0, opt_scratch_mb = 0, opt_block = 0, opt_bitmaps = 0, opt_compact = 0, opt_defer_block = 0;
 };

@@ -93,6 +93,9 @@ _SIGS = {
     "percis_graph_info": (C.c_int, [_P, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int64),
                                     C.POINTER(C.c_int32)]),
     "percis_sample_tasks": (C.c_int, [_P, C.c_int32, C.POINTER(Task), C.POINTER(Stats)]),
+    "percis_batch_capture": (C.c_int, [_P, C.c_int32, C.POINTER(Task), C.POINTER(_P)]),
+    "percis_batch_replay": (C.c_int, [_P, C.POINTER(Stats)]),
+    "percis_batch_destroy": (None, [_P]),
     "percis_graph_estimate": (C.c_int, [_P, C.c_int32, C.c_double, C.c_double, C.c_uint64, _P,
                                         C.POINTER(EstimateInfo)]),
     "percis_graph_estimate_di": (C.c_int, [_P, C.c_int32, C.c_double, C.c_double, C.c_uint64, _P,
@@ -306,6 +309,21 @@ class Context:
         self._check(rc, allow=(E_SIGMA_OVERFLOW,) if allow_overflow else ())
         return [s.to_dict() for s in sts], ls.to_dict()
 
+    def capture_batch(self, tasks):
+        """The launch of sample_tasks(tasks) captured as a HIP graph; returns a
+        Batch whose replay() re-runs it."""
+        arr = (Task * len(tasks))()
+        sts = [Stats() for _ in tasks]
+        for i, t in enumerate(tasks):
+            h = t["hits"]
+            assert isinstance(h, torch.Tensor) and h.is_cuda and h.dtype == torch.int32
+            arr[i] = Task(int(t["graph"]), int(t.get("phase", 0)), int(t.get("first", 0)), int(t["count"]),
+                          int(t["seed"]), C.c_void_p(h.data_ptr()), ACCUMULATE if t.get("accumulate") else 0,
+                          C.pointer(sts[i]))
+        b = _P()
+        self._check(_lib.percis_batch_capture(self._h, len(tasks), arr, C.byref(b)))
+        return Batch(self, b, sts, [t["hits"] for t in tasks])
+
     def graph_estimate(self, graph, eps, delta, seed):
         n = self.graph_info(graph)[0]
         p = np.zeros(n, np.float64)
@@ -346,6 +364,29 @@ class Context:
         v = C.c_int64()
         self._check(_lib.percis_get_option(self._h, int(opt), C.byref(v)))
         return int(v.value)
+
+
+class Batch:
+    """A captured task launch (percis_batch_*)."""
+
+    def __init__(self, ctx, handle, stats, hits):
+        self._ctx, self._h, self._stats, self._hits = ctx, handle, stats, hits
+
+    def replay(self, allow_overflow=False):
+        """Returns (per-task stats, launch stats), as Context.sample_tasks."""
+        ls = Stats()
+        rc = _lib.percis_batch_replay(self._h, C.byref(ls))
+        self._ctx._check(rc, allow=(E_SIGMA_OVERFLOW,) if allow_overflow else ())
+        return [s.to_dict() for s in self._stats], ls.to_dict()
+
+    def close(self):
+        if self._h:
+            _lib.percis_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            self.close()
 
 
 class Server:
