@@ -65,7 +65,12 @@ typedef struct percis_ctx percis_ctx;
  * pair and 0 for an unreachable one. The four work counters count, over all
  * samples of the call: adjacency entries examined (edges), shortest-path
  * count accumulations (sigma_adds), vertices whose adjacency was scanned
- * (vertices_expanded) and vertices first reached (vertices_discovered). */
+ * (vertices_expanded) and vertices first reached (vertices_discovered).
+ * Results (hits, samples, reachable, sum_I, sum_I2, overflow) never depend
+ * on timing; the work counters may vary slightly between runs, because
+ * arcs of a search's last level that do not reach the other ball are skipped
+ * as soon as any thread has seen one that does, and because a sample near a
+ * compact slot's table limit may or may not be handed on and redone. */
 typedef struct {
     uint64_t samples;
     uint64_t reachable;

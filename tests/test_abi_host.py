@@ -147,3 +147,19 @@ def test_option_validation(P):
         assert c.get_option(P.OPT_DEFER_BLOCK) == b
     with pytest.raises(P.PercisError):
         c.set_option(P.OPT_DEFER_BLOCK, 96)
+
+
+def test_batch_capture_needs_a_device(P):
+    c = ctx(P)
+    g, k = W.workload_er1000()
+    c.load_csr(g.n, g.row_ptr, g.col)
+    c.set_states(k)
+    lib = P.raw_library()
+    h = C.c_void_p()
+    rc = lib.percis_batch_capture(c._h, 0, None, C.byref(h))
+    assert rc == P.E_INVAL and not h.value
+    arr = (P.Task * 1)()
+    arr[0] = P.Task(0, 0, 0, 10, 1, C.c_void_p(0x1000), 0, None)   # never dereferenced: no device
+    rc = lib.percis_batch_capture(c._h, 1, arr, C.byref(h))
+    assert rc == P.E_STATE and not h.value
+    lib.percis_batch_destroy(None)   # a null batch is accepted

@@ -61,8 +61,10 @@ def test_captured_batch_replays_match_eager(compact):
         for i in range(5):
             for key in ("samples", "reachable", "sum_I", "sum_I2", "overflow"):
                 assert per[i][key] == eager_stats[i][key], (rep, i, key)
-        for key in ("samples", "edges", "sigma_adds"):
-            assert launch[key] == eager_launch[key], (rep, key)
+        # work counters (edges, sigma_adds) may differ between runs: which
+        # arcs of a last level are skipped, and (compact slots) which samples
+        # near a table's limit are handed on and redone, depend on timing
+        assert launch["samples"] == eager_launch["samples"], rep
         # eager work on the same context between replays
         c.sample_range(0, 1500, 11 + rep, 0, hits=side)
         torch.cuda.synchronize()
