@@ -133,3 +133,45 @@ def test_compact_hands_large_balls_to_per_node_slots():
     same_stats(so, sg)
     assert sg["deferred"] > 0
     c.close()
+
+
+def test_compact_estimates_equal_per_node_estimates():
+    """Algorithm 1 and PercIS-DI end to end (bounds, both phases, the
+    estimate) give bit-identical results on compact and per-node slots."""
+    from paper_2509_11454_amd import percis as P
+    g, k = W.workload_er1000()
+    h = W.ba_graph(3000, 4, 5)
+    kh = W.skewed_states(h.n, np.random.default_rng(4))
+    res = []
+    for mode in (1, 2):
+        c = P.Context(0)
+        c.set_option(P.OPT_COMPACT, mode)
+        c.load_csr(g.n, g.row_ptr, g.col)
+        c.set_states(k)
+        gid = c.add_graph(h.n, h.row_ptr, h.col, kh)
+        assert c.get_option(P.OPT_COMPACT) == mode
+        res.append([c.estimate(0.02, 0.1, 3), c.graph_estimate(gid, 0.03, 0.1, 4),
+                    c.graph_estimate_di(0, 0.05, 0.1, 5)])
+        c.close()
+    for (p1, i1), (p2, i2) in zip(res[0], res[1]):
+        assert np.array_equal(p1, p2)
+        for key in ("l1", "l", "D", "d_hat", "rho_hat", "v_hat", "x_hat", "overflow"):
+            assert i1[key] == i2[key], key
+
+
+def test_compact_serving_matches_per_node_estimates():
+    """The continuous-batching server on compact slots returns, per query,
+    the estimate that per-node slots give."""
+    from paper_2509_11454_amd import percis as P
+    import test_gpu_serving as S
+    c, ids = S.serving_context()
+    ref = [c.graph_estimate(ids[gi], e, d, s) for gi, e, d, s in S.QUERIES[:5]]
+    c.close()
+    c, ids = S.serving_context()
+    c.set_option(P.OPT_COMPACT, 2)
+    queries = [(ids[gi], e, d, s) for gi, e, d, s in S.QUERIES[:5]]
+    out, _, _ = S.run_server(c, queries, budget=1 << 30)
+    assert c.get_option(P.OPT_COMPACT) == 2
+    for (rc, p, info), (p_ref, info_ref) in zip(out, ref):
+        assert rc == 0 and info["l"] == info_ref["l"]
+        assert np.array_equal(p, p_ref)
