@@ -104,6 +104,7 @@ def main():
                     help="visited sets: 0 auto, 1 device bitmaps, 2 LDS hash tables")
     ap.add_argument("--compact", type=int, default=0,
                     help="compact slots: 0 auto, 1 off, 2 on (samples outgrowing them go to per-node slots)")
+    ap.add_argument("--scratch-mb", type=int, default=0, help="cap on the sampler scratch (0 = the library's default)")
     ap.add_argument("--defer-block", type=int, default=0,
                     help="threads per sample of the per-node slots while compact slots are on (0 auto)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -155,6 +156,8 @@ def main():
     c.set_option(P.OPT_BLOCK, args.block)
     c.set_option(P.OPT_BITMAPS, args.bitmaps)
     c.set_option(P.OPT_COMPACT, args.compact)
+    if args.scratch_mb:
+        c.set_option(P.OPT_SCRATCH_MB, args.scratch_mb)
     c.set_option(P.OPT_DEFER_BLOCK, args.defer_block)
     c.load_csr(g.n, g.row_ptr, g.col, directed=g.directed)
     c.set_states(k)

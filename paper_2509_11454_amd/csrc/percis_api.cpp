@@ -315,6 +315,11 @@ constexpr uint64_t kPairChunk = 1ull << 22;  // samples per pair-kernel chunk (1
 constexpr int64_t kWideSlots = 16;           // workgroups of the 128-bit path
 constexpr int64_t kWideBytesPerNode = 4 + 16 + 4;
 constexpr int kDeferBlock = 512;             // per-node slots' block while compact slots are on
+// Share of free device memory the per-node slots may take by default. Only
+// graphs too large for slots to fill the device reach it; there the per-node
+// slots run the samples compact slots hand on (R-MAT 24 directed: 7.75M
+// samples/s at 60 %, 8.38M at 78 %).
+constexpr double kScratchFraction = 0.8;
 
 static int64_t bitmap_words(int64_t act) { return ((std::max<int64_t>(act, 1) + 31) / 32 + 63) / 64 * 64; }
 
@@ -374,7 +379,8 @@ static int ensure_slots(percis_ctx* c, int64_t act) {
                              + kArcsPerSlot * (int64_t)sizeof(DagArc);
     size_t free_b = 0, total_b = 0;
     HIPCHK(c, hipMemGetInfo(&free_b, &total_b));
-    const int64_t budget = c->opt_scratch_mb > 0 ? c->opt_scratch_mb * (1ll << 20) : (int64_t)(free_b * 0.6);
+    const int64_t budget =
+        c->opt_scratch_mb > 0 ? c->opt_scratch_mb * (1ll << 20) : (int64_t)((double)free_b * kScratchFraction);
     const int64_t want = c->opt_slots > 0 ? c->opt_slots : (int64_t)std::max(c->cu_count, 1) * occ;
     int64_t ns = std::max<int64_t>(1, std::min(want, budget / per_slot));
     void* mem = nullptr;
