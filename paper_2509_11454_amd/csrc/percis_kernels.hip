@@ -45,12 +45,17 @@ constexpr int chunk_len() { return BSZ < CH ? BSZ : CH; }
 constexpr uint32_t LVMASK = 0x0FFFFFFFu;
 constexpr uint32_t OVFBIT = 0x40000000u;
 #ifndef PERCIS_UNROLL
-#define PERCIS_UNROLL 8
+#define PERCIS_UNROLL 6
 #endif
 constexpr int UNROLL = PERCIS_UNROLL;  // adjacency entries per thread per batch
+#ifndef PERCIS_SCAN_UNROLL
+#define PERCIS_SCAN_UNROLL 4
+#endif
+constexpr int SCAN_UNROLL = PERCIS_SCAN_UNROLL;  // entries per thread per step of a long chunk's first pass
 constexpr int WALK_UNROLL = 4;  // in-row chunks of 64 loaded together by the walk's row scan
 constexpr int ARC_UNROLL = 4;   // DAG-arc chunks of 64 loaded together by the walk
 constexpr int KCAP = 64;        // predecessors a walk step gathers from the arc list
+constexpr int MLCAP = 128;      // arcs into the other ball that a chunk's first pass lists
 
 // Slot scratch is private to one workgroup (one CU), so every access to it is
 // a workgroup-scope atomic: coherent among the workgroup's waves without the
@@ -376,6 +381,9 @@ struct SampleShared {
     int32_t tail, tail_s, tail_t;
     int32_t nmeet;
     int32_t level_meets;  // the level being built has an arc into the other ball
+    int32_t mcnt;         // arcs into the other ball found by a chunk's first pass
+    int32_t ml_w[MLCAP];  // those arcs: head node, and staged tail | (head's position in the other table + 1) << 8
+    int32_t ml_m[MLCAP];
     int32_t narcs;        // DAG arcs recorded by this sample (may exceed the slot's capacity)
     int32_t wk_u[KCAP];   // predecessors of the walk's current node, and their sigma_s
     uint64_t wk_w[KCAP];
@@ -539,6 +547,45 @@ __device__ __forceinline__ void wave_sum_wrap(uint64_t& v, uint32_t& wrap) {
     }
 }
 
+// The adjacency entries b0 + tid + k * BSZ (k < UNROLL) of a staged chunk
+// with `total` entries over `cnt` nodes: the staged tail jj[k] (-1 past the
+// end) and the head w[k].
+template <int BSZ, int U>
+__device__ __forceinline__ void fetch_batch(const G<int32_t>* col, const SampleShared& sh, int b0, int total, int cnt,
+                                            int32_t (&w)[U], int (&jj)[U]) {
+#pragma unroll
+    for (int k = 0; k < U; k++) {
+        const int e = b0 + threadIdx.x + k * BSZ;
+        jj[k] = -1;
+        w[k] = 0;
+        if (e < total) {
+            jj[k] = chunk_owner(sh, cnt, e);
+            w[k] = col[sh.beg[jj[k]] + (e - sh.off[jj[k]])];
+        }
+    }
+}
+
+// Member tests of a batch against the other side's ball (side OTHER); bit k
+// of the result is set when w[k] is in it, at position po[k] of its table
+// (compact slots).
+template <int OTHER, bool LDS, bool CMP, int U>
+__device__ __forceinline__ uint32_t probe_batch(const Vis<LDS>& V, const SampleShared& sh, const int32_t (&w)[U],
+                                                const int (&jj)[U], int (&po)[U]) {
+    uint32_t into = 0;
+#pragma unroll
+    for (int k = 0; k < U; k++) {
+        po[k] = -1;
+        if (jj[k] < 0) continue;
+        if constexpr (CMP) {
+            po[k] = table_find<HBITS_C>(tab<HBITS_C>(OTHER), w[k]);
+            if (po[k] >= 0) into |= 1u << k;
+        } else if (member<LDS>(V, sh, OTHER, w[k])) {
+            into |= 1u << k;
+        }
+    }
+    return into;
+}
+
 // One BFS level over the frontier q[lo, hi) of one side (SIDE 0: s, out-arcs;
 // SIDE 1: t, in-arcs), edge-balanced: the rows of a chunk of frontier nodes are
 // concatenated and the workgroup strides over the concatenation, UNROLL
@@ -550,12 +597,20 @@ __device__ __forceinline__ void wave_sum_wrap(uint64_t& v, uint32_t& wrap) {
 // carry their own nonzero level, written before the last barrier. New nodes
 // that the other side has reached form the meeting layer, written to the
 // head of q_d.
+// A level with an arc into the other ball is the last one, and of its new
+// nodes only the meeting layer is used again, so such a level processes only
+// the arcs into the other ball. A chunk of one batch decides this after its
+// member tests (one barrier). A longer chunk first scans all its entries for
+// such arcs without barriers and lists them in LDS; its second pass then takes
+// the list (the last level), or every entry again from the rows just read (a
+// level that does not meet), or, past the list's capacity, the entries again,
+// keeping those into the other ball.
 // Every count of the new level is at most the sum of the frontier's counts
 // (no parallel arcs), so the adds are checked for wrapping (`careful`) only
 // when that sum reached 2^64. The level's own sum and degree sum (the
 // degrees its expansion will scan) are gathered on the way.
 template <int SIDE, int BSZ, bool LDS, bool CMP>
-__device__ void expand_bfs(const GGraph& g, const GSlots& sl, int64_t so, const Vis<LDS>& V, const Recs<CMP>& rc,
+__device__ __forceinline__ void expand_bfs(const GGraph& g, const GSlots& sl, int64_t so, const Vis<LDS>& V, const Recs<CMP>& rc,
                            int lo, int hi, uint32_t nl, bool careful, SampleShared& sh, Counters& cn) {
     using B = Bits;
     const int tid = threadIdx.x;
@@ -569,50 +624,84 @@ __device__ void expand_bfs(const GGraph& g, const GSlots& sl, int64_t so, const 
     uint32_t wrap = 0;
 
     constexpr int CHK = chunk_len<BSZ>();
+    constexpr int BATCH = BSZ * UNROLL;
     for (int base = lo; base < hi; base += CHK) {
         const int cnt = min(CHK, hi - base);
+        if (tid == 0) sh.mcnt = 0;  // ordered before the first pass by stage_chunk's barriers
         const int total = stage_chunk<BSZ, SIDE, CMP>(q, base, cnt, rp, rc, careful, sh, cn);
-        for (int b0 = 0; b0 < total; b0 += BSZ * UNROLL) {
+        const bool single = total <= BATCH;
+        bool meets = false, listed = false;
+        int n2 = total;  // entries, or listed arcs, of the processing pass
+        if (!single) {
+            // first pass: list the arcs into the other ball
+            for (int b0 = 0; b0 < total; b0 += BSZ * SCAN_UNROLL) {
+                int32_t w[SCAN_UNROLL];
+                int jj[SCAN_UNROLL], po[SCAN_UNROLL];
+                fetch_batch<BSZ>(col, sh, b0, total, cnt, w, jj);
+                const uint32_t in = probe_batch<1 - SIDE, LDS, CMP>(V, sh, w, jj, po);
+#pragma unroll
+                for (int k = 0; k < SCAN_UNROLL; k++) {
+                    if (jj[k] < 0) continue;
+                    cn.E++;
+                    if ((in >> k) & 1u) {
+                        const int i = atomicAdd(&sh.mcnt, 1);
+                        if (i < MLCAP) {
+                            sh.ml_w[i] = w[k];
+                            sh.ml_m[i] = jj[k] | ((po[k] + 1) << 8);
+                        }
+                    }
+                }
+            }
+            __syncthreads();
+            // mcnt is final here; level_meets changes only from 0 to 1, and
+            // only when mcnt > 0, so every thread makes the same choice
+            const int mc = sh.mcnt;
+            meets = mc > 0 || sh.level_meets != 0;
+            listed = meets && mc <= MLCAP;
+            if (listed) n2 = mc;
+            if (mc > 0 && tid == 0) sh.level_meets = 1;
+        }
+        for (int b0 = 0; b0 < n2; b0 += BATCH) {
             int32_t w[UNROLL];
             int jj[UNROLL];
-            uint32_t into_other = 0;  // bit k: arc k ends in the other side's ball
-#pragma unroll
-            for (int k = 0; k < UNROLL; k++) {
-                const int e = b0 + tid + k * BSZ;
-                jj[k] = -1;
-                w[k] = 0;
-                if (e < total) {
-                    jj[k] = chunk_owner(sh, cnt, e);
-                    w[k] = col[sh.beg[jj[k]] + (e - sh.off[jj[k]])];
-                }
-            }
             int po[UNROLL];  // compact slots: the arc's head in the other side's table
+            uint32_t into_other = 0;  // bit k: arc k ends in the other side's ball
+            if (listed) {
 #pragma unroll
-            for (int k = 0; k < UNROLL; k++) {
-                po[k] = -1;
-                if (jj[k] < 0) continue;
-                if constexpr (CMP) {
-                    po[k] = table_find<HBITS_C>(tab<HBITS_C>(1 - SIDE), w[k]);
-                    if (po[k] >= 0) into_other |= 1u << k;
-                } else if (member<LDS>(V, sh, 1 - SIDE, w[k])) {
-                    into_other |= 1u << k;
+                for (int k = 0; k < UNROLL; k++) {
+                    const int i = b0 + tid + k * BSZ;
+                    jj[k] = -1;
+                    w[k] = 0;
+                    po[k] = -1;
+                    if (i < n2) {
+                        const int m = sh.ml_m[i];
+                        jj[k] = m & 255;
+                        po[k] = (m >> 8) - 1;
+                        w[k] = sh.ml_w[i];
+                        into_other |= 1u << k;
+                    }
+                }
+            } else {
+                fetch_batch<BSZ>(col, sh, b0, total, cnt, w, jj);
+                if (single || meets) {
+                    into_other = probe_batch<1 - SIDE, LDS, CMP>(V, sh, w, jj, po);
+                } else {
+#pragma unroll
+                    for (int k = 0; k < UNROLL; k++) po[k] = -1;
                 }
             }
-            // A level with an arc into the other ball is the last one, and of
-            // its new nodes only the meeting layer is used again: once any
-            // thread has seen such an arc, arcs to other nodes are skipped.
-            // The flag only ever goes up within a level, so a thread may see
-            // it raised by the next batch while its neighbours did not; either
-            // way every arc into the meeting layer is processed, and the rest
-            // only touch nodes that nothing reads (they are still queued, so
-            // they are cleared).
-            if (into_other) sh.level_meets = 1;
-            __syncthreads();
-            const bool meets = sh.level_meets != 0;
+            if (single) {
+                // The flag only goes up within a level, and a later chunk's
+                // writers pass this chunk's closing barrier first, so every
+                // thread reads the same value.
+                if (into_other) sh.level_meets = 1;
+                __syncthreads();
+                meets = sh.level_meets != 0;
+            }
 #pragma unroll
             for (int k = 0; k < UNROLL; k++) {
                 if (jj[k] < 0) continue;
-                cn.E++;
+                if (single) cn.E++;
                 if (meets && !((into_other >> k) & 1u)) continue;
                 const int32_t x = w[k];
                 const int j = jj[k];
