@@ -1146,7 +1146,8 @@ __device__ __forceinline__ void run_sample(const GGraph& g, const GSlots& sl, in
         // the one of smallest id whose cumulative sigma_s, in id order, exceeds
         // r. Without a complete arc list (or with more than KCAP
         // predecessors) a step scans w's in-row instead: the same choice.
-        if (!sh.ovf && wid == 0) {
+        // (a debug call's path index past sigma_st gets L and sigma_st only)
+        if (!sh.ovf && wid == 0 && !(dbg && dbg_r >= sh.sigma)) {
             const int32_t aM = sh.a;
             uint64_t r = dbg ? dbg_r : draw_bounded(T.seed, T.phase, idx, 2, sh.sigma);
             const int32_t na = __builtin_amdgcn_readfirstlane(sh.narcs);
