@@ -300,7 +300,9 @@ int percis_exact(percis_ctx* ctx, int32_t graph, double* p_out, double* kernel_m
  * loaded. PERCIS_OPT_SLOTS reads the compact slots' count when they are on.
  * PERCIS_OPT_SCRATCH_MB: cap on the sampler's scratch memory, 0 = auto (up to
  * 80 % of the free device memory when a graph is large enough to need it).
- * PERCIS_OPT_BLOCK: threads per sample (64, 128, 256, 512 or 1024), 0 = auto.
+ * PERCIS_OPT_BLOCK: threads per sample (64, 128, 256, 512 or 1024), 0 = auto
+ * (auto also runs a launch of at most 16 samples per slot with 512 threads
+ * per sample on fewer slots: such a launch is bound by its slowest samples).
  * PERCIS_OPT_BITMAPS: how a sample's visited sets are kept: 1 = one bitmap
  * per side in device memory; 2 = an exact hash table per side in LDS (8 KB
  * per sample), moved to the device bitmap if a side grows past 768 nodes;

@@ -315,6 +315,13 @@ constexpr uint64_t kPairChunk = 1ull << 22;  // samples per pair-kernel chunk (1
 constexpr int64_t kWideSlots = 16;           // workgroups of the 128-bit path
 constexpr int64_t kWideBytesPerNode = 4 + 16 + 4;
 constexpr int kDeferBlock = 512;             // per-node slots' block while compact slots are on
+// A launch of at most kFewPerSlot samples per slot ends with its slowest
+// sample chains, so it runs with kFewBlock threads per sample (fewer slots).
+// An estimate at eps = 0.01 on R-MAT 18 (about 7K samples per phase): 3.5 ms
+// at 128 threads, 1.6 ms at 512; at eps = 0.005 (24K): 4.2 and 2.8 ms; at
+// eps = 0.001 (481K), 512 threads are slower (23 against 15.6 ms).
+constexpr uint64_t kFewPerSlot = 16;
+constexpr int kFewBlock = 512;
 // Share of free device memory the per-node slots may take by default. Only
 // graphs too large for slots to fill the device reach it; there the per-node
 // slots run the samples compact slots hand on (R-MAT 24 directed: 7.75M
@@ -702,7 +709,21 @@ static int enqueue_tasks(percis_ctx* c, const LaunchPlan& lp, const DevTask* tab
     a.work = c->d_work;
     a.npairs = c->d_work + 1;
     a.stats = c->d_stats;
-    a.slots = (int)std::min<uint64_t>((uint64_t)c->nslots, lp.chunk);
+    // the per-node shape of this launch: wider workgroups for a small launch
+    // unless the caller fixed the shape
+    SamplerShape shape = c->shape;
+    int nsl = c->nslots;
+    if (c->ncslots == 0 && c->opt_block == 0 && c->opt_slots == 0 && shape.block < kFewBlock &&
+        lp.total <= (uint64_t)c->nslots * kFewPerSlot) {
+        SamplerShape wide = shape;
+        wide.block = kFewBlock;
+        const int occ = sampler_occupancy(wide);
+        if (occ > 0) {
+            shape = wide;
+            nsl = (int)std::min<int64_t>(c->nslots, (int64_t)std::max(c->cu_count, 1) * occ);
+        }
+    }
+    a.slots = (int)std::min<uint64_t>((uint64_t)nsl, lp.chunk);
     a.wide = c->d_wide;
     a.nwide = c->d_work + 2;
     a.big = c->d_big;
@@ -725,7 +746,7 @@ static int enqueue_tasks(percis_ctx* c, const LaunchPlan& lp, const DevTask* tab
             da.work = a.big_work;
             HIPCHK(c, launch_sampler(c->slots, da, c->shape, stream));
         } else {
-            HIPCHK(c, launch_sampler(c->slots, a, c->shape, stream));
+            HIPCHK(c, launch_sampler(c->slots, a, shape, stream));
         }
         HIPCHK(c, launch_wide(a, c->wslots, c->wide_slots, stream));
         if (timed) HIPCHK(c, hipEventRecord(c->chunk_ev[3 * i + 2], stream));
