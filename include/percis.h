@@ -318,6 +318,11 @@ int percis_exact(percis_ctx* ctx, int32_t graph, double* p_out, double* kernel_m
  * compact slots are on (they then only run the samples with large balls):
  * 64 .. 1024, 0 = auto. */
 #define PERCIS_OPT_DEFER_BLOCK 6
+/* PERCIS_OPT_PAIR_CHUNK: samples per chunk of a launch, 1 .. 2^30, 0 = auto
+ * (2^24). The pair kernel draws and lists one chunk's pairs before the
+ * sampler runs them; the lists take 48 bytes of device memory per sample of a
+ * chunk. Results do not depend on it. Reading it gives the chunk in use. */
+#define PERCIS_OPT_PAIR_CHUNK  7
 int percis_set_option(percis_ctx* ctx, int option, int64_t value);
 int percis_get_option(percis_ctx* ctx, int option, int64_t* value);
 

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(_HERE, "lib", "libpercis.so")
 HOST_ONLY = -1
 OK, E_INVAL, E_STATE, E_NOMEM, E_DEVICE, E_DEGENERATE, E_TOO_LARGE, E_SIGMA_OVERFLOW = 0, -1, -2, -3, -4, -5, -6, -7
 DIRECTED, DEVICE_PTRS, ACCUMULATE = 0x1, 0x2, 0x4
-OPT_SLOTS, OPT_SCRATCH_MB, OPT_BLOCK, OPT_BITMAPS, OPT_COMPACT, OPT_DEFER_BLOCK = 1, 2, 3, 4, 5, 6
+OPT_SLOTS, OPT_SCRATCH_MB, OPT_BLOCK, OPT_BITMAPS, OPT_COMPACT, OPT_DEFER_BLOCK, OPT_PAIR_CHUNK = 1, 2, 3, 4, 5, 6, 7
 
 if not os.path.exists(LIB_PATH):
     raise ImportError("libpercis.so is not built (%s); run __graft_entry__.build() or "

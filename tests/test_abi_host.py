@@ -147,6 +147,15 @@ def test_option_validation(P):
         assert c.get_option(P.OPT_DEFER_BLOCK) == b
     with pytest.raises(P.PercisError):
         c.set_option(P.OPT_DEFER_BLOCK, 96)
+    assert c.get_option(P.OPT_PAIR_CHUNK) == 1 << 24   # the default chunk
+    for v in (1, 4096, 1 << 30):
+        c.set_option(P.OPT_PAIR_CHUNK, v)
+        assert c.get_option(P.OPT_PAIR_CHUNK) == v
+    with pytest.raises(P.PercisError) as e:
+        c.set_option(P.OPT_PAIR_CHUNK, (1 << 30) + 1)
+    assert e.value.status == P.E_INVAL
+    c.set_option(P.OPT_PAIR_CHUNK, 0)
+    assert c.get_option(P.OPT_PAIR_CHUNK) == 1 << 24
 
 
 def test_batch_capture_needs_a_device(P):
