@@ -134,7 +134,7 @@ def main():
         return
 
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (samples would be sharded by index "
+        print("bench.py measures one GPU: the library has no multi-GPU path (samples would be sharded by index "
               "range with one integer all-reduce of the hit counts); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
