@@ -10,7 +10,7 @@ import workloads as W
 pytestmark = pytest.mark.gpu
 
 
-def build(P, compact):
+def build(P, compact, chunk=0):
     import torch
     rng = np.random.default_rng(21)
     g0, k0 = W.workload_er1000()
@@ -22,6 +22,7 @@ def build(P, compact):
     g4, k4 = W.with_isolated_component(W.er_graph(400, 900, 3), 40)
     c = P.Context(0)
     c.set_option(P.OPT_COMPACT, compact)
+    c.set_option(P.OPT_PAIR_CHUNK, chunk)
     c.load_csr(g0.n, g0.row_ptr, g0.col)
     c.set_states(k0)
     ids = [0,
@@ -39,11 +40,13 @@ def build(P, compact):
     return c, tasks, hits
 
 
-@pytest.mark.parametrize("compact", [1, 2])
-def test_captured_batch_replays_match_eager(compact):
+@pytest.mark.parametrize("compact,chunk", [(1, 0), (2, 0), (1, 4096), (2, 4096)])
+def test_captured_batch_replays_match_eager(compact, chunk):
+    """chunk 4096: the captured launch holds seven pair-kernel chunks, and
+    tasks start and end inside them."""
     import torch
     from paper_2509_11454_amd import percis as P
-    c, tasks, hits = build(P, compact)
+    c, tasks, hits = build(P, compact, chunk)
     eager_stats, eager_launch = c.sample_tasks(tasks)
     torch.cuda.synchronize()
     eager = [h.cpu().numpy().copy() for h in hits]
