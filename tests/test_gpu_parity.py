@@ -177,18 +177,30 @@ def test_rmat24_directed_window_parity():
     """The largest workload, directed R-MAT 24 with Beta(1/2, 1/2) states:
     hits and statistics of the sample window [10^6, 10^6 + 192) are
     bit-identical to the oracle's. The oracle does about 8 samples/s on 16
-    threads at this size, so a window stands in for a full run."""
+    threads at this size, so a window stands in for a full run. The full
+    10^7-sample launch that the benchmark times is then checked by properties
+    that hold at any size: it equals the window plus the ranges on either
+    side, and its hits add up to sum |I|."""
     g, k = W.workload_rmat24_directed()
     og, st = oracle_objects(g, k)
     first, count = 1_000_000, 192
     ho, so = oracle_hits(og, st, first, count, 1)
     assert so["reachable"] > 0
+    del og, st
     c = gpu_context(g, k)
     hg, sg = gpu_hits(c, first, count, 1)
     assert np.array_equal(ho, hg)
     same_stats(so, sg)
+    N = 10_000_000
+    h_full, s_full = gpu_hits(c, 0, N, 1)
+    assert s_full["samples"] == N and s_full["overflow"] == 0
+    assert int(h_full.astype(np.uint64).sum()) == s_full["sum_I"]
+    h_a, s_a = gpu_hits(c, 0, first, 1)
+    h_b, s_b = gpu_hits(c, first + count, N - first - count, 1)
+    assert np.array_equal(h_full, h_a + hg + h_b)
+    for key in ("samples", "reachable", "sum_I", "sum_I2"):
+        assert s_full[key] == s_a[key] + sg[key] + s_b[key], key
     c.close()
-    del og, st
 
 
 def test_ranges_add_up_and_accumulate():
