@@ -524,7 +524,7 @@ int vertex_diam_ub(percis_ctx* c, GraphData& G, int64_t* D) {
     int rc = graph_upload(c, G, false);
     if (rc) return rc;
     void* scratch = nullptr;
-    if (hipMalloc(&scratch, (size_t)diam_scratch_bytes(G.n_act)) != hipSuccess) {
+    if (hipMalloc(&scratch, (size_t)diam_scratch_bytes(G.n_act, G.m)) != hipSuccess) {
         (void)hipGetLastError();
         return fail(c, PERCIS_E_NOMEM, "cannot allocate the VertexDiamUB scratch");
     }

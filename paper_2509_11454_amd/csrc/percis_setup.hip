@@ -441,30 +441,77 @@ __global__ void bfs_init_kernel(const int32_t* parent, int32_t na, int32_t* dist
     }
 }
 
-// One BFS level: a wave per frontier node, its lanes over the node's arcs;
+// Rows longer than SEG entries are split into segments of SEG entries that
+// any wave can take, so that a hub's row does not hold one wave for a level.
+constexpr int32_t SEG = 1024;
+constexpr int BFS_BATCH = 8;  // BFS levels queued per host check (the count words fit the 256-byte counter block)
+
+// The arcs col[b, e) of a frontier node, one wave, its lanes over the arcs:
 // first visits are claimed by compare-and-swap and appended to the next
 // frontier (count in *nout).
-__global__ void bfs_level_kernel(const int32_t* rp, const int32_t* col, const int32_t* qin, int32_t nin,
-                                 int32_t* qout, uint32_t* nout, int32_t* dist, int32_t level) {
+__device__ __forceinline__ void bfs_visit_row(const int32_t* col, int32_t b, int32_t e, int32_t* qout, uint32_t* nout,
+                                              int32_t* dist, int32_t level) {
+    const int lane = lane_id();
+    for (int32_t j0 = b; j0 < e; j0 += 64) {
+        const int32_t j = j0 + lane;
+        bool found = false;
+        int32_t y = 0;
+        if (j < e) {
+            y = col[j];
+            if (ld_relaxed(dist + y) < 0) found = atomicCAS(&dist[y], -1, level + 1) == -1;
+        }
+        const uint64_t bal = __ballot(found);
+        uint32_t at = 0;
+        if (bal && lane == 0) at = atomicAdd(nout, (uint32_t)__popcll(bal));
+        at = (uint32_t)__shfl((int)at, 0, 64);
+        if (found) qout[at + __popcll(bal & lanes_below())] = y;
+    }
+}
+
+// One BFS level: a wave per frontier node. A row longer than SEG is not
+// scanned here: its segments (node, first entry) go to segs (count in *nseg)
+// for bfs_segment_kernel.
+__global__ void bfs_level_kernel(const int32_t* rp, const int32_t* col, const int32_t* qin, const uint32_t* nin_p,
+                                 int32_t* qout, uint32_t* nout, int32_t* dist, int32_t level, int2* segs,
+                                 uint32_t* nseg) {
     const int lane = lane_id();
     const int64_t nw = gstride() >> 6;
+    const int64_t nin = (int64_t)uniform((int32_t)*nin_p);
     for (int64_t f = uniform((int32_t)(gtid() >> 6)); f < nin; f += nw) {
         const int32_t x = uniform(qin[f]);
         const int32_t b = uniform(rp[x]), e = uniform(rp[x + 1]);
-        for (int32_t j0 = b; j0 < e; j0 += 64) {
-            const int32_t j = j0 + lane;
-            bool found = false;
-            int32_t y = 0;
-            if (j < e) {
-                y = col[j];
-                if (ld_relaxed(dist + y) < 0) found = atomicCAS(&dist[y], -1, level + 1) == -1;
-            }
-            const uint64_t bal = __ballot(found);
+        if (e - b > SEG) {
+            const int32_t k = (e - b + SEG - 1) / SEG;
             uint32_t at = 0;
-            if (bal && lane == 0) at = atomicAdd(nout, (uint32_t)__popcll(bal));
+            if (lane == 0) at = atomicAdd(nseg, (uint32_t)k);
             at = (uint32_t)__shfl((int)at, 0, 64);
-            if (found) qout[at + __popcll(bal & lanes_below())] = y;
+            for (int32_t i = lane; i < k; i += 64) segs[at + i] = make_int2(x, b + i * SEG);
+        } else {
+            bfs_visit_row(col, b, e, qout, nout, dist, level);
         }
+    }
+}
+
+// Counts of a batch of BFS levels: lc[0] := *head (the current frontier's
+// count, possibly lc[K] itself), lc[1..K] := 0, sc[0..K-1] := 0. One thread.
+__global__ void bfs_batch_counts_kernel(const uint32_t* head, uint32_t* lc, uint32_t* sc, int K) {
+    if (gtid() != 0) return;
+    const uint32_t h = *head;
+    for (int i = 1; i <= K; i++) lc[i] = 0u;
+    for (int i = 0; i < K; i++) sc[i] = 0u;
+    lc[0] = h;
+}
+
+// The long-row segments of the level: a wave per segment.
+__global__ void bfs_segment_kernel(const int32_t* rp, const int32_t* col, const int2* segs, const uint32_t* nseg,
+                                   int32_t* qout, uint32_t* nout, int32_t* dist, int32_t level) {
+    const int64_t nw = gstride() >> 6;
+    const int64_t ns = (int64_t)uniform((int32_t)*nseg);
+    for (int64_t f = uniform((int32_t)(gtid() >> 6)); f < ns; f += nw) {
+        const int2 sg = segs[f];
+        const int32_t x = uniform(sg.x), b = uniform(sg.y);
+        const int32_t e = (int32_t)min((int64_t)b + SEG, (int64_t)uniform(rp[x + 1]));
+        bfs_visit_row(col, b, e, qout, nout, dist, level);
     }
 }
 
@@ -582,9 +629,13 @@ hipError_t launch_state_build(const StateArrays& a, void* scratch, const uint64_
     return hipGetLastError();
 }
 
-int64_t diam_scratch_bytes(int32_t n_act) {
+// Long-row segments of one BFS level: at most one per SEG arcs plus one per
+// frontier node.
+static int64_t max_segments(int32_t na, int64_t m) { return m / SEG + (int64_t)na + 64; }
+
+int64_t diam_scratch_bytes(int32_t n_act, int64_t m) {
     const int64_t na = n_act > 0 ? n_act : 1;
-    return 6 * ((4 * na + 255) / 256 * 256) + 256;
+    return 6 * ((4 * na + 255) / 256 * 256) + 256 + max_segments((int32_t)na, m) * (int64_t)sizeof(int2);
 }
 
 hipError_t run_vertex_diam_ub(const int32_t* rp, const int32_t* col, int32_t na, int64_t m, bool directed,
@@ -601,8 +652,9 @@ hipError_t run_vertex_diam_ub(const int32_t* rp, const int32_t* col, int32_t na,
     int32_t* qb = (int32_t*)(s + 3 * seg);
     uint32_t* size = (uint32_t*)(s + 4 * seg);
     int32_t* ecc = (int32_t*)(s + 5 * seg);
-    uint32_t* ctr = (uint32_t*)(s + 6 * seg);            // [0] joined, [1] frontier count, [2..3] D
+    uint32_t* ctr = (uint32_t*)(s + 6 * seg);            // [0] joined, [1] frontier count, [2..3] D, [4] segments
     unsigned long long* Dd = (unsigned long long*)(ctr + 2);
+    int2* segs = (int2*)(s + 6 * seg + 256);
     hipError_t e = hipSuccess;
     const int g = grid_for(na, EB);
     hipLaunchKernelGGL(wcc_init_kernel, dim3(g), dim3(EB), 0, stream, parent, na, ctr);
@@ -630,17 +682,37 @@ hipError_t run_vertex_diam_ub(const int32_t* rp, const int32_t* col, int32_t na,
         if ((e = hipMemcpyAsync(&nin, ctr + 1, sizeof nin, hipMemcpyDeviceToHost, stream)) != hipSuccess) return e;
         if ((e = hipStreamSynchronize(stream)) != hipSuccess) return e;
         int32_t level = 0;
+        // Levels are queued BFS_BATCH at a time: each kernel reads its
+        // frontier's count from device memory (an empty frontier makes the
+        // rest of the batch no-ops), and the host looks once per batch.
+        const int sgrid = grid_for(std::min<int64_t>(max_segments(na, m), 8192) * 64, EB);
+        const int lgrid = grid_for(std::min<int64_t>(na, 8192) * 64, EB);
+        uint32_t* lc = ctr + 8;    // [0..BFS_BATCH] frontier counts of the batch
+        uint32_t* sc = ctr + 24;   // [0..BFS_BATCH) long-row segment counts
+        const uint32_t* head = ctr + 1;
         while (nin > 0) {
-            hipLaunchKernelGGL(zero_u32_kernel, dim3(1), dim3(64), 0, stream, ctr + 1, (int64_t)1);
-            const int lg = grid_for((int64_t)nin * 64, EB);
-            hipLaunchKernelGGL(bfs_level_kernel, dim3(lg), dim3(EB), 0, stream, rp, col, (const int32_t*)qa,
-                               (int32_t)nin, qb, ctr + 1, dist, level);
-            if ((e = hipMemcpyAsync(&nin, ctr + 1, sizeof nin, hipMemcpyDeviceToHost, stream)) != hipSuccess) return e;
+            hipLaunchKernelGGL(bfs_batch_counts_kernel, dim3(1), dim3(64), 0, stream, head, lc, sc, BFS_BATCH);
+            for (int i = 0; i < BFS_BATCH; i++) {
+                hipLaunchKernelGGL(bfs_level_kernel, dim3(lgrid), dim3(EB), 0, stream, rp, col, (const int32_t*)qa,
+                                   (const uint32_t*)(lc + i), qb, lc + i + 1, dist, level + i, segs, sc + i);
+                hipLaunchKernelGGL(bfs_segment_kernel, dim3(sgrid), dim3(EB), 0, stream, rp, col, (const int2*)segs,
+                                   (const uint32_t*)(sc + i), qb, lc + i + 1, dist, level + i);
+                int32_t* t = qa;
+                qa = qb;
+                qb = t;
+            }
+            uint32_t counts[BFS_BATCH + 1];
+            if ((e = hipMemcpyAsync(counts, lc, sizeof counts, hipMemcpyDeviceToHost, stream)) != hipSuccess) return e;
             if ((e = hipStreamSynchronize(stream)) != hipSuccess) return e;
-            int32_t* t = qa;
-            qa = qb;
-            qb = t;
-            level++;
+            int done = BFS_BATCH;  // non-empty frontiers of this batch
+            for (int i = 1; i <= BFS_BATCH; i++)
+                if (counts[i] == 0) {
+                    done = i;
+                    break;
+                }
+            level += done;
+            nin = counts[BFS_BATCH];
+            head = lc + BFS_BATCH;
         }
         *levels_out = level;
         dist_arg = dist;

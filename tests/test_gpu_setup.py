@@ -118,11 +118,14 @@ def diameter_cases():
                               directed=True))
     out.append(W.prop7_instance(40)[0])
     out.append(W.csr_from_edges(6, np.zeros(0, np.int32), np.zeros(0, np.int32), False, name="no arcs"))
+    # hub rows past the 1024-entry segments of the BFS (several segments, a ragged last one)
+    out.append(W.star_graph(5000))
+    out.append(disjoint_union([W.star_graph(3000), W.path_graph(40), W.star_graph(1025), W.star_graph(1024)]))
     del rng
     return out
 
 
-@pytest.mark.parametrize("ci", range(16))
+@pytest.mark.parametrize("ci", range(18))
 def test_vertex_diameter_matches_oracle(ci):
     """VertexDiamUB on the device equals the oracle's serial BFS/components
     bound (pinned on the CPU to the definition); an override replaces it and
