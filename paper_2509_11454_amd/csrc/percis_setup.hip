@@ -377,6 +377,21 @@ BuildLayout build_layout(int32_t n) {
 __device__ __forceinline__ int32_t ld_relaxed(int32_t* p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, AGENT); }
 
 // Parents only ever decrease and never exceed the node, so the chase ends.
+// The same chase with loads that may be served by the CU's cache, so a value
+// can be stale within a kernel. Parents only decrease and stay inside their
+// component, so a stale parent is still an ancestor in the same component:
+// a stale root only makes a hook link two nodes of one component, or count a
+// join that a later round finds settled. A round with no join writes nothing,
+// so its reads are exact and the final check is exact too.
+__device__ __forceinline__ int32_t find_root_cached(int32_t* parent, int32_t x) {
+    int32_t p = __hip_atomic_load(parent + x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    while (p != x) {
+        x = p;
+        p = __hip_atomic_load(parent + x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    }
+    return x;
+}
+
 __device__ __forceinline__ int32_t find_root(int32_t* parent, int32_t x) {
     int32_t p = ld_relaxed(parent + x);
     while (p != x) {
@@ -406,15 +421,21 @@ __global__ void wcc_hook_kernel(const int32_t* rp, const int32_t* col, int32_t n
         if (rp[mid] <= j) lo = mid; else hi = mid - 1;
     }
     int32_t u = lo;
+    int32_t ru = -1;  // u's root, found again after a hook and for each new row
     bool joined = false;
     for (; j < jend; j++) {
-        while (rp[u + 1] <= j) u++;
+        while (rp[u + 1] <= j) {
+            u++;
+            ru = -1;
+        }
         const int32_t w = col[j];
         if (undirected && w < u) continue;  // each edge once
-        const int32_t ru = find_root(parent, u), rw = find_root(parent, w);
+        if (ru < 0) ru = find_root_cached(parent, u);
+        const int32_t rw = find_root_cached(parent, w);
         if (ru == rw) continue;
         atomicMin(&parent[ru > rw ? ru : rw], ru > rw ? rw : ru);
         joined = true;
+        ru = -1;
     }
     if (joined) atomicOr(&ctr[0], 1u);
 }
