@@ -341,7 +341,7 @@ static int pick_shape(percis_ctx* c, int64_t act, SamplerShape* out, int* occ_ou
     SamplerShape sh{};
     sh.block = c->opt_block ? (int)c->opt_block : 128;
     (void)words;
-    const int64_t lds_need = sampler_table_lds(false);
+    const int64_t lds_need = sampler_table_lds(false, sh.block);
     const bool fits = lds_need + sampler_static_lds() <= kLdsPerCu;
     if (c->opt_bitmaps == 2 && !fits)
         return fail(c, PERCIS_E_INVAL, "visited-set tables do not fit in LDS");
@@ -464,7 +464,7 @@ static int ensure_slots(percis_ctx* c, int64_t act) {
     if (compact) {
         SamplerShape cs = sh;
         cs.compact = true;
-        cs.lds_bytes = sampler_table_lds(true);
+        cs.lds_bytes = sampler_table_lds(true, cs.block);
         const int cocc = sampler_occupancy(cs);
         const int64_t cap = sampler_table_cap(true);
         const int64_t cper = 2 * cap * (int64_t)sizeof(CRec) + 4 * cap * 4 + (cap + 2) * 4 +
@@ -502,6 +502,7 @@ static int ensure_slots(percis_ctx* c, int64_t act) {
         // threads per sample pay off there
         SamplerShape big = sh;
         big.block = c->opt_defer_block > 0 ? (int)c->opt_defer_block : kDeferBlock;
+        big.lds_bytes = sampler_table_lds(false, big.block);
         if (sampler_occupancy(big) > 0) c->shape = big;
     }
     return PERCIS_OK;
@@ -722,6 +723,7 @@ static int enqueue_tasks(percis_ctx* c, const LaunchPlan& lp, const DevTask* tab
         lp.total <= (uint64_t)c->nslots * kFewPerSlot) {
         SamplerShape wide = shape;
         wide.block = kFewBlock;
+        wide.lds_bytes = wide.lds_sets ? sampler_table_lds(false, kFewBlock) : 0;
         const int occ = sampler_occupancy(wide);
         if (occ > 0) {
             shape = wide;
@@ -1502,9 +1504,8 @@ int percis_autotune(percis_ctx* c, int32_t graph, uint64_t probe_samples, uint64
         int64_t block, bitmaps;
     };
     std::vector<Cand> cands;
-    const bool lds_ok = sampler_table_lds(false) + sampler_static_lds() <= kLdsPerCu;
     for (int64_t b : {128, 256, 512, 1024}) {
-        if (lds_ok) cands.push_back({b, 2});
+        if (sampler_table_lds(false, (int)b) + sampler_static_lds() <= kLdsPerCu) cands.push_back({b, 2});
         cands.push_back({b, 1});
     }
     std::vector<TaskSpec> one(1);

@@ -199,9 +199,11 @@ int64_t exact_scratch_bytes(int64_t stride, int slots);
 // Resident workgroups per CU for a shape (0 if it cannot launch).
 int sampler_occupancy(const SamplerShape& shape);
 int64_t sampler_static_lds();
-// Dynamic LDS of the visited-set tables (LDS mode) and their entries per
-// side (the records per side of a compact slot), for per-node or compact slots.
-int64_t sampler_table_lds(bool compact);
+// Dynamic LDS of the visited-set tables (LDS mode) of a sampler with `block`
+// threads per sample (per-node slots of 512 threads or more have larger
+// tables), and the entries per side of a table (the records per side of a
+// compact slot).
+int64_t sampler_table_lds(bool compact, int block);
 int sampler_table_cap(bool compact);
 
 }  // namespace percis

@@ -171,18 +171,26 @@ struct Recs {
 #ifndef PERCIS_HBITS_COMPACT
 #define PERCIS_HBITS_COMPACT 11
 #endif
+// Per-node slots of 512 threads or more run few workgroups per CU (the
+// samples compact slots hand on, and small launches), so their tables can be
+// larger: a side then stays in LDS up to 3/4 of 2^HBITS_WIDE nodes.
+#ifndef PERCIS_HBITS_WIDE
+#define PERCIS_HBITS_WIDE 13
+#endif
 constexpr int HBITS = PERCIS_HBITS;           // per-node slots
 constexpr int HBITS_C = PERCIS_HBITS_COMPACT; // compact slots
+constexpr int HBITS_W = PERCIS_HBITS_WIDE;    // per-node slots of 512 threads or more
 template <int TB>
 struct Tab {
     static constexpr int CAP = 1 << TB;          // table slots per side
     static constexpr int LIMIT = 3 * CAP / 4;    // most entries a table takes
     static constexpr int ADMIT = 5 * CAP / 8;    // a level decides first visits by the table if it cannot add more
 };
-template <bool CMP>
-constexpr int tbits() { return CMP ? HBITS_C : HBITS; }
+// Table bits of a sampler build (threads per sample, compact slots or not).
+template <int BSZ, bool CMP>
+constexpr int tbits() { return CMP ? HBITS_C : (BSZ >= 512 ? HBITS_W : HBITS); }
+constexpr int table_bits(int block, bool compact) { return compact ? HBITS_C : (block >= 512 ? HBITS_W : HBITS); }
 constexpr int HCAP = Tab<HBITS>::CAP;         // per-node slots' table
-constexpr int HADMIT = Tab<HBITS>::ADMIT;
 constexpr int CCAP = Tab<HBITS_C>::CAP;       // compact slots' table (records per side)
 
 // Level word of x on side SIDE.
@@ -236,14 +244,14 @@ struct Vis {
 // first; they are addressed from the array itself so that the compiler keeps
 // their accesses in LDS.
 extern __shared__ uint32_t dyn_lds[];
-template <int TB = HBITS>
+template <int TB>
 __device__ __forceinline__ uint32_t* tab(int side) { return dyn_lds + side * Tab<TB>::CAP; }
 
 template <int TB>
 __device__ __forceinline__ uint32_t hslot(int32_t x) { return ((uint32_t)x * 0x9E3779B1u) >> (32 - TB); }
 
 // Position of x in table T, or -1.
-template <int TB = HBITS>
+template <int TB>
 __device__ __forceinline__ int table_find(uint32_t* T, int32_t x) {
     const uint32_t key = (uint32_t)x + 1;
     for (uint32_t i = hslot<TB>(x);; i = (i + 1) & (Tab<TB>::CAP - 1)) {
@@ -252,11 +260,12 @@ __device__ __forceinline__ int table_find(uint32_t* T, int32_t x) {
         if (v == 0) return -1;
     }
 }
-__device__ __forceinline__ bool table_has(uint32_t* T, int32_t x) { return table_find<HBITS>(T, x) >= 0; }
+template <int TB>
+__device__ __forceinline__ bool table_has(uint32_t* T, int32_t x) { return table_find<TB>(T, x) >= 0; }
 
 // Inserts x, known to be absent and inserted by this thread only; returns
 // its position, or -1 if the table is full (it then stays without x).
-template <int TB = HBITS>
+template <int TB>
 __device__ __forceinline__ int table_put(uint32_t* T, int32_t* cnt, int32_t x) {
     if (atomicAdd(cnt, 1) >= Tab<TB>::LIMIT) return -1;
     const uint32_t key = (uint32_t)x + 1;
@@ -291,10 +300,12 @@ __device__ __forceinline__ int table_visit_bounded(uint32_t* T, int32_t* cnt, in
 }
 
 // Finds or inserts x; true iff this call inserted it. The caller guarantees
-// room (fewer than HCAP entries after every possible insert). Per-node slots.
+// room (fewer than Tab<TB>::CAP entries after every possible insert).
+// Per-node slots.
+template <int TB>
 __device__ __forceinline__ bool table_visit(uint32_t* T, int32_t* cnt, int32_t x) {
     const uint32_t key = (uint32_t)x + 1;
-    for (uint32_t i = hslot<HBITS>(x);; i = (i + 1) & (HCAP - 1)) {
+    for (uint32_t i = hslot<TB>(x);; i = (i + 1) & (Tab<TB>::CAP - 1)) {
         uint32_t v = __hip_atomic_load(T + i, __ATOMIC_RELAXED, WGS);
         if (v == 0) {
             uint32_t expect = 0;
@@ -410,10 +421,10 @@ struct SampleShared {
 };
 
 // Is x in side `side`'s ball? Exact.
-template <bool LDS>
+template <bool LDS, int TB>
 __device__ __forceinline__ bool member(const Vis<LDS>& V, const SampleShared& sh, int side, int32_t x) {
     if (!LDS || sh.spilled[side]) return Bits::test(Bits::rd(V.bm[side], x), x);
-    return table_has(tab(side), x);
+    return table_has<TB>(tab<TB>(side), x);
 }
 
 // Records the DAG arc tail -> head weighed by sigma_s(tail) = w; arcs past the
@@ -568,7 +579,7 @@ __device__ __forceinline__ void fetch_batch(const G<int32_t>* col, const SampleS
 // Member tests of a batch against the other side's ball (side OTHER); bit k
 // of the result is set when w[k] is in it, at position po[k] of its table
 // (compact slots).
-template <int OTHER, bool LDS, bool CMP, int U>
+template <int OTHER, bool LDS, bool CMP, int TB, int U>
 __device__ __forceinline__ uint32_t probe_batch(const Vis<LDS>& V, const SampleShared& sh, const int32_t (&w)[U],
                                                 const int (&jj)[U], int (&po)[U]) {
     uint32_t into = 0;
@@ -579,7 +590,7 @@ __device__ __forceinline__ uint32_t probe_batch(const Vis<LDS>& V, const SampleS
         if constexpr (CMP) {
             po[k] = table_find<HBITS_C>(tab<HBITS_C>(OTHER), w[k]);
             if (po[k] >= 0) into |= 1u << k;
-        } else if (member<LDS>(V, sh, OTHER, w[k])) {
+        } else if (member<LDS, TB>(V, sh, OTHER, w[k])) {
             into |= 1u << k;
         }
     }
@@ -613,6 +624,7 @@ template <int SIDE, int BSZ, bool LDS, bool CMP>
 __device__ __forceinline__ void expand_bfs(const GGraph& g, const GSlots& sl, int64_t so, const Vis<LDS>& V, const Recs<CMP>& rc,
                            int lo, int hi, uint32_t nl, bool careful, SampleShared& sh, Counters& cn) {
     using B = Bits;
+    constexpr int TB = tbits<BSZ, CMP>();
     const int tid = threadIdx.x;
     const bool by_table = LDS && sh.level_table;   // else: bitmap (device mode) or record CAS (LDS mode)
     G<DagArc>* arcs = sl.arcs + (int64_t)blockIdx.x * sl.acap;
@@ -638,7 +650,7 @@ __device__ __forceinline__ void expand_bfs(const GGraph& g, const GSlots& sl, in
                 int32_t w[SCAN_UNROLL];
                 int jj[SCAN_UNROLL], po[SCAN_UNROLL];
                 fetch_batch<BSZ>(col, sh, b0, total, cnt, w, jj);
-                const uint32_t in = probe_batch<1 - SIDE, LDS, CMP>(V, sh, w, jj, po);
+                const uint32_t in = probe_batch<1 - SIDE, LDS, CMP, TB>(V, sh, w, jj, po);
 #pragma unroll
                 for (int k = 0; k < SCAN_UNROLL; k++) {
                     if (jj[k] < 0) continue;
@@ -684,7 +696,7 @@ __device__ __forceinline__ void expand_bfs(const GGraph& g, const GSlots& sl, in
             } else {
                 fetch_batch<BSZ>(col, sh, b0, total, cnt, w, jj);
                 if (single || meets) {
-                    into_other = probe_batch<1 - SIDE, LDS, CMP>(V, sh, w, jj, po);
+                    into_other = probe_batch<1 - SIDE, LDS, CMP, TB>(V, sh, w, jj, po);
                 } else {
 #pragma unroll
                     for (int k = 0; k < UNROLL; k++) po[k] = -1;
@@ -729,7 +741,7 @@ __device__ __forceinline__ void expand_bfs(const GGraph& g, const GSlots& sl, in
                         add = lv == 0 || lv == nl;
                     }
                 } else if (by_table) {
-                    fresh = table_visit(tab(SIDE), &sh.hcnt[SIDE], x);
+                    fresh = table_visit<TB>(tab<TB>(SIDE), &sh.hcnt[SIDE], x);
                     if (fresh) {
                         add = true;
                     } else {
@@ -745,7 +757,7 @@ __device__ __forceinline__ void expand_bfs(const GGraph& g, const GSlots& sl, in
                     lv_written = true;
                     if (fresh) {
                         if (sh.spilled[SIDE]) (void)B::set(vis_mine, x);
-                        else if (table_put(tab(SIDE), &sh.hcnt[SIDE], x) < 0) sh.spill_req[SIDE] = 1;
+                        else if (table_put<TB>(tab<TB>(SIDE), &sh.hcnt[SIDE], x) < 0) sh.spill_req[SIDE] = 1;
                     }
                 }
                 if (add) {
@@ -851,7 +863,7 @@ __device__ void pull_level(const GGraph& g, const GSlots& sl, int64_t so, const 
             if constexpr (CMP) {
                 pu = table_find<HBITS_C>(tab<HBITS_C>(1), u);
                 if (pu < 0) continue;
-            } else if (!member<LDS>(V, sh, 1, u)) {
+            } else if (!member<LDS, tbits<BSZ, CMP>()>(V, sh, 1, u)) {
                 continue;
             }
             // levels of this level's nodes are final (set before the last
@@ -893,7 +905,7 @@ __device__ void push_meeting(const GGraph& g, const GSlots& sl, int64_t so, cons
             if constexpr (CMP) {
                 px = table_find<HBITS_C>(tab<HBITS_C>(1), x);
                 if (px < 0) continue;
-            } else if (!member<LDS>(V, sh, 1, x)) {
+            } else if (!member<LDS, tbits<BSZ, CMP>()>(V, sh, 1, x)) {
                 continue;
             }
             if ((ld32(rc.template lv<1>(x, px)) & LVMASK) != want) continue;
@@ -908,12 +920,14 @@ __device__ void push_meeting(const GGraph& g, const GSlots& sl, int64_t so, cons
 // Next BFS level: the side with the smaller frontier degree sum (Section
 // III-B's balanced expansion), its queue's append position, fresh
 // accumulators. Called by one thread.
+template <int TB>
 __device__ __forceinline__ void plan_level(SampleShared& sh) {
     sh.side = (sh.deg_s <= sh.deg_t) ? 0 : 1;
     sh.tail = sh.side == 0 ? sh.hi_s : sh.hi_t;
     // a level adds at most its frontier degree sum of new nodes
     const unsigned long long deg = sh.side == 0 ? sh.deg_s : sh.deg_t;
-    sh.level_table = !sh.spilled[sh.side] && (unsigned long long)sh.hcnt[sh.side] + deg <= (unsigned long long)HADMIT;
+    sh.level_table =
+        !sh.spilled[sh.side] && (unsigned long long)sh.hcnt[sh.side] + deg <= (unsigned long long)Tab<TB>::ADMIT;
     sh.deg_next = 0;
     sh.mass_next = 0;
     sh.wide_next = 0;
@@ -966,7 +980,7 @@ __device__ __forceinline__ void run_sample(const GGraph& g, const GSlots& sl, in
                                            uint64_t dbg_r, int32_t dbg_cap) {
     using B = Bits;
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-    constexpr int TB = tbits<CMP>();
+    constexpr int TB = tbits<BSZ, CMP>();
     const Recs<CMP> rc{CMP ? nullptr : sl.rec + so, CMP ? sl.crec + (int64_t)blockIdx.x * 2 * CCAP : nullptr};
     G<int32_t>* q_s = sl.q_s + so;
     G<int32_t>* q_t = sl.q_t + so;
@@ -1023,7 +1037,7 @@ __device__ __forceinline__ void run_sample(const GGraph& g, const GSlots& sl, in
                 sh.wide_s = 0; sh.wide_t = 0;
                 sh.deg_t_prev = 0;
                 sh.tail_s = 1; sh.tail_t = 1;
-                plan_level(sh);
+                plan_level<TB>(sh);
             }
         }
     }
@@ -1067,7 +1081,7 @@ __device__ __forceinline__ void run_sample(const GGraph& g, const GSlots& sl, in
             if (CMP && sh.abort) sh.status = 3;
             else if (sh.nmeet > 0) sh.status = 1;
             else if (nhi == nlo) sh.status = 2;
-            else plan_level(sh);
+            else plan_level<TB>(sh);
         }
         level_barrier();
     }
@@ -1233,7 +1247,7 @@ __device__ __forceinline__ void run_sample(const GGraph& g, const GSlots& sl, in
                                     pu = table_find<HBITS_C>(tab<HBITS_C>(on_s ? 0 : 1), u[k]);
                                     in_ball = pu >= 0;
                                 } else {
-                                    in_ball = member<LDS>(V, sh, on_s ? 0 : 1, u[k]);
+                                    in_ball = member<LDS, TB>(V, sh, on_s ? 0 : 1, u[k]);
                                 }
                             }
                             if (in_ball) {
@@ -1393,7 +1407,7 @@ __global__ __launch_bounds__(BSZ) SAMPLER_OCCUPANCY void sampler_kernel(DevSlots
     const Vis<LDS> V = slot_vis<BSZ, LDS>(sl, blockIdx.x);
     Counters cn = {0, 0, 0, 0};
     if (LDS) {
-        for (int i = tid; i < 2 * Tab<tbits<CMP>()>::CAP; i += BSZ) dyn_lds[i] = 0;
+        for (int i = tid; i < 2 * Tab<tbits<BSZ, CMP>()>::CAP; i += BSZ) dyn_lds[i] = 0;
     }
     if (tid == 0) {
         for (int i = 0; i < 5; i++) sh.phase_ticks[i] = 0;
@@ -1438,7 +1452,7 @@ __global__ __launch_bounds__(BSZ) void debug_path_kernel(DevGraph g, DevSlots sl
     const Vis<LDS> V = slot_vis<BSZ, LDS>(sl, 0);
     Counters cn = {0, 0, 0, 0};
     if (LDS) {
-        for (int i = threadIdx.x; i < 2 * HCAP; i += BSZ) dyn_lds[i] = 0;
+        for (int i = threadIdx.x; i < 2 * Tab<tbits<BSZ, false>()>::CAP; i += BSZ) dyn_lds[i] = 0;
     }
     if (threadIdx.x == 0) {
         for (int i = 0; i < 5; i++) sh.phase_ticks[i] = 0;
@@ -1814,7 +1828,9 @@ hipError_t launch_clear_tasks(const DevTask* tasks, int ntasks, int64_t max_n, h
 }
 
 int64_t sampler_static_lds() { return (int64_t)sizeof(SampleShared); }
-int64_t sampler_table_lds(bool compact) { return (int64_t)2 * (compact ? CCAP : HCAP) * sizeof(uint32_t); }
+int64_t sampler_table_lds(bool compact, int block) {
+    return (int64_t)2 * ((int64_t)1 << table_bits(block, compact)) * (int64_t)sizeof(uint32_t);
+}
 int sampler_table_cap(bool compact) { return compact ? CCAP : HCAP; }
 
 template <int BSZ, bool LDS>
@@ -1846,7 +1862,7 @@ int sampler_occupancy(const SamplerShape& s) {
     const void* fn = pick_sampler(s);
     if (!fn) return 0;
     int blocks = 0;
-    const size_t dyn = s.lds_sets ? (size_t)s.lds_bytes : 0;
+    const size_t dyn = s.lds_sets ? (size_t)sampler_table_lds(s.compact, s.block) : 0;
     if (dyn > 0) (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn);
     (void)hipGetLastError();
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, fn, s.block, dyn) != hipSuccess) return 0;
@@ -1858,7 +1874,7 @@ hipError_t launch_sampler(const DevSlots& slots, const SampleLaunch& a, const Sa
     if (a.count == 0 || a.slots <= 0) return hipSuccess;
     const void* fn = pick_sampler(shape);
     if (!fn) return hipErrorInvalidValue;
-    const size_t dyn = shape.lds_sets ? (size_t)shape.lds_bytes : 0;
+    const size_t dyn = shape.lds_sets ? (size_t)sampler_table_lds(shape.compact, shape.block) : 0;
     if (dyn > 0) (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn);
     (void)hipGetLastError();
     void* args[] = {(void*)&slots, (void*)&a};
@@ -1876,7 +1892,7 @@ hipError_t launch_debug_path(const DevGraph& g, const DevSlots& slots, int32_t s
         case 1024: fn = shape.lds_sets ? (const void*)&debug_path_kernel<1024, true> : (const void*)&debug_path_kernel<1024, false>; break;
         default: return hipErrorInvalidValue;
     }
-    const size_t dyn = shape.lds_sets ? (size_t)shape.lds_bytes : 0;
+    const size_t dyn = shape.lds_sets ? (size_t)sampler_table_lds(shape.compact, shape.block) : 0;
     if (dyn > 0) (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn);
     (void)hipGetLastError();
     void* args[] = {(void*)&g, (void*)&slots, (void*)&s, (void*)&t, (void*)&r, (void*)&out, (void*)&cap};
