@@ -72,6 +72,10 @@ def _load():
         "orc_path128": (i32, [P, i32, i32, u64, u64, P, i32, P, P]),
         "orc_bounded128_parts": (None, [u64, u64, u64, u64, u64, u64, P, P, P]),
         "orc_sample_range": (None, [P, P, u64, u64, u64, u64, P, P, P]),
+        "orc_sample_range_bidir": (None, [P, P, u64, u64, u64, u64, P, P, P, P]),
+        "orc_bidir_work_new": (P, [i32]),
+        "orc_bidir_work_free": (None, [P]),
+        "orc_path_bidir128": (i32, [P, i32, i32, u64, u64, P, i32, P, P]),
         "orc_exact": (None, [P, P, P]),
         "orc_vertex_diam_ub": (i64, [P]),
         "orc_sample_size": (C.c_double, [C.c_double] * 5 + [P]),
@@ -172,13 +176,15 @@ def draw_pair(st, seed, phase, idx):
 SIGMA_SATURATED = (1 << 128) - 1
 
 
-def path(g, s, t, r=0):
+def path(g, s, t, r=0, bidir=False):
     """Returns (L, sigma, path) with path = [s, ..., t] or None; r and sigma
-    are Python ints (sigma saturates at 2^128 - 1, which means overflow)."""
+    are Python ints (sigma saturates at 2^128 - 1, which means overflow).
+    bidir: through the balanced bidirectional search instead of the
+    truncated BFS (the same result)."""
     buf = np.zeros(g.n + 1, np.int32)
     lo, hi = C.c_uint64(0), C.c_uint64(0)
-    L = int(_load().orc_path128(g._h, s, t, r & ((1 << 64) - 1), r >> 64, _ptr(buf), g.n + 1,
-                                C.byref(lo), C.byref(hi)))
+    fn = _load().orc_path_bidir128 if bidir else _load().orc_path128
+    L = int(fn(g._h, s, t, r & ((1 << 64) - 1), r >> 64, _ptr(buf), g.n + 1, C.byref(lo), C.byref(hi)))
     sigma = (int(hi.value) << 64) | int(lo.value)
     p = None
     if L >= 0 and sigma < SIGMA_SATURATED and r < sigma:
@@ -195,14 +201,37 @@ def bounded128(seed, phase, idx, variate, N):
     return (int(hi.value) << 64) | int(lo.value), int(used.value)
 
 
-def sample_range(g, st, first, count, seed, phase=0, with_I=False):
-    """Returns (hits uint32[n], stats dict[, I int32[count]])."""
+class BidirWork:
+    """Scratch of the bidirectional search for graphs of up to n nodes; one
+    thread uses it at a time. Reusing it across sample ranges saves
+    allocating and touching about 70 bytes per node for every range."""
+
+    def __init__(self, n):
+        self.n = int(n)
+        self._h = _load().orc_bidir_work_new(self.n)
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.orc_bidir_work_free(self._h)
+            self._h = None
+
+
+def sample_range(g, st, first, count, seed, phase=0, with_I=False, bidir=False, work=None):
+    """Returns (hits uint32[n], stats dict[, I int32[count]]). bidir: each
+    sample's path through the balanced bidirectional search instead of the
+    truncated BFS (the same results, much faster on large graphs); work: a
+    BidirWork of at least g.n nodes to run it in."""
     lib = _load()
     hits = np.zeros(g.n, np.uint32)
     S = _Stats()
     I = np.zeros(max(count, 1), np.int32) if with_I else None
-    lib.orc_sample_range(g._h, st._h, first, count, seed, phase, _ptr(hits), C.byref(S),
-                         _ptr(I) if with_I else None)
+    if bidir:
+        assert work is None or work.n >= g.n
+        lib.orc_sample_range_bidir(g._h, st._h, first, count, seed, phase, _ptr(hits), C.byref(S),
+                                   _ptr(I) if with_I else None, work._h if work is not None else None)
+    else:
+        lib.orc_sample_range(g._h, st._h, first, count, seed, phase, _ptr(hits), C.byref(S),
+                             _ptr(I) if with_I else None)
     if with_I:
         return hits, S.to_dict(), I[:count]
     return hits, S.to_dict()

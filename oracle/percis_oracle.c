@@ -22,6 +22,11 @@
  *   orc_path            RandomSP (Section III-B): BFS from s expanded until t is
  *                       found, shortest-path counts sigma (Section II-A), and one
  *                       shortest path chosen by the canonical backward walk.
+ *   orc_path_bidir128,  RandomSP through the balanced bidirectional BFS that
+ *   orc_sample_range_   Section III-B recommends: two balls grown from s and t,
+ *   bidir               the sigma_s counts carried through the t side, the same
+ *                       canonical walk. A speed path for the largest graphs,
+ *                       proved equal to the truncated BFS by the CPU tests.
  *   orc_bounded128      Lemire's method at 128 bits, for r when sigma_st >= 2^64.
  *   orc_sample_range    The sampling loop of Algorithm 2 with RandomSP, reporting
  *                       per-node counts of internal-node hits (estimator of
@@ -348,14 +353,17 @@ typedef struct {
     int32_t* dist;   /* -1 = not reached */
     u128* sigma;     /* saturates at 2^128 - 1 */
     int32_t* queue;
+    int32_t touched; /* nodes the last search reached: queue[0 .. touched) */
 } orc_work;
 
 static orc_work* work_new(int32_t n)
 {
     orc_work* w = (orc_work*)malloc(sizeof(orc_work));
     w->dist = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
-    w->sigma = (u128*)malloc(sizeof(u128) * (size_t)(n > 0 ? n : 1));
+    w->sigma = (u128*)calloc((size_t)(n > 0 ? n : 1), sizeof(u128));
     w->queue = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    for (int32_t v = 0; v < n; v++) w->dist[v] = -1;
+    w->touched = 0;
     return w;
 }
 static void work_free(orc_work* w) { free(w->dist); free(w->sigma); free(w->queue); free(w); }
@@ -371,7 +379,8 @@ static u128 add_sat(u128 a, u128 b)
  * has been expanded and sigma[t] is complete. Returns dist(t) or -1. */
 static int32_t truncated_bfs(const orc_graph* g, int32_t s, int32_t t, orc_work* wk)
 {
-    for (int32_t v = 0; v < g->n; v++) { wk->dist[v] = -1; wk->sigma[v] = 0; }
+    /* forget the previous search: every node it reached is in its queue */
+    for (int32_t i = 0; i < wk->touched; i++) { wk->dist[wk->queue[i]] = -1; wk->sigma[wk->queue[i]] = 0; }
     int32_t head = 0, tail = 0;
     wk->dist[s] = 0; wk->sigma[s] = 1; wk->queue[tail++] = s;
     while (head < tail) {
@@ -383,6 +392,7 @@ static int32_t truncated_bfs(const orc_graph* g, int32_t s, int32_t t, orc_work*
             if (wk->dist[v] == wk->dist[u] + 1) wk->sigma[v] = add_sat(wk->sigma[v], wk->sigma[u]);
         }
     }
+    wk->touched = tail;
     return wk->dist[t];
 }
 
@@ -491,6 +501,235 @@ void orc_sample_range(const orc_graph* g, const orc_states* st, uint64_t first, 
     if (stats) *stats = S;
     free(path);
     work_free(wk);
+}
+
+/* ------------------------------------------------------------------------- */
+/* RandomSP by balanced bidirectional BFS (Section III-B): two BFS balls, one  */
+/* grown from s along out-arcs and one grown from t along in-arcs, the ball   */
+/* whose frontier has fewer arcs to scan growing by one full level at a time. */
+/* The canonical path depends only on the graph, s, t and r, so this finds    */
+/* exactly the path of the truncated BFS above; the CPU tests check that on   */
+/* every (s, t, r) of small graphs and on sample windows of large ones. It is */
+/* a speed path of the oracle for graphs where a truncated BFS from s would   */
+/* scan most of the graph for every sample.                                   */
+/* ------------------------------------------------------------------------- */
+typedef struct {
+    int32_t* ds;    /* distance from s, -1 = outside the s-ball */
+    int32_t* dt;    /* distance to t, -1 = outside the t-ball */
+    u128* gs;       /* shortest s-x path counts in the s-ball */
+    u128* gt;       /* shortest x-t path counts in the t-ball */
+    u128* gw;       /* t-ball: shortest s-x path counts for x on a shortest s-t path, else 0 */
+    int32_t* qs;    /* the s-ball in BFS order (each level contiguous) */
+    int32_t* qt;    /* the t-ball in BFS order */
+    int32_t* tlev;  /* t-level j is qt[tlev[j] .. tlev[j+1]) */
+    int32_t ns, nt; /* ball sizes */
+    int32_t a, b;   /* levels each ball has completed */
+} orc_bwork;
+
+static orc_bwork* bwork_new(int32_t n)
+{
+    size_t N = (size_t)(n > 0 ? n : 1);
+    orc_bwork* w = (orc_bwork*)calloc(1, sizeof(orc_bwork));
+    w->ds = (int32_t*)malloc(sizeof(int32_t) * N);
+    w->dt = (int32_t*)malloc(sizeof(int32_t) * N);
+    w->gs = (u128*)calloc(N, sizeof(u128));
+    w->gt = (u128*)calloc(N, sizeof(u128));
+    w->gw = (u128*)calloc(N, sizeof(u128));
+    w->qs = (int32_t*)malloc(sizeof(int32_t) * N);
+    w->qt = (int32_t*)malloc(sizeof(int32_t) * N);
+    w->tlev = (int32_t*)malloc(sizeof(int32_t) * (N + 2));
+    for (int32_t v = 0; v < n; v++) { w->ds[v] = -1; w->dt[v] = -1; }
+    return w;
+}
+
+static void bwork_free(orc_bwork* w)
+{
+    free(w->ds); free(w->dt); free(w->gs); free(w->gt); free(w->gw); free(w->qs); free(w->qt); free(w->tlev);
+    free(w);
+}
+
+static u128 mul_sat(u128 x, u128 y)
+{
+    if (x != 0 && y > ~(u128)0 / x) return ~(u128)0;
+    return x * y;
+}
+
+/* Grows both balls until a level reaches the other ball. Returns d(s,t), or
+ * -1 if a ball stops growing first (t unreachable), and sets *sigma_st
+ * (saturated at 2^128 - 1). On return every node at distance <= a from s
+ * has ds and gs, and every node at distance <= b to t has dt and gt.
+ * If the last level grown is level a of the s-ball, its new nodes that lie
+ * in the t-ball are all at distance b to t (an earlier meeting would have
+ * stopped the search), so d(s,t) = a + b, and every shortest path crosses
+ * t-level b at one of them; the same holds with the sides swapped. Then
+ * sigma_st = sum over that meeting layer of gs * gt. */
+static int32_t bidir_search(const orc_graph* g, int32_t s, int32_t t, orc_bwork* w, u128* sigma_st)
+{
+    for (int32_t i = 0; i < w->ns; i++) { w->ds[w->qs[i]] = -1; w->gs[w->qs[i]] = 0; }
+    for (int32_t i = 0; i < w->nt; i++) { w->dt[w->qt[i]] = -1; w->gt[w->qt[i]] = 0; w->gw[w->qt[i]] = 0; }
+    w->ns = w->nt = 0;
+    w->a = w->b = 0;
+    *sigma_st = 0;
+    w->ds[s] = 0; w->gs[s] = 1; w->qs[w->ns++] = s;
+    w->dt[t] = 0; w->gt[t] = 1; w->qt[w->nt++] = t;
+    w->tlev[0] = 0; w->tlev[1] = 1;
+    if (s == t) { *sigma_st = 1; return 0; }
+    int32_t s_lo = 0, t_lo = 0;   /* current frontiers: qs[s_lo .. ns), qt[t_lo .. nt) */
+    for (;;) {
+        if (s_lo == w->ns || t_lo == w->nt) return -1;
+        uint64_t arcs_s = 0, arcs_t = 0;
+        for (int32_t i = s_lo; i < w->ns; i++) arcs_s += (uint64_t)(g->rp[w->qs[i] + 1] - g->rp[w->qs[i]]);
+        for (int32_t i = t_lo; i < w->nt; i++) arcs_t += (uint64_t)(g->irp[w->qt[i] + 1] - g->irp[w->qt[i]]);
+        u128 meet = 0;
+        int met = 0;
+        if (arcs_s <= arcs_t) {
+            int32_t hi = w->ns, lv = w->a + 1;
+            for (int32_t i = s_lo; i < hi; i++) {
+                int32_t u = w->qs[i];
+                for (int64_t e = g->rp[u]; e < g->rp[u + 1]; e++) {
+                    int32_t v = g->col[e];
+                    if (w->ds[v] < 0) { w->ds[v] = lv; w->qs[w->ns++] = v; }
+                    if (w->ds[v] == lv) w->gs[v] = add_sat(w->gs[v], w->gs[u]);
+                }
+            }
+            s_lo = hi;
+            w->a = lv;
+            for (int32_t i = hi; i < w->ns; i++) {
+                int32_t v = w->qs[i];
+                if (w->dt[v] >= 0) { met = 1; meet = add_sat(meet, mul_sat(w->gs[v], w->gt[v])); }
+            }
+        } else {
+            int32_t hi = w->nt, lv = w->b + 1;
+            for (int32_t i = t_lo; i < hi; i++) {
+                int32_t u = w->qt[i];
+                for (int64_t e = g->irp[u]; e < g->irp[u + 1]; e++) {
+                    int32_t v = g->icol[e];
+                    if (w->dt[v] < 0) { w->dt[v] = lv; w->qt[w->nt++] = v; }
+                    if (w->dt[v] == lv) w->gt[v] = add_sat(w->gt[v], w->gt[u]);
+                }
+            }
+            t_lo = hi;
+            w->b = lv;
+            w->tlev[lv + 1] = w->nt;
+            for (int32_t i = hi; i < w->nt; i++) {
+                int32_t v = w->qt[i];
+                if (w->ds[v] >= 0) { met = 1; meet = add_sat(meet, mul_sat(w->gs[v], w->gt[v])); }
+            }
+        }
+        if (met) { *sigma_st = meet; return w->a + w->b; }
+    }
+}
+
+/* After a meeting: gw[x] for the t-ball. A node x at distance j < b to t lies
+ * on a shortest s-t path iff its distance from s is L - j; its shortest
+ * predecessors u then lie on shortest s-t paths too, at distance j + 1 to t,
+ * so sigma_s(x) = the sum of sigma_s(u) over in-neighbours u at t-level j + 1
+ * that lie on shortest s-t paths. At t-level b those are the meeting layer
+ * (the t-level-b nodes inside the s-ball), whose sigma_s is gs. Off the
+ * shortest paths the sums come out 0. */
+static void bidir_carry(const orc_graph* g, orc_bwork* w)
+{
+    for (int32_t i = w->tlev[w->b]; i < w->tlev[w->b + 1]; i++) {
+        int32_t x = w->qt[i];
+        if (w->ds[x] >= 0) w->gw[x] = w->gs[x];
+    }
+    for (int32_t j = w->b - 1; j >= 0; j--) {
+        for (int32_t i = w->tlev[j]; i < w->tlev[j + 1]; i++) {
+            int32_t x = w->qt[i];
+            u128 sum = 0;
+            for (int64_t e = g->irp[x]; e < g->irp[x + 1]; e++) {
+                int32_t u = g->icol[e];
+                if (w->dt[u] == j + 1) sum = add_sat(sum, w->gw[u]);
+            }
+            w->gw[x] = sum;
+        }
+    }
+}
+
+/* The canonical backward walk of canonical_walk on the two balls: the
+ * predecessors of the node at position p + 1 are its in-neighbours at
+ * distance p from s, weighed by sigma_s: read from the s-ball while p <= a,
+ * from the t-ball (distance L - p to t, weight gw) beyond it. A node with
+ * weight 0 is not a predecessor. */
+static void bidir_walk(const orc_graph* g, int32_t t, int32_t L, u128 r, const orc_bwork* w, int32_t* path)
+{
+    int32_t x = t;
+    path[L] = t;
+    for (int32_t pos = L; pos >= 1; pos--) {
+        int32_t p = pos - 1, next = -1;
+        for (int64_t e = g->irp[x]; e < g->irp[x + 1]; e++) {
+            int32_t u = g->icol[e];
+            u128 su;
+            if (p <= w->a) su = w->ds[u] == p ? w->gs[u] : 0;
+            else su = w->dt[u] == L - p ? w->gw[u] : 0;
+            if (su == 0) continue;
+            if (r < su) { next = u; break; }
+            r -= su;
+        }
+        path[p] = next;
+        x = next;
+    }
+}
+
+/* orc_path128 through the bidirectional search. */
+int32_t orc_path_bidir128(const orc_graph* g, int32_t s, int32_t t, uint64_t r_lo, uint64_t r_hi, int32_t* path,
+                          int32_t cap, uint64_t* sigma_lo, uint64_t* sigma_hi)
+{
+    orc_bwork* w = bwork_new(g->n);
+    u128 sg = 0;
+    int32_t L = bidir_search(g, s, t, w, &sg);
+    u128 r = (u128)r_lo | ((u128)r_hi << 64);
+    if (sigma_lo) *sigma_lo = (uint64_t)sg;
+    if (sigma_hi) *sigma_hi = (uint64_t)(sg >> 64);
+    if (L >= 0 && sg != ~(u128)0 && r < sg && cap >= L + 1) {
+        bidir_carry(g, w);
+        bidir_walk(g, t, L, r, w, path);
+    }
+    bwork_free(w);
+    return L;
+}
+
+/* Scratch of the bidirectional search for graphs of up to n nodes, for
+ * callers that run many sample ranges (one per thread at a time). */
+orc_bwork* orc_bidir_work_new(int32_t n) { return bwork_new(n); }
+void orc_bidir_work_free(orc_bwork* w) { if (w) bwork_free(w); }
+
+/* orc_sample_range through the bidirectional search: the same hits and
+ * statistics, sample by sample. w: scratch from orc_bidir_work_new for at
+ * least g's nodes, or NULL (then allocated for this call). */
+void orc_sample_range_bidir(const orc_graph* g, const orc_states* st, uint64_t first, uint64_t count,
+                            uint64_t seed, uint64_t phase, uint32_t* hits, orc_stats* stats, int32_t* I_out,
+                            orc_bwork* work)
+{
+    orc_bwork* w = work ? work : bwork_new(g->n);
+    int32_t* path = (int32_t*)malloc(sizeof(int32_t) * (size_t)(g->n + 1));
+    orc_stats S; memset(&S, 0, sizeof S); S.first_overflow = UINT64_MAX;
+    for (uint64_t q = 0; q < count; q++) {
+        uint64_t idx = first + q;
+        int32_t s, t;
+        orc_draw_pair(st, seed, phase, idx, &s, &t, NULL, NULL);
+        S.samples++;
+        if (I_out) I_out[q] = 0;
+        u128 sg = 0;
+        int32_t L = bidir_search(g, s, t, w, &sg);
+        if (L < 0) continue;
+        if (sg == ~(u128)0) {
+            S.overflow++;
+            if (idx < S.first_overflow) S.first_overflow = idx;
+            continue;
+        }
+        bidir_carry(g, w);
+        bidir_walk(g, t, L, draw_r(seed, phase, idx, sg), w, path);
+        for (int32_t i = 1; i < L; i++) hits[path[i]]++;
+        uint64_t I = (uint64_t)(L - 1);
+        S.reachable++;
+        S.sum_I += I;
+        S.sum_I2 += I * I;
+        if (I_out) I_out[q] = (int32_t)I;
+    }
+    if (stats) *stats = S;
+    free(path);
+    if (!work) bwork_free(w);
 }
 
 /* ------------------------------------------------------------------------- */

@@ -22,14 +22,37 @@ def oracle_objects(g, k):
     return O.Graph(g.n, g.row_ptr, g.col, g.directed), O.States(k)
 
 
-def oracle_hits(og, st, first, count, seed, phase=0, threads=None):
-    """Oracle hits and merged stats over [first, first+count)."""
+_WORK = []  # scratch of the oracle's bidirectional mode, one per thread
+
+
+def oracle_work(parts, n):
+    """`parts` bidirectional-search workspaces of at least n nodes, kept
+    across calls (allocating and touching them costs more than thousands of
+    samples on the largest graphs)."""
+    global _WORK
+    if len(_WORK) < parts or _WORK[0].n < n:
+        _WORK = []
+        _WORK = [O.BidirWork(n) for _ in range(parts)]
+    return _WORK[:parts]
+
+
+def release_oracle_work():
+    global _WORK
+    _WORK = []
+
+
+def oracle_hits(og, st, first, count, seed, phase=0, threads=None, bidir=False):
+    """Oracle hits and merged stats over [first, first+count); bidir runs the
+    oracle's bidirectional search mode (the CPU tests prove it equal to the
+    truncated BFS)."""
     threads = threads or min(16, os.cpu_count() or 1)
     parts = max(1, min(threads, count))
     bounds = [first + count * i // parts for i in range(parts + 1)]
+    work = oracle_work(parts, og.n) if bidir else [None] * parts
 
     def job(i):
-        return O.sample_range(og, st, bounds[i], bounds[i + 1] - bounds[i], seed, phase)
+        return O.sample_range(og, st, bounds[i], bounds[i + 1] - bounds[i], seed, phase, bidir=bidir,
+                              work=work[i])
 
     with ThreadPoolExecutor(parts) as ex:
         res = list(ex.map(job, range(parts)))

@@ -178,6 +178,7 @@ def test_prop7_instance():
 
 
 def test_vertex_diam_ub():
+    # (directed graphs: test_oracle_bounds.test_vertex_diam_ub_directed)
     for g in small_graphs():
         if g.directed:
             continue
