@@ -4,6 +4,9 @@
 One step = one call of the sampler over the workload's full batch of samples
 (pair draw, bidirectional shortest-path-counting BFS, canonical path, hits)
 with the graph, the pair distribution and the hit buffer resident in HBM.
+The default workload is the largest one that fits one GPU: directed R-MAT
+scale 24 (16.8M nodes, 263M arcs) with Beta(1/2, 1/2) states, 10^7 samples
+per step.
 Prints one JSON line: sampled s-t paths per second (value), GTEPS, the
 roofline of the sampler kernel (algorithmic bytes / kernel time against the
 8 TB/s HBM peak), the CPU oracle timed on the host, and the time to an
@@ -65,37 +68,57 @@ def measured_traffic(workload, samples):
     return d.get("bytes_per_launch")
 
 
-def cpu_baseline(g, k, seed, budget_s, threads):
-    """The oracle as it is, on host cores: disjoint sample windows in parallel
-    threads (ctypes releases the GIL), grown until about budget_s of work."""
+def oracle_threads():
+    """Threads for the oracle: the CPUs this process may run on, at most 16
+    (a GPU server's host share for one GPU); and the CPUs the host has."""
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    return max(1, min(16, avail)), os.cpu_count() or avail
+
+
+def cpu_baseline(og, st, seed, budget_s, threads, bidir=True, cap=5_000_000):
+    """The oracle as it is, on host cores: disjoint windows of the same sample
+    stream in parallel threads (ctypes releases the GIL), grown until about
+    budget_s of work. bidir: the oracle's bidirectional search mode (each
+    thread keeps one workspace, first touched by an untimed window of 8
+    samples), else its truncated BFS."""
     from concurrent.futures import ThreadPoolExecutor
 
     import oracle as O
-    og, st = O.Graph(g.n, g.row_ptr, g.col, g.directed), O.States(k)
+    work = [O.BidirWork(og.n) for _ in range(threads)] if bidir else [None] * threads
+    if bidir:
+        with ThreadPoolExecutor(threads) as ex:
+            list(ex.map(lambda i: O.sample_range(og, st, 10 ** 12 + 8 * i, 8, seed, 0, bidir=True, work=work[i]),
+                        range(threads)))
     per = 8
     total = 0
     elapsed = 0.0
     while True:
         t0 = time.perf_counter()
         with ThreadPoolExecutor(threads) as ex:
-            list(ex.map(lambda i: O.sample_range(og, st, total + i * per, per, seed, 0), range(threads)))
+            list(ex.map(lambda i: O.sample_range(og, st, total + i * per, per, seed, 0, bidir=bidir, work=work[i]),
+                        range(threads)))
         dt = time.perf_counter() - t0
         total += per * threads
         elapsed += dt
-        if elapsed >= budget_s or total >= 200000:
+        if elapsed >= budget_s or total >= cap:
             break
         per = max(per, int(per * min(8.0, max(1.5, (budget_s - elapsed) / max(dt, 1e-3)))))
+    del work
+    mode = "bidirectional search" if bidir else "truncated BFS"
     return {"value": total / elapsed, "unit": "samples/s", "cores": threads, "kind": "oracle",
             "sample": "first %d sample indices of the same stream (seed %d), %d threads over disjoint windows, "
-                      "%.1f s" % (total, seed, threads, elapsed)}
+                      "oracle's %s, %.1f s" % (total, seed, threads, mode, elapsed)}
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=6)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="rmat18", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="rmat24d", choices=sorted(WORKLOADS))
     ap.add_argument("--samples", type=int, default=0, help="samples per step (default: the workload's)")
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--slots", type=int, default=0)
@@ -172,6 +195,7 @@ def main():
     phases = {}
     kernel_ms = []
     pair_ms = []
+    pass_ms = [0.0, 0.0]
     t_start = time.perf_counter()
     for i in range(args.steps):
         _, st = c.sample_range(0, samples, args.seed, 0, hits=hits)
@@ -181,8 +205,9 @@ def main():
             phases[key] = phases.get(key, 0.0) + v
         kernel_ms.append(st["kernel_ms"])
         pair_ms.append(st["pair_ms"])
-        print("[bench] step %d: sampler %.1f ms, pairs %.2f ms" % (i, st["kernel_ms"], st["pair_ms"]),
-              file=sys.stderr, flush=True)
+        pass_ms = [a + b for a, b in zip(pass_ms, st["pass_ms"])]
+        print("[bench] step %d: sampler %.1f ms (passes %.1f + %.1f), pairs %.2f ms"
+              % (i, st["kernel_ms"], st["pass_ms"][0], st["pass_ms"][1], st["pair_ms"]), file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
 
@@ -223,6 +248,9 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "sampler_kernel", "kernel_ms": avg_kernel_s * 1e3,
+                     "pass_ms": [v / args.steps for v in pass_ms],
+                     "passes": ("compact slots, then per-node slots for the samples handed on"
+                                if c.get_option(P.OPT_COMPACT) == 2 else "per-node slots"),
                      "pair_kernel_ms": sum(pair_ms) / len(pair_ms),
                      "algorithmic_bytes_per_launch": b_alg},
         "hbm_gbs_measured": (traffic / avg_kernel_s / 1e9) if traffic else None,
@@ -265,12 +293,18 @@ def main():
               file=sys.stderr, flush=True)
 
     if not args.no_cpu_baseline:
-        threads = min(16, os.cpu_count() or 1)
-        out["cpu_baseline"] = cpu_baseline(g, k, args.seed, args.cpu_seconds, threads)
+        import oracle as O
+        threads, host_cpus = oracle_threads()
+        og, ost = O.Graph(g.n, g.row_ptr, g.col, g.directed), O.States(k)
+        out["cpu_baseline"] = cpu_baseline(og, ost, args.seed, args.cpu_seconds, threads)
         out["cpu_baseline"]["host"] = host_cpu_model()
-        one = cpu_baseline(g, k, args.seed, min(4.0, args.cpu_seconds / 4), 1)
+        out["cpu_baseline"]["host_cpus"] = host_cpus
+        one = cpu_baseline(og, ost, args.seed, min(4.0, args.cpu_seconds / 4), 1)
         out["cpu_baseline"]["one_thread"] = {"value": one["value"], "sample": one["sample"]}
-        print("[bench] cpu baseline: %.1f samples/s" % out["cpu_baseline"]["value"], file=sys.stderr, flush=True)
+        trunc = cpu_baseline(og, ost, args.seed, min(5.0, args.cpu_seconds / 3), threads, bidir=False)
+        out["cpu_baseline"]["truncated_bfs"] = {"value": trunc["value"], "sample": trunc["sample"]}
+        print("[bench] cpu baseline: %.1f samples/s (%d threads; truncated BFS %.1f)"
+              % (out["cpu_baseline"]["value"], threads, trunc["value"]), file=sys.stderr, flush=True)
 
     print(json.dumps(out), flush=True)
 

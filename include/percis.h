@@ -91,6 +91,11 @@ typedef struct {
     double   pair_ms;           /* device time of the pair kernel (Algorithm 2 draws) */
     uint64_t spilled;           /* samples whose visited set on a side outgrew its LDS table */
     uint64_t deferred;          /* samples a compact slot handed to the per-node slots (PERCIS_OPT_COMPACT) */
+    /* kernel_ms split by sampler pass: [0] the first pass (the compact slots
+     * when they are on, else the only pass), [1] the per-node slots' pass over
+     * the samples handed on, with the 128-bit path's launch. Captured replays
+     * report 0 for both. */
+    double   pass_ms[2];
 } percis_stats;
 
 /* Result summary of percis_estimate (Algorithm 1). */

@@ -212,6 +212,9 @@ static int graph_set_states(percis_ctx* c, GraphData& G, const uint16_t* k_in, u
     a.d_v = G.d_dv;
     a.S_v = G.d_Sv;
     const uint64_t* res = nullptr;
+    // The build rewrites the arrays a captured launch reads, whatever its
+    // outcome (all-equal states leave them zero): no capture survives it.
+    c->generation++;
     HIPCHK(c, launch_state_build(a, G.build_mem, &res, c->stream));
     uint64_t h[2] = {0, 0};
     HIPCHK(c, hipMemcpyAsync(h, res, sizeof h, hipMemcpyDeviceToHost, c->stream));
@@ -337,6 +340,63 @@ constexpr double kScratchFraction = 0.8;
 
 static int64_t bitmap_words(int64_t act) { return ((std::max<int64_t>(act, 1) + 31) / 32 + 63) / 64 * 64; }
 
+// Bytes of one per-node slot for graphs of up to `stride` nodes with arcs
+// (stride a multiple of 64): records and queues, the bitmap planes and the
+// DAG-arc list.
+static int64_t node_slot_bytes(int64_t stride, int64_t words) {
+    return stride * kSlotBytesPerNode + 8 + kBitmapPlanes * words * 4 + kArcsPerSlot * (int64_t)sizeof(DagArc);
+}
+
+// ns per-node slots laid out from p (node_slot_bytes each, all zero before use).
+static DevSlots node_slots_at(char* p, int64_t ns, int64_t stride, int64_t words) {
+    DevSlots s{};
+    s.stride = stride;
+    s.words = words;
+    const int64_t cnt = ns * stride;
+    s.rec = (NodeRec*)p; p += cnt * (int64_t)sizeof(NodeRec);
+    s.q_s = (int32_t*)p; p += cnt * 4;
+    s.q_t = (int32_t*)p; p += cnt * 4;
+    s.q_d = (int32_t*)p; p += cnt * 4;
+    s.tls = (int32_t*)p; p += ns * (stride + 2) * 4;
+    s.bm = (uint32_t*)p; p += ns * kBitmapPlanes * words * 4;
+    s.arcs = (DagArc*)p;
+    s.acap = (int32_t)kArcsPerSlot;
+    return s;
+}
+
+// Bytes of one compact slot (records by table position, whatever the graph).
+static int64_t compact_slot_bytes() {
+    const int64_t cap = sampler_table_cap(true);
+    return 2 * cap * (int64_t)sizeof(CRec) + 4 * cap * 4 + (cap + 2) * 4 + kArcsPerSlot * (int64_t)sizeof(DagArc);
+}
+
+// nc compact slots laid out from p (compact_slot_bytes each, all zero before use).
+static DevSlots compact_slots_at(char* p, int64_t nc) {
+    const int64_t cap = sampler_table_cap(true);
+    DevSlots d{};
+    d.stride = cap;
+    d.crec = (CRec*)p; p += nc * 2 * cap * (int64_t)sizeof(CRec);
+    d.q_s = (int32_t*)p; p += nc * cap * 4;
+    d.q_t = (int32_t*)p; p += nc * cap * 4;
+    d.q_d = (int32_t*)p; p += nc * 2 * cap * 4;
+    d.tls = (int32_t*)p; p += nc * (cap + 2) * 4;
+    d.arcs = (DagArc*)p;
+    d.acap = (int32_t)kArcsPerSlot;
+    return d;
+}
+
+// nw slots of the 128-bit path laid out from p (kWideBytesPerNode per node
+// each; before use the counts must be zero and the distances -1).
+static WideSlots wide_slots_at(char* p, int64_t nw, int64_t stride, unsigned long long* work) {
+    WideSlots w{};
+    w.stride = stride;
+    w.sigma = (unsigned __int128*)p; p += nw * stride * 16;
+    w.dist = (int32_t*)p; p += nw * stride * 4;
+    w.queue = (int32_t*)p;
+    w.work = work;
+    return w;
+}
+
 // The launch shape for graphs of up to `act` nodes with arcs, given the
 // context's options.
 static int pick_shape(percis_ctx* c, int64_t act, SamplerShape* out, int* occ_out) {
@@ -389,8 +449,7 @@ static int ensure_slots(percis_ctx* c, int64_t act) {
     if (rc) return rc;
     const int64_t stride = (act + 63) / 64 * 64;
     const int64_t words = bitmap_words(act);
-    const int64_t per_slot = stride * kSlotBytesPerNode + 8 + kBitmapPlanes * words * 4  // device bitmaps (spill space in LDS mode)
-                             + kArcsPerSlot * (int64_t)sizeof(DagArc);
+    const int64_t per_slot = node_slot_bytes(stride, words);
     size_t free_b = 0, total_b = 0;
     HIPCHK(c, hipMemGetInfo(&free_b, &total_b));
     const int64_t budget =
@@ -410,19 +469,7 @@ static int ensure_slots(percis_ctx* c, int64_t act) {
         (void)hipFree(mem);
         return fail(c, PERCIS_E_DEVICE, "scratch clear failed");
     }
-    char* p = (char*)mem;
-    DevSlots s{};
-    s.stride = stride;
-    s.words = words;
-    const int64_t cnt = ns * stride;
-    s.rec = (NodeRec*)p; p += cnt * (int64_t)sizeof(NodeRec);
-    s.q_s = (int32_t*)p; p += cnt * 4;
-    s.q_t = (int32_t*)p; p += cnt * 4;
-    s.q_d = (int32_t*)p; p += cnt * 4;
-    s.tls = (int32_t*)p; p += ns * (stride + 2) * 4;
-    s.bm = (uint32_t*)p; p += ns * kBitmapPlanes * words * 4;
-    s.arcs = (DagArc*)p;
-    s.acap = (int32_t)kArcsPerSlot;
+    const DevSlots s = node_slots_at((char*)mem, ns, stride, words);
     // scratch of the 128-bit path: distances -1, counts 0
     const int64_t wbudget = std::max<int64_t>(budget / 8, stride * kWideBytesPerNode);
     int64_t nw = std::max<int64_t>(1, std::min<int64_t>(kWideSlots, wbudget / (stride * kWideBytesPerNode)));
@@ -437,13 +484,7 @@ static int ensure_slots(percis_ctx* c, int64_t act) {
         (void)hipFree(mem);
         return fail(c, PERCIS_E_NOMEM, "cannot allocate the 128-bit path's scratch");
     }
-    WideSlots w{};
-    w.stride = stride;
-    char* wp = (char*)wmem;
-    w.sigma = (unsigned __int128*)wp; wp += nw * stride * 16;
-    w.dist = (int32_t*)wp; wp += nw * stride * 4;
-    w.queue = (int32_t*)wp;
-    w.work = c->d_work + 3;
+    const WideSlots w = wide_slots_at((char*)wmem, nw, stride, c->d_work + 3);
     if (launch_fill_u8(w.sigma, nw * stride * 16, c->stream) != hipSuccess ||
         launch_fill_u32((uint32_t*)w.dist, 0xFFFFFFFFu, nw * stride, c->stream) != hipSuccess) {
         (void)hipFree(mem);
@@ -470,9 +511,7 @@ static int ensure_slots(percis_ctx* c, int64_t act) {
         if (c->opt_block == 0) cs.block = kCompactBlock;
         cs.lds_bytes = sampler_table_lds(true, cs.block);
         const int cocc = sampler_occupancy(cs);
-        const int64_t cap = sampler_table_cap(true);
-        const int64_t cper = 2 * cap * (int64_t)sizeof(CRec) + 4 * cap * 4 + (cap + 2) * 4 +
-                             kArcsPerSlot * (int64_t)sizeof(DagArc);
+        const int64_t cper = compact_slot_bytes();
         int64_t nc = c->opt_slots > 0 ? c->opt_slots : (int64_t)std::max(c->cu_count, 1) * cocc;
         void* cmem = nullptr;
         e = hipErrorOutOfMemory;
@@ -488,16 +527,7 @@ static int ensure_slots(percis_ctx* c, int64_t act) {
             free_slots(c);
             return fail(c, PERCIS_E_NOMEM, "cannot allocate compact slots");
         }
-        char* cp = (char*)cmem;
-        DevSlots d{};
-        d.stride = cap;
-        d.crec = (CRec*)cp; cp += nc * 2 * cap * (int64_t)sizeof(CRec);
-        d.q_s = (int32_t*)cp; cp += nc * cap * 4;
-        d.q_t = (int32_t*)cp; cp += nc * cap * 4;
-        d.q_d = (int32_t*)cp; cp += nc * 2 * cap * 4;
-        d.tls = (int32_t*)cp; cp += nc * (cap + 2) * 4;
-        d.arcs = (DagArc*)cp;
-        d.acap = (int32_t)kArcsPerSlot;
+        const DevSlots d = compact_slots_at((char*)cmem, nc);
         c->cslot_mem = cmem;
         c->cslots = d;
         c->ncslots = (int)nc;
@@ -698,82 +728,152 @@ static int plan_tasks(percis_ctx* c, const std::vector<TaskSpec>& tasks, DevTask
     return PERCIS_OK;
 }
 
+// The device buffers one launch runs on: the context's own (ctx_bufs), or
+// views into the library's static scratch (the no-allocation entry point).
+struct LaunchBufs {
+    DevStats* stats = nullptr;            // launch-wide counters
+    unsigned long long* work = nullptr;   // [6], as percis_ctx::d_work
+    PairRec *pairs = nullptr, *wide = nullptr, *big = nullptr;  // one chunk's lists
+    DevSlots slots{};                     // per-node slots
+    SamplerShape shape{};
+    int nslots = 0;
+    DevSlots cslots{};                    // compact slots (ncslots = 0: none)
+    SamplerShape cshape{};
+    int ncslots = 0;
+    WideSlots wslots{};                   // the 128-bit path
+    int wide_slots = 0;
+};
+
+static LaunchBufs ctx_bufs(const percis_ctx* c) {
+    LaunchBufs b;
+    b.stats = c->d_stats;
+    b.work = c->d_work;
+    b.pairs = c->d_pairs;
+    b.wide = c->d_wide;
+    b.big = c->d_big;
+    b.slots = c->slots;
+    b.shape = c->shape;
+    b.nslots = c->nslots;
+    b.cslots = c->cslots;
+    b.cshape = c->cshape;
+    b.ncslots = c->ncslots;
+    b.wslots = c->wslots;
+    b.wide_slots = c->wide_slots;
+    return b;
+}
+
 // Enqueues the launch's kernels on `stream`: task clearing, then per chunk
 // the pair kernel, the sampler (compact slots first when they are on), the
 // 128-bit path. Kernels only, so that the sequence can be captured; with
 // `timed`, per-chunk events bracket the pair kernel and the rest.
-static int enqueue_tasks(percis_ctx* c, const LaunchPlan& lp, const DevTask* table, hipStream_t stream, bool timed) {
+static int enqueue_tasks(percis_ctx* c, const LaunchPlan& lp, const DevTask* table, const LaunchBufs& B,
+                         hipStream_t stream, bool timed) {
     if (timed) {
-        while (c->chunk_ev.size() < 3 * lp.nchunks) {
+        while (c->chunk_ev.size() < 4 * lp.nchunks) {
             hipEvent_t e;
             HIPCHK(c, hipEventCreate(&e));
             c->chunk_ev.push_back(e);
         }
     }
     HIPCHK(c, launch_clear_tasks(table, lp.nt, lp.max_n, stream));
-    HIPCHK(c, launch_init_stats(c->d_stats, c->d_work, stream));
+    HIPCHK(c, launch_init_stats(B.stats, B.work, stream));
     SampleLaunch a{};
     a.tasks = table;
     a.ntasks = lp.nt;
-    a.pairs = c->d_pairs;
-    a.work = c->d_work;
-    a.npairs = c->d_work + 1;
-    a.stats = c->d_stats;
+    a.pairs = B.pairs;
+    a.work = B.work;
+    a.npairs = B.work + 1;
+    a.stats = B.stats;
     // the per-node shape of this launch: wider workgroups for a small launch
     // unless the caller fixed the shape
-    SamplerShape shape = c->shape;
-    int nsl = c->nslots;
-    if (c->ncslots == 0 && c->opt_block == 0 && c->opt_slots == 0 && shape.block < kFewBlock &&
-        lp.total <= (uint64_t)c->nslots * kFewPerSlot) {
+    SamplerShape shape = B.shape;
+    int nsl = B.nslots;
+    if (B.ncslots == 0 && c->opt_block == 0 && c->opt_slots == 0 && shape.block < kFewBlock &&
+        lp.total <= (uint64_t)B.nslots * kFewPerSlot) {
         SamplerShape wide = shape;
         wide.block = kFewBlock;
         wide.lds_bytes = wide.lds_sets ? sampler_table_lds(false, kFewBlock) : 0;
         const int occ = sampler_occupancy(wide);
         if (occ > 0) {
             shape = wide;
-            nsl = (int)std::min<int64_t>(c->nslots, (int64_t)std::max(c->cu_count, 1) * occ);
+            nsl = (int)std::min<int64_t>(B.nslots, (int64_t)std::max(c->cu_count, 1) * occ);
         }
     }
     a.slots = (int)std::min<uint64_t>((uint64_t)nsl, lp.chunk);
-    a.wide = c->d_wide;
-    a.nwide = c->d_work + 2;
-    a.big = c->d_big;
-    a.nbig = c->d_work + 4;
-    a.big_work = c->d_work + 5;
+    a.wide = B.wide;
+    a.nwide = B.work + 2;
+    a.big = B.big;
+    a.nbig = B.work + 4;
+    a.big_work = B.work + 5;
     for (size_t i = 0; i < lp.nchunks; i++) {
         a.base = (uint64_t)i * lp.chunk;
         a.count = std::min<uint64_t>(lp.chunk, lp.total - a.base);
-        if (timed) HIPCHK(c, hipEventRecord(c->chunk_ev[3 * i], stream));
+        if (timed) HIPCHK(c, hipEventRecord(c->chunk_ev[4 * i], stream));
         HIPCHK(c, launch_pairs(a, stream));
-        if (timed) HIPCHK(c, hipEventRecord(c->chunk_ev[3 * i + 1], stream));
-        if (c->ncslots > 0) {
+        if (timed) HIPCHK(c, hipEventRecord(c->chunk_ev[4 * i + 1], stream));
+        if (B.ncslots > 0) {
             // compact slots first; the samples they hand on go to the per-node slots
             SampleLaunch ca = a;
-            ca.slots = (int)std::min<uint64_t>((uint64_t)c->ncslots, lp.chunk);
-            HIPCHK(c, launch_sampler(c->cslots, ca, c->cshape, stream));
+            ca.slots = (int)std::min<uint64_t>((uint64_t)B.ncslots, lp.chunk);
+            HIPCHK(c, launch_sampler(B.cslots, ca, B.cshape, stream));
+            if (timed) HIPCHK(c, hipEventRecord(c->chunk_ev[4 * i + 2], stream));
             SampleLaunch da = a;
-            da.pairs = c->d_big;
+            da.pairs = B.big;
             da.npairs = a.nbig;
             da.work = a.big_work;
-            HIPCHK(c, launch_sampler(c->slots, da, c->shape, stream));
+            da.slots = (int)std::min<uint64_t>((uint64_t)B.nslots, lp.chunk);
+            HIPCHK(c, launch_sampler(B.slots, da, B.shape, stream));
         } else {
-            HIPCHK(c, launch_sampler(c->slots, a, shape, stream));
+            HIPCHK(c, launch_sampler(B.slots, a, shape, stream));
+            if (timed) HIPCHK(c, hipEventRecord(c->chunk_ev[4 * i + 2], stream));
         }
-        HIPCHK(c, launch_wide(a, c->wslots, c->wide_slots, stream));
-        if (timed) HIPCHK(c, hipEventRecord(c->chunk_ev[3 * i + 2], stream));
+        HIPCHK(c, launch_wide(a, B.wslots, B.wide_slots, stream));
+        if (timed) HIPCHK(c, hipEventRecord(c->chunk_ev[4 * i + 3], stream));
     }
+    return PERCIS_OK;
+}
+
+// The launch-wide work counters, phase times and device times of a finished
+// launch into agg.
+static void launch_fields(const percis_ctx* c, const DevStats& hl, double ms, double pair_ms, const double* pass_ms,
+                          percis_stats* agg) {
+    agg->edges = hl.edges;
+    agg->sigma_adds = hl.sigma_adds;
+    agg->vertices_expanded = hl.vexp;
+    agg->vertices_discovered = hl.vdisc;
+    agg->spilled = hl.spills;
+    agg->deferred = hl.deferred;
+    agg->kernel_ms = ms;
+    agg->pair_ms = pair_ms;
+    if (pass_ms) {
+        agg->pass_ms[0] = pass_ms[0];
+        agg->pass_ms[1] = pass_ms[1];
+    }
+    for (int i = 0; i < 5; i++) agg->phase_ms[i] = c->wall_hz > 0 ? (double)hl.phase_ticks[i] / c->wall_hz * 1e3 : 0.0;
+}
+
+// The status of a finished launch: a broken walk, then overflow.
+static int launch_status(percis_ctx* c, const DevStats& hl, const percis_stats& agg) {
+    if (hl.walk_errors)
+        return fail(c, PERCIS_E_DEVICE,
+                    "%llu sample(s) whose path walk found no predecessor (a search invariant broke); they added no hits",
+                    (unsigned long long)hl.walk_errors);
+    if (agg.overflow)
+        return fail(c, PERCIS_E_SIGMA_OVERFLOW, "%llu sample(s) with sigma_st >= 2^64, first index %llu",
+                    (unsigned long long)agg.overflow, (unsigned long long)agg.first_overflow);
     return PERCIS_OK;
 }
 
 // Reads a finished launch's statistics (`tstats`, per task, and the
 // launch-wide counters) and checks that every task ran all its samples.
-static int collect_tasks(percis_ctx* c, const std::vector<TaskSpec>& tasks, const DevStats* tstats, double ms,
-                         double pair_ms, std::vector<percis_stats>* out, percis_stats* launch) {
+static int collect_tasks(percis_ctx* c, const std::vector<TaskSpec>& tasks, const DevStats* tstats,
+                         const DevStats* lstats, double ms, double pair_ms, const double* pass_ms,
+                         std::vector<percis_stats>* out, percis_stats* launch) {
     const int nt = (int)tasks.size();
     std::vector<DevStats> hts(nt);
     DevStats hl{};
     HIPCHK(c, hipMemcpyAsync(hts.data(), tstats, sizeof(DevStats) * nt, hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(c, hipMemcpyAsync(&hl, c->d_stats, sizeof hl, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(&hl, lstats, sizeof hl, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     percis_stats agg{};
     agg.first_overflow = ~0ull;
@@ -794,20 +894,9 @@ static int collect_tasks(percis_ctx* c, const std::vector<TaskSpec>& tasks, cons
         agg.overflow += st.overflow;
         agg.first_overflow = std::min(agg.first_overflow, st.first_overflow);
     }
-    agg.edges = hl.edges;
-    agg.sigma_adds = hl.sigma_adds;
-    agg.vertices_expanded = hl.vexp;
-    agg.vertices_discovered = hl.vdisc;
-    agg.spilled = hl.spills;
-    agg.deferred = hl.deferred;
-    agg.kernel_ms = ms;
-    agg.pair_ms = pair_ms;
-    for (int i = 0; i < 5; i++) agg.phase_ms[i] = c->wall_hz > 0 ? (double)hl.phase_ticks[i] / c->wall_hz * 1e3 : 0.0;
+    launch_fields(c, hl, ms, pair_ms, pass_ms, &agg);
     if (launch) *launch = agg;
-    if (agg.overflow)
-        return fail(c, PERCIS_E_SIGMA_OVERFLOW, "%llu sample(s) with sigma_st >= 2^64, first index %llu",
-                    (unsigned long long)agg.overflow, (unsigned long long)agg.first_overflow);
-    return PERCIS_OK;
+    return launch_status(c, hl, agg);
 }
 
 // Runs `tasks` in one persistent launch on the context's stream and waits for
@@ -827,17 +916,20 @@ int run_tasks(percis_ctx* c, const std::vector<TaskSpec>& tasks, std::vector<per
     LaunchPlan lp;
     std::vector<DevTask> ht;
     if ((rc = plan_tasks(c, tasks, c->d_tasks, c->d_task_stats, ht, &lp))) return rc;
-    if ((rc = enqueue_tasks(c, lp, c->d_tasks, c->stream, true))) return rc;
+    if ((rc = enqueue_tasks(c, lp, c->d_tasks, ctx_bufs(c), c->stream, true))) return rc;
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    double ms = 0.0, pair_ms = 0.0;
+    double ms = 0.0, pair_ms = 0.0, pass_ms[2] = {0.0, 0.0};
     for (size_t i = 0; i < lp.nchunks; i++) {
-        float a_ms = 0.f, b_ms = 0.f;
-        HIPCHK(c, hipEventElapsedTime(&a_ms, c->chunk_ev[3 * i], c->chunk_ev[3 * i + 1]));
-        HIPCHK(c, hipEventElapsedTime(&b_ms, c->chunk_ev[3 * i + 1], c->chunk_ev[3 * i + 2]));
+        float a_ms = 0.f, b_ms = 0.f, c_ms = 0.f;
+        HIPCHK(c, hipEventElapsedTime(&a_ms, c->chunk_ev[4 * i], c->chunk_ev[4 * i + 1]));
+        HIPCHK(c, hipEventElapsedTime(&b_ms, c->chunk_ev[4 * i + 1], c->chunk_ev[4 * i + 2]));
+        HIPCHK(c, hipEventElapsedTime(&c_ms, c->chunk_ev[4 * i + 2], c->chunk_ev[4 * i + 3]));
         pair_ms += a_ms;
-        ms += b_ms;
+        pass_ms[0] += b_ms;
+        pass_ms[1] += c_ms;
+        ms += b_ms + c_ms;
     }
-    return collect_tasks(c, tasks, c->d_task_stats, ms, pair_ms, out, launch);
+    return collect_tasks(c, tasks, c->d_task_stats, c->d_stats, ms, pair_ms, pass_ms, out, launch);
 }
 
 GraphData* get_graph(percis_ctx* c, int32_t id) {
@@ -1190,7 +1282,7 @@ int percis_batch_capture(percis_ctx* c, int32_t ntasks, const percis_task* tasks
         batch_free(b);
         return fail(c, PERCIS_E_DEVICE, "cannot begin a stream capture");
     }
-    rc = enqueue_tasks(c, lp, b->d_tasks, c->cap_stream, false);
+    rc = enqueue_tasks(c, lp, b->d_tasks, ctx_bufs(c), c->cap_stream, false);
     hipGraph_t graph = nullptr;
     const hipError_t e = hipStreamEndCapture(c->cap_stream, &graph);
     if (rc == PERCIS_OK && e != hipSuccess) rc = fail(c, PERCIS_E_DEVICE, "stream capture: %s", hipGetErrorString(e));
@@ -1214,6 +1306,12 @@ int percis_batch_replay(percis_batch* b, percis_stats* launch_stats) {
     percis_ctx* c = b->ctx;
     if (b->generation != c->generation)
         return fail(c, PERCIS_E_STATE, "graphs, states, options or buffers changed since the capture; capture again");
+    for (size_t i = 0; i < b->tasks.size(); i++) {
+        const GraphData* G = get_graph(c, b->tasks[i].graph);
+        if (!G || !G->has_graph || !G->has_states || !G->states_on_device)
+            return fail(c, PERCIS_E_STATE, "task %zu: graph %d has no states; set them and capture again", i,
+                        b->tasks[i].graph);
+    }
     int rc = set_device(c);
     if (rc) return rc;
     HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -1224,7 +1322,7 @@ int percis_batch_replay(percis_batch* b, percis_stats* launch_stats) {
     float ms = 0.f;
     HIPCHK(c, hipEventElapsedTime(&ms, c->ev0, c->ev1));
     std::vector<percis_stats> ts;
-    rc = collect_tasks(c, b->tasks, b->d_task_stats, ms, 0.0, &ts, launch_stats);
+    rc = collect_tasks(c, b->tasks, b->d_task_stats, c->d_stats, ms, 0.0, nullptr, &ts, launch_stats);
     if (rc != PERCIS_OK && rc != PERCIS_E_SIGMA_OVERFLOW) return rc;
     for (size_t i = 0; i < b->task_stats.size() && i < ts.size(); i++)
         if (b->task_stats[i]) *b->task_stats[i] = ts[i];

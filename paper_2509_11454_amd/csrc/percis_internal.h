@@ -91,6 +91,7 @@ struct DevStats {
     unsigned long long spills;           // samples whose visited set outgrew an LDS table
     unsigned long long deferred;         // samples a compact slot handed to the per-node slots
     unsigned long long phase_ticks[5];   // summed over workgroups, wall-clock ticks
+    unsigned long long walk_errors;      // samples whose walk found no predecessor (launch-wide only)
 };
 
 // One task of a launch: samples first .. first+count-1 of stream

@@ -414,6 +414,7 @@ struct SampleShared {
     unsigned long long phase_ticks[5];  // start, BFS, meeting + DAG, walk (+ next pair), clearing
     unsigned long long spills;          // samples of this workgroup that spilled a side
     unsigned long long deferred;        // samples this compact workgroup handed on
+    unsigned long long walk_errs;       // samples whose walk found no predecessor at some step
     // per-sample statistics of one task, summed here by thread 0 and added to
     // the task's counters when the workgroup moves to another task
     unsigned long long acc_samples, acc_reach, acc_sum_I, acc_sum_I2, acc_ovf, acc_first;
@@ -1277,11 +1278,12 @@ __device__ __forceinline__ void run_sample(const GGraph& g, const GSlots& sl, in
                 if (sel < 0) { err = 1; break; }
                 w = sel;
                 if (lane == 0) {
+                    // the path is kept (the meeting layer's queue is free by
+                    // now) and credited only once the walk reaches s
                     if (dbg) {
                         if (p < dbg_cap) dbg->path[p] = w;
                     } else {
-                        __hip_atomic_fetch_add(gptr(T.hits) + g.orig[w], 1u, __ATOMIC_RELAXED,
-                                               __HIP_MEMORY_SCOPE_AGENT);
+                        __hip_atomic_store(q_d + p, w, __ATOMIC_RELAXED, WGS);
                     }
                     cn.V++;
                 }
@@ -1293,6 +1295,11 @@ __device__ __forceinline__ void run_sample(const GGraph& g, const GSlots& sl, in
     // workgroup claims it after its walk)
     if (next && wid == (BSZ >= 128 ? 1 : 0)) claim_next(*next, npairs, sh);
     __syncthreads();
+    // ---- one hit to each internal node of a path the walk completed
+    if (!dbg && sh.status == 1 && !sh.ovf && !sh.walk_err) {
+        for (int p = 1 + tid; p < L; p += BSZ)
+            __hip_atomic_fetch_add(gptr(T.hits) + g.orig[ldq(q_d + p)], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
     phase_mark(3);
 
     // ---- per-sample statistics
@@ -1315,8 +1322,9 @@ __device__ __forceinline__ void run_sample(const GGraph& g, const GSlots& sl, in
                     const unsigned long long at = atomicAdd(next->nwide, 1ull);
                     next->wide[at] = PairRec{q_rel, s, t, task};
                 } else if (sh.walk_err) {
-                    sh.acc_ovf++;
-                    sh.acc_first = idx < sh.acc_first ? idx : sh.acc_first;
+                    // no predecessor at some step: a broken invariant of the
+                    // search; the sample adds no hits and fails the call
+                    sh.walk_errs++;
                 } else {
                     const unsigned long long I = (unsigned long long)(L - 1);
                     sh.acc_reach++;
@@ -1413,6 +1421,7 @@ __global__ __launch_bounds__(BSZ) SAMPLER_OCCUPANCY void sampler_kernel(DevSlots
         for (int i = 0; i < 5; i++) sh.phase_ticks[i] = 0;
         sh.spills = 0;
         sh.deferred = 0;
+        sh.walk_errs = 0;
         sh.acc_task = -1;
         flush_task_stats(sh, L);
     }
@@ -1441,6 +1450,7 @@ __global__ __launch_bounds__(BSZ) SAMPLER_OCCUPANCY void sampler_kernel(DevSlots
         for (int i = 0; i < 5; i++) atomicAdd(&L.stats->phase_ticks[i], sh.phase_ticks[i]);
         atomicAdd(&L.stats->spills, sh.spills);
         if (CMP) atomicAdd(&L.stats->deferred, sh.deferred);
+        if (sh.walk_errs) atomicAdd(&L.stats->walk_errors, sh.walk_errs);
     }
 }
 
@@ -1657,7 +1667,7 @@ __device__ int32_t wide_bfs(const DevGraph& g, int32_t* dist, u128* sig, int32_t
 // Canonical walk with 128-bit weights (one thread), from t down to s: adds a
 // hit to every internal node when hits is given, writes path[L] = t ..
 // path[0] = s when path is given (cap entries); false if a step finds no
-// predecessor.
+// predecessor (callers check a walk without hits first).
 __device__ bool wide_walk(const DevGraph& g, const int32_t* dist, const u128* sig, int32_t t, int32_t L, u128 r,
                           uint32_t* hits, int32_t* path, int32_t cap) {
     int32_t w = t;
@@ -1711,14 +1721,16 @@ __global__ __launch_bounds__(WB) void wide_kernel(SampleLaunch L, WideSlots W) {
                 atomicMin(&st->first_overflow, (unsigned long long)idx);
             } else {
                 const u128 r = draw_r_wide(T.seed, T.phase, idx, sg);
-                if (wide_walk(T.g, dist, sig, rec.t, Ld, r, T.hits, nullptr, 0)) {
+                // the walk is checked to reach s before it is walked again
+                // with hits (the same path: it depends on r and the counts)
+                if (wide_walk(T.g, dist, sig, rec.t, Ld, r, nullptr, nullptr, 0)) {
+                    (void)wide_walk(T.g, dist, sig, rec.t, Ld, r, T.hits, nullptr, 0);
                     const unsigned long long I = (unsigned long long)(Ld - 1);
                     atomicAdd(&st->reachable, 1ull);
                     atomicAdd(&st->sum_I, I);
                     atomicAdd(&st->sum_I2, I * I);
                 } else {
-                    atomicAdd(&st->overflow, 1ull);
-                    atomicMin(&st->first_overflow, (unsigned long long)idx);
+                    atomicAdd(&L.stats->walk_errors, 1ull);
                 }
             }
         }
@@ -1748,7 +1760,7 @@ __global__ void init_stats_kernel(DevStats* st, unsigned long long* work) {
     if (threadIdx.x == 0) {
         st->samples = st->reachable = st->sum_I = st->sum_I2 = st->overflow = 0;
         st->first_overflow = ~0ull;
-        st->edges = st->sigma_adds = st->vexp = st->vdisc = st->spills = st->deferred = 0;
+        st->edges = st->sigma_adds = st->vexp = st->vdisc = st->spills = st->deferred = st->walk_errors = 0;
         for (int i = 0; i < 5; i++) st->phase_ticks[i] = 0;
         *work = 0;
     }
@@ -1762,7 +1774,7 @@ __global__ void clear_tasks_kernel(const DevTask* tasks, int ntasks) {
         DevStats* st = T.stats;
         st->samples = st->reachable = st->sum_I = st->sum_I2 = st->overflow = 0;
         st->first_overflow = ~0ull;
-        st->edges = st->sigma_adds = st->vexp = st->vdisc = st->spills = st->deferred = 0;
+        st->edges = st->sigma_adds = st->vexp = st->vdisc = st->spills = st->deferred = st->walk_errors = 0;
         for (int i = 0; i < 5; i++) st->phase_ticks[i] = 0;
     }
     if (T.clear_hits) {

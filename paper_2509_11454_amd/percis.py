@@ -31,7 +31,8 @@ class Stats(C.Structure):
                 ("sum_I2", C.c_uint64), ("overflow", C.c_uint64), ("first_overflow", C.c_uint64),
                 ("edges", C.c_uint64), ("sigma_adds", C.c_uint64), ("vertices_expanded", C.c_uint64),
                 ("vertices_discovered", C.c_uint64), ("kernel_ms", C.c_double), ("phase_ms", C.c_double * 5),
-                ("pair_ms", C.c_double), ("spilled", C.c_uint64), ("deferred", C.c_uint64)]
+                ("pair_ms", C.c_double), ("spilled", C.c_uint64), ("deferred", C.c_uint64),
+                ("pass_ms", C.c_double * 2)]
 
     PHASES = ("start", "bfs", "dag", "walk", "clear")
 
@@ -40,6 +41,8 @@ class Stats(C.Structure):
         for k, t in self._fields_:
             if k == "phase_ms":
                 d[k] = dict(zip(self.PHASES, [float(x) for x in self.phase_ms]))
+            elif k == "pass_ms":
+                d[k] = [float(x) for x in self.pass_ms]
             else:
                 d[k] = float(getattr(self, k)) if t is C.c_double else int(getattr(self, k))
         return d
@@ -211,11 +214,15 @@ class Context:
         if hits is None:
             hits = torch.zeros(self.n, dtype=torch.int32, device="cuda:%d" % self.device)
         if isinstance(hits, torch.Tensor):
-            assert hits.is_cuda and hits.dtype == torch.int32 and hits.numel() >= self.n
+            if hits.dtype != torch.int32 or hits.numel() < self.n:
+                raise ValueError("hits must be an int32 tensor of at least %d entries" % self.n)
+            if not hits.is_cuda or not hits.is_contiguous():
+                raise ValueError("hits must be a contiguous device tensor")
             rc = _lib.percis_sample_range(self._h, int(first), int(count), int(seed), int(phase),
                                           C.c_void_p(hits.data_ptr()), flags | DEVICE_PTRS, C.byref(st))
         else:
-            assert hits.dtype == np.uint32 and hits.size >= self.n and hits.flags.c_contiguous
+            if hits.dtype != np.uint32 or hits.size < self.n or not hits.flags.c_contiguous:
+                raise ValueError("hits must be a contiguous uint32 array of at least %d entries" % self.n)
             rc = _lib.percis_sample_range(self._h, int(first), int(count), int(seed), int(phase),
                                           _np_ptr(hits), flags, C.byref(st))
         self._check(rc, allow=(E_SIGMA_OVERFLOW,) if allow_overflow else ())
@@ -293,17 +300,31 @@ class Context:
         self._check(_lib.percis_graph_info(self._h, int(graph), C.byref(n), C.byref(m), C.byref(na)))
         return int(n.value), int(m.value), int(na.value)
 
-    def sample_tasks(self, tasks, allow_overflow=False):
-        """tasks: list of dicts with graph, first, count, seed, phase, hits
-        (int32 device tensor), accumulate. Returns (per-task stats, launch stats)."""
+    def _task_table(self, tasks):
+        """The C task table of `tasks` and their stats records. Each task's
+        hits must be an int32 device tensor of at least its graph's node
+        count: the library receives a bare pointer and writes that many
+        entries (checked before any launch)."""
         arr = (Task * len(tasks))()
         sts = [Stats() for _ in tasks]
         for i, t in enumerate(tasks):
             h = t["hits"]
-            assert isinstance(h, torch.Tensor) and h.is_cuda and h.dtype == torch.int32
+            if not isinstance(h, torch.Tensor) or h.dtype != torch.int32:
+                raise TypeError("task %d: hits must be an int32 torch tensor" % i)
+            n = self.graph_info(int(t["graph"]))[0]
+            if h.numel() < n:
+                raise ValueError("task %d: hits holds %d entries, graph %d has %d nodes" % (i, h.numel(), t["graph"], n))
+            if not h.is_cuda or not h.is_contiguous():
+                raise ValueError("task %d: hits must be a contiguous device tensor" % i)
             arr[i] = Task(int(t["graph"]), int(t.get("phase", 0)), int(t.get("first", 0)), int(t["count"]),
                           int(t["seed"]), C.c_void_p(h.data_ptr()), ACCUMULATE if t.get("accumulate") else 0,
                           C.pointer(sts[i]))
+        return arr, sts
+
+    def sample_tasks(self, tasks, allow_overflow=False):
+        """tasks: list of dicts with graph, first, count, seed, phase, hits
+        (int32 device tensor), accumulate. Returns (per-task stats, launch stats)."""
+        arr, sts = self._task_table(tasks)
         ls = Stats()
         rc = _lib.percis_sample_tasks(self._h, len(tasks), arr, C.byref(ls))
         self._check(rc, allow=(E_SIGMA_OVERFLOW,) if allow_overflow else ())
@@ -312,14 +333,7 @@ class Context:
     def capture_batch(self, tasks):
         """The launch of sample_tasks(tasks) captured as a HIP graph; returns a
         Batch whose replay() re-runs it."""
-        arr = (Task * len(tasks))()
-        sts = [Stats() for _ in tasks]
-        for i, t in enumerate(tasks):
-            h = t["hits"]
-            assert isinstance(h, torch.Tensor) and h.is_cuda and h.dtype == torch.int32
-            arr[i] = Task(int(t["graph"]), int(t.get("phase", 0)), int(t.get("first", 0)), int(t["count"]),
-                          int(t["seed"]), C.c_void_p(h.data_ptr()), ACCUMULATE if t.get("accumulate") else 0,
-                          C.pointer(sts[i]))
+        arr, sts = self._task_table(tasks)
         b = _P()
         self._check(_lib.percis_batch_capture(self._h, len(tasks), arr, C.byref(b)))
         return Batch(self, b, sts, [t["hits"] for t in tasks])

@@ -172,3 +172,25 @@ def test_batch_capture_needs_a_device(P):
     rc = lib.percis_batch_capture(c._h, 1, arr, C.byref(h))
     assert rc == P.E_STATE and not h.value
     lib.percis_batch_destroy(None)   # a null batch is accepted
+
+
+def test_task_hits_checked_before_any_launch(P):
+    """A task's hits tensor must hold its graph's node count: the library
+    gets a bare pointer and would write past a shorter buffer. The binding
+    rejects it (and a host tensor) before calling into the library."""
+    import torch
+    c = ctx(P)
+    g, k = W.workload_er1000()
+    c.load_csr(g.n, g.row_ptr, g.col)
+    c.set_states(k)
+    small = torch.zeros(g.n - 1, dtype=torch.int32)
+    task = dict(graph=0, first=0, count=10, seed=1, hits=small)
+    for call in (c.sample_tasks, c.capture_batch):
+        with pytest.raises(ValueError, match="holds %d entries" % (g.n - 1)):
+            call([task])
+        with pytest.raises(ValueError, match="device tensor"):
+            call([dict(task, hits=torch.zeros(g.n, dtype=torch.int32))])
+        with pytest.raises(TypeError):
+            call([dict(task, hits=torch.zeros(g.n, dtype=torch.int64))])
+    with pytest.raises(ValueError):
+        c.sample_range(0, 10, 1, hits=np.zeros(g.n - 1, np.uint32))

@@ -91,3 +91,30 @@ def test_capture_is_invalidated_by_new_states():
     torch.cuda.synchronize()
     assert [p["sum_I"] for p in per] == [p["sum_I"] for p in eager]
     b2.close()
+
+
+def test_capture_is_invalidated_by_degenerate_states():
+    """All-equal states are rejected (the pair distribution is undefined),
+    but their build has already rewritten the arrays the capture reads: the
+    replay must refuse to run, and sampling the graph must too, until new
+    states are set."""
+    from paper_2509_11454_amd import percis as P
+    c, tasks, hits = build(P, 0)
+    b = c.capture_batch(tasks[:2])
+    b.replay()
+    with pytest.raises(P.PercisError) as e:
+        c.set_states(np.full(1000, 1234, np.uint16))
+    assert e.value.status == P.E_DEGENERATE
+    with pytest.raises(P.PercisError) as e:
+        b.replay()
+    assert e.value.status == P.E_STATE
+    with pytest.raises(P.PercisError) as e:
+        c.sample_tasks(tasks[:1])
+    assert e.value.status == P.E_STATE
+    b.close()
+    c.set_states(W.uniform_states(1000, np.random.default_rng(4)))
+    b2 = c.capture_batch(tasks[:2])
+    per, _ = b2.replay()
+    eager, _ = c.sample_tasks(tasks[:2])
+    assert [p["sum_I"] for p in per] == [p["sum_I"] for p in eager]
+    b2.close()
