@@ -169,6 +169,28 @@ int percis_sample_range(percis_ctx* ctx, uint64_t first, uint64_t count, uint64_
 int percis_sample(percis_ctx* ctx, uint64_t n_samples, uint64_t seed, uint32_t* hits, uint32_t flags,
                   percis_stats* st);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * samples, hits and statistics as percis_sample_range on the context's graph
+ * 0, with no hipMalloc, hipFree or other allocation in the call. Every
+ * scratch buffer of the launch lies in a static device array of the library,
+ * 256 MiB per GPU (allocated once when the library is first used on a GPU,
+ * held until the process ends): the pair lists of chunks of at most 2^16
+ * samples, the visited-set slots and one slot of the 128-bit path, laid out
+ * anew for each call and cleared by kernels first. Requirements: the graph
+ * and its states were set with percis_load_csr and percis_set_states (those
+ * calls allocate); hits is device memory (flags must contain
+ * PERCIS_DEVICE_PTRS; PERCIS_ACCUMULATE is allowed). Returns
+ * PERCIS_E_TOO_LARGE when the graph has more nodes with arcs than one
+ * per-node slot and one 128-bit slot can hold in the array (about 3.6
+ * million), PERCIS_E_INVAL without PERCIS_DEVICE_PTRS, PERCIS_E_STATE before
+ * a graph with states. All calls on one GPU share the array, whatever their
+ * context: calls that overlap on one GPU (other host threads, other streams)
+ * race and give wrong results. kernel_ms covers the whole call (pair draws
+ * included); pair_ms and pass_ms are 0. */
+int percis_sample_range_noalloc(percis_ctx* ctx, uint64_t first, uint64_t count, uint64_t seed, uint32_t phase,
+                                uint32_t* hits, uint32_t flags, percis_stats* st);
+
 /* Algorithm 1 (PercIS): VertexDiamUB, l1 samples in phase 1, the bounds of
  * Propositions 2 and 3 and the sample size of Theorem 1 (with the constants
  * of Alg. 1), l samples in phase 2, and p_out[v] = d_v h_v / l (host array of

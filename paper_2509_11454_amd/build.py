@@ -11,7 +11,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIBDIR = os.path.join(HERE, "lib")
 LIB = os.path.join(LIBDIR, "libpercis.so")
-SOURCES = ["percis_kernels.hip", "percis_exact.hip", "percis_setup.hip", "percis_api.cpp", "percis_server.cpp"]
+SOURCES = ["percis_kernels.hip", "percis_exact.hip", "percis_setup.hip", "percis_noalloc.hip", "percis_api.cpp",
+           "percis_server.cpp"]
 ARCH = os.environ.get("PERCIS_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [

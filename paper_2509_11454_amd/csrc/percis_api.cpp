@@ -319,6 +319,7 @@ constexpr int64_t kArcsPerSlot = 4096;  // DAG arcs a sample may record for its 
 // 24 directed, 10^7 samples: 2^22 8.66M, 2^23 8.86M, 2^24 9.11M samples/s.
 constexpr uint64_t kPairChunk = 1ull << 24;
 constexpr uint64_t kMaxPairChunk = 1ull << 30;  // list entries index their chunk in 32 bits
+constexpr uint64_t kNoAllocChunk = 1ull << 16;  // samples per chunk of a no-allocation call
 constexpr int64_t kWideSlots = 16;           // workgroups of the 128-bit path
 constexpr int64_t kWideBytesPerNode = 4 + 16 + 4;
 constexpr int kDeferBlock = 512;             // per-node slots' block while compact slots are on
@@ -1065,6 +1066,13 @@ int percis_create(int device, void* hip_stream, percis_ctx** out) {
             percis_destroy(c);
             return PERCIS_E_DEVICE;
         }
+        // the no-allocation call's scratch: its address on this device, once
+        // (if the lookup fails here, that call repeats it and reports why)
+        if (noalloc_scratch(c, &c->noalloc) != PERCIS_OK) {
+            (void)hipGetLastError();
+            c->noalloc = nullptr;
+            c->err.clear();
+        }
     }
     c->graphs.push_back(new (std::nothrow) GraphData());
     if (!c->graphs[0]) {
@@ -1192,6 +1200,144 @@ int percis_sample_range(percis_ctx* c, uint64_t first, uint64_t count, uint64_t 
         HIPCHK(c, hipStreamSynchronize(c->stream));
     }
     return rc;
+}
+
+// percis_sample_range without allocating: every buffer of the launch is a
+// view into the library's static device scratch (kNoAllocScratchBytes per
+// GPU), laid out for this call's graph: the task table and counters, the
+// pair lists of one chunk of at most kNoAllocChunk samples, one slot of the
+// 128-bit path, compact slots when the per-node slots cannot fill the device,
+// and per-node slots (at least one) for the rest. The used part is cleared by
+// fill kernels first; the kernels are those of percis_sample_range.
+int percis_sample_range_noalloc(percis_ctx* c, uint64_t first, uint64_t count, uint64_t seed, uint32_t phase,
+                                uint32_t* hits, uint32_t flags, percis_stats* st) {
+    if (!c) return PERCIS_E_INVAL;
+    if (c->host_only) return fail(c, PERCIS_E_STATE, "host-only context: no device work possible");
+    if (!hits) return fail(c, PERCIS_E_INVAL, "null hits");
+    if (!(flags & PERCIS_DEVICE_PTRS))
+        return fail(c, PERCIS_E_INVAL, "hits must be device memory (PERCIS_DEVICE_PTRS): host hits need a staging buffer");
+    if (flags & ~(uint32_t)(PERCIS_DEVICE_PTRS | PERCIS_ACCUMULATE)) return fail(c, PERCIS_E_INVAL, "unknown flags");
+    if (count >= (1ull << 32)) return fail(c, PERCIS_E_TOO_LARGE, "at most 2^32 - 1 samples per call");
+    GraphData& G = *c->graphs[0];
+    if (!G.has_graph || !G.has_states || !G.graph_on_device || !G.states_on_device)
+        return fail(c, PERCIS_E_STATE, "load a graph and set its states first (those calls allocate, this one does not)");
+    int rc = set_device(c);
+    if (rc) return rc;
+    if (!c->noalloc && (rc = noalloc_scratch(c, &c->noalloc))) return rc;
+    char* base = (char*)c->noalloc;
+
+    // layout
+    const int64_t act = std::max<int64_t>(G.n_act, 1);
+    const int64_t stride = (act + 63) / 64 * 64;
+    const int64_t words = bitmap_words(act);
+    const int64_t per_node = node_slot_bytes(stride, words);
+    const int64_t wide_one = stride * kWideBytesPerNode;
+    const uint64_t chunk = std::max<uint64_t>(1, std::min<uint64_t>(count, kNoAllocChunk));
+    int64_t off = 0;
+    auto take = [&](int64_t bytes) {
+        const int64_t at = off;
+        off = (off + bytes + 255) / 256 * 256;
+        return at;
+    };
+    const int64_t o_task = take(sizeof(DevTask)), o_tstats = take(sizeof(DevStats)), o_stats = take(sizeof(DevStats));
+    const int64_t o_work = take(6 * sizeof(unsigned long long));
+    const int64_t o_pairs = take((int64_t)chunk * sizeof(PairRec)), o_wide = take((int64_t)chunk * sizeof(PairRec));
+    const int64_t o_big = take((int64_t)chunk * sizeof(PairRec));
+    const int64_t o_clear = off;  // from here on the scratch must be cleared before use
+    const int64_t o_wslot = take(wide_one);
+    const int64_t avail = kNoAllocScratchBytes - off;
+    if (avail < per_node) {
+        const int64_t lim = (kNoAllocScratchBytes - off - kArcsPerSlot * (int64_t)sizeof(DagArc)) /
+                            (kSlotBytesPerNode + kWideBytesPerNode + 1);
+        return fail(c, PERCIS_E_TOO_LARGE,
+                    "the graph has %d nodes with arcs; the no-allocation call's %lld MiB scratch holds graphs of "
+                    "up to about %lld",
+                    G.n_act, (long long)(kNoAllocScratchBytes >> 20), (long long)lim);
+    }
+    SamplerShape sh{};
+    int occ = 0;
+    if ((rc = pick_shape(c, act, &sh, &occ))) return rc;
+    const int64_t cu = std::max(c->cu_count, 1);
+    const int64_t want = c->opt_slots > 0 ? c->opt_slots : cu * occ;
+    LaunchBufs B;
+    B.shape = sh;
+    int64_t np = std::min<int64_t>(want, avail / per_node), nc = 0;
+    if (sh.lds_sets && (c->opt_compact == 2 || (c->opt_compact == 0 && np < want))) {
+        SamplerShape cs = sh, big = sh;
+        cs.compact = true;
+        if (c->opt_block == 0) cs.block = kCompactBlock;
+        cs.lds_bytes = sampler_table_lds(true, cs.block);
+        const int cocc = sampler_occupancy(cs);
+        big.block = c->opt_defer_block > 0 ? (int)c->opt_defer_block : kDeferBlock;
+        big.lds_bytes = sampler_table_lds(false, big.block);
+        const int bocc = sampler_occupancy(big);
+        if (bocc <= 0) big = sh;
+        const int64_t cper = compact_slot_bytes();
+        // one per-node slot at least; the compact slots take the rest up to
+        // the device's fill, more per-node slots what is left after them
+        nc = cocc > 0 ? std::min<int64_t>(c->opt_slots > 0 ? c->opt_slots : cu * cocc, (avail - per_node) / cper) : 0;
+        if (nc >= 1) {
+            np = std::max<int64_t>(1, std::min<int64_t>(cu * std::max(bocc, 1), (avail - nc * cper) / per_node));
+            B.cshape = cs;
+            B.shape = big;
+        } else {
+            nc = 0;
+        }
+    }
+    const int64_t o_nodes = take(np * per_node);
+    const int64_t o_cslots = take(nc * compact_slot_bytes());
+    if (off > kNoAllocScratchBytes) return fail(c, PERCIS_E_DEVICE, "no-allocation scratch layout overflow");
+    B.stats = (DevStats*)(base + o_stats);
+    B.work = (unsigned long long*)(base + o_work);
+    B.pairs = (PairRec*)(base + o_pairs);
+    B.wide = (PairRec*)(base + o_wide);
+    B.big = (PairRec*)(base + o_big);
+    B.slots = node_slots_at(base + o_nodes, np, stride, words);
+    B.nslots = (int)np;
+    if (nc > 0) B.cslots = compact_slots_at(base + o_cslots, nc);
+    B.ncslots = (int)nc;
+    B.wslots = wide_slots_at(base + o_wslot, 1, stride, B.work + 3);
+    B.wide_slots = 1;
+
+    // the task, then a cleared scratch (the slots' between-sample state)
+    DevTask t{};
+    t.g = dev_graph(G);
+    t.cdf = dev_cdf(G);
+    t.first = first;
+    t.count = count;
+    t.seed = seed;
+    t.phase = phase;
+    t.hits = hits;
+    t.stats = (DevStats*)(base + o_tstats);
+    t.offset = 0;
+    t.clear_hits = (flags & PERCIS_ACCUMULATE) ? 0u : 1u;
+    DevTask* table = (DevTask*)(base + o_task);
+    HIPCHK(c, hipMemcpyAsync(table, &t, sizeof t, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, launch_fill_u8(base + o_clear, off - o_clear, c->stream));
+    HIPCHK(c, launch_fill_u32((uint32_t*)B.wslots.dist, 0xFFFFFFFFu, stride, c->stream));
+    LaunchPlan lp;
+    lp.nt = 1;
+    lp.max_n = G.n;
+    lp.total = count;
+    lp.chunk = chunk;
+    lp.nchunks = (size_t)((count + chunk - 1) / chunk);
+    HIPCHK(c, hipEventRecord(c->ev0, c->stream));
+    if ((rc = enqueue_tasks(c, lp, table, B, c->stream, false))) return rc;
+    HIPCHK(c, hipEventRecord(c->ev1, c->stream));
+    DevStats ht{}, hl{};
+    HIPCHK(c, hipMemcpyAsync(&ht, t.stats, sizeof ht, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(&hl, B.stats, sizeof hl, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    float ms = 0.f;
+    HIPCHK(c, hipEventElapsedTime(&ms, c->ev0, c->ev1));
+    percis_stats agg;
+    stats_from_dev(ht, &agg);
+    launch_fields(c, hl, ms, 0.0, nullptr, &agg);
+    if (st) *st = agg;
+    if (agg.samples != count)
+        return fail(c, PERCIS_E_DEVICE, "sampler processed %llu of %llu samples", (unsigned long long)agg.samples,
+                    (unsigned long long)count);
+    return launch_status(c, hl, agg);
 }
 
 int percis_sample(percis_ctx* c, uint64_t n_samples, uint64_t seed, uint32_t* hits, uint32_t flags, percis_stats* st) {

@@ -100,11 +100,19 @@ struct percis_ctx {
 
     int64_t opt_slots = 0, opt_scratch_mb = 0, opt_block = 0, opt_bitmaps = 0, opt_compact = 0, opt_defer_block = 0;
     int64_t opt_pair_chunk = 0;
+    void* noalloc = nullptr;               // this device's copy of the no-allocation scratch
 };
 
 namespace percis {
 
 int fail(percis_ctx* c, int code, const char* fmt, ...);
+
+// Size of the static device scratch of percis_sample_range_noalloc (one copy
+// per GPU the library runs on, held until the process ends).
+constexpr int64_t kNoAllocScratchBytes = 256ll << 20;
+// Device address of the context's device's copy of that scratch, looked up
+// once per device (percis_create does it).
+int noalloc_scratch(percis_ctx* c, void** out);
 
 #define HIPCHK(c, expr)                                                                            \
     do {                                                                                           \

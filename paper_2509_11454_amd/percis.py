@@ -83,6 +83,8 @@ _SIGS = {
     "percis_sample_range": (C.c_int, [_P, C.c_uint64, C.c_uint64, C.c_uint64, C.c_uint32, _P, C.c_uint32,
                                       C.POINTER(Stats)]),
     "percis_sample": (C.c_int, [_P, C.c_uint64, C.c_uint64, _P, C.c_uint32, C.POINTER(Stats)]),
+    "percis_sample_range_noalloc": (C.c_int, [_P, C.c_uint64, C.c_uint64, C.c_uint64, C.c_uint32, _P, C.c_uint32,
+                                              C.POINTER(Stats)]),
     "percis_estimate": (C.c_int, [_P, C.c_double, C.c_double, C.c_uint64, _P, C.POINTER(EstimateInfo)]),
     "percis_set_vertex_diameter": (C.c_int, [_P, C.c_int64]),
     "percis_debug_path": (C.c_int, [_P, C.c_int32, C.c_int32, C.c_uint64, _P, C.c_int32,
@@ -227,6 +229,20 @@ class Context:
                                           _np_ptr(hits), flags, C.byref(st))
         self._check(rc, allow=(E_SIGMA_OVERFLOW,) if allow_overflow else ())
         return hits, st.to_dict()
+
+    def sample_range_noalloc(self, first, count, seed, phase, hits, accumulate=False, allow_overflow=False):
+        """percis_sample_range_noalloc: hits is an int32 device tensor of at
+        least n entries; returns the stats dict."""
+        if not isinstance(hits, torch.Tensor) or hits.dtype != torch.int32 or hits.numel() < self.n:
+            raise ValueError("hits must be an int32 tensor of at least %d entries" % self.n)
+        if not hits.is_cuda or not hits.is_contiguous():
+            raise ValueError("hits must be a contiguous device tensor")
+        st = Stats()
+        flags = DEVICE_PTRS | (ACCUMULATE if accumulate else 0)
+        rc = _lib.percis_sample_range_noalloc(self._h, int(first), int(count), int(seed), int(phase),
+                                              C.c_void_p(hits.data_ptr()), flags, C.byref(st))
+        self._check(rc, allow=(E_SIGMA_OVERFLOW,) if allow_overflow else ())
+        return st.to_dict()
 
     def sample(self, n_samples, seed, hits=None):
         return self.sample_range(0, n_samples, seed, 0, hits)
