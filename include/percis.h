@@ -370,15 +370,23 @@ int percis_autotune(percis_ctx* ctx, int32_t graph, uint64_t probe_samples, uint
 
 /* ---- serving: continuous batching of centrality queries ----
  * A server runs Algorithm 1 queries (graph, eps, delta, seed) over the graphs
- * resident in its context. Queries wait in arrival order until their hit
- * buffer (4 bytes per node, device memory owned by the server) fits in
- * memory_budget_bytes; admitted queries advance in chunks of at most
- * chunk_samples samples, and each percis_server_step is one launch that
- * carries a chunk of every active query, up to step_samples samples in all,
- * so queries of different graphs share the device and a query submitted
- * while others run joins at the next step. A query's result is the same
- * alone or in any mix, and equals percis_graph_estimate with the same
- * arguments. The server is used from one host thread at a time. */
+ * resident in its context. percis_server_create allocates one device pool of
+ * memory_budget_bytes (rounded down to 256 bytes); queries wait in arrival
+ * order until their hit buffer (4 bytes per node, rounded up to 256) fits in
+ * it (first fit, no further allocation per query). A launch of at most
+ * step_samples samples carries phase 1 of every admitted query in that
+ * phase (at most chunk_samples samples of each per launch), then phase 2 of
+ * the others in arrival order, each taking what it still needs from what is
+ * left. Two launches are kept in flight on the
+ * context's stream; each percis_server_step waits for the older one, reads
+ * its statistics, finishes the phases it completed (the bounds of Algorithm
+ * 1, the estimates; on a second stream of the server), retires and admits
+ * queries and enqueues the next launch. Queries of different graphs share
+ * the device, and a query submitted while others run joins a launch at the
+ * next step. A query's result is the same alone or in any mix, and equals
+ * percis_graph_estimate with the same arguments. The server is used from one
+ * host thread at a time; no other work may use the context while queries are
+ * in flight. */
 typedef struct percis_server percis_server;
 int percis_server_create(percis_ctx* ctx, int64_t memory_budget_bytes, uint64_t chunk_samples,
                          uint64_t step_samples, percis_server** out);
@@ -386,10 +394,10 @@ void percis_server_destroy(percis_server* server);
 /* Queues a query; returns its id. */
 int percis_server_submit(percis_server* server, int32_t graph, double eps, double delta, uint64_t seed,
                          int64_t* query_id);
-/* Admits what fits, runs one batched launch, advances the queries and
- * retires finished ones; *completed (may be NULL) counts queries that
- * finished a phase-2 or failed in this step. Does nothing if no query is
- * active or queued. */
+/* Admits what fits, keeps two launches in flight, waits for the older one
+ * and advances and retires the queries it served; *completed (may be NULL)
+ * counts queries that finished or failed in this step. Returns at once if
+ * no query is active or queued. */
 int percis_server_step(percis_server* server, int32_t* completed);
 /* *done = 1 once the query has finished: its estimate is copied to p_out
  * (host, n_cap >= n of its graph; may be NULL), its summary to info (may be

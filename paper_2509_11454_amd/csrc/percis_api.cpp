@@ -313,7 +313,11 @@ static void free_slots(percis_ctx* c) {
 constexpr int64_t kSlotBytesPerNode = (int64_t)sizeof(NodeRec) + 4 + 4 + 4 + 4;
 constexpr int64_t kLdsPerCu = 160 * 1024;
 constexpr int64_t kBitmapPlanes = 2;  // s-side and t-side visited
-constexpr int64_t kArcsPerSlot = 4096;  // DAG arcs a sample may record for its walk
+// DAG arcs a sample may record for its walk: per-node slots, which run the
+// samples with large balls when compact slots are on, keep more (a walk step
+// past a dropped arc scans its node's in-row instead)
+constexpr int64_t kArcsPerSlot = 16384;
+constexpr int64_t kArcsPerCompactSlot = 4096;
 // Samples per pair-kernel chunk by default (the pair, wide and handed-on lists
 // take 16 bytes each per sample). Fewer chunks end fewer sampler tails: R-MAT
 // 24 directed, 10^7 samples: 2^22 8.66M, 2^23 8.86M, 2^24 9.11M samples/s.
@@ -368,7 +372,7 @@ static DevSlots node_slots_at(char* p, int64_t ns, int64_t stride, int64_t words
 // Bytes of one compact slot (records by table position, whatever the graph).
 static int64_t compact_slot_bytes() {
     const int64_t cap = sampler_table_cap(true);
-    return 2 * cap * (int64_t)sizeof(CRec) + 4 * cap * 4 + (cap + 2) * 4 + kArcsPerSlot * (int64_t)sizeof(DagArc);
+    return 2 * cap * (int64_t)sizeof(CRec) + 4 * cap * 4 + (cap + 2) * 4 + kArcsPerCompactSlot * (int64_t)sizeof(DagArc);
 }
 
 // nc compact slots laid out from p (compact_slot_bytes each, all zero before use).
@@ -382,7 +386,7 @@ static DevSlots compact_slots_at(char* p, int64_t nc) {
     d.q_d = (int32_t*)p; p += nc * 2 * cap * 4;
     d.tls = (int32_t*)p; p += nc * (cap + 2) * 4;
     d.arcs = (DagArc*)p;
-    d.acap = (int32_t)kArcsPerSlot;
+    d.acap = (int32_t)kArcsPerCompactSlot;
     return d;
 }
 
@@ -619,12 +623,12 @@ static double sample_size_sup(double d, double rho, double v, double eps, double
 // too: every operation in it is monotone), so its maximum over v is its value
 // at max_v d_v h_v, which a device reduction provides.
 int phase1_bounds(percis_ctx* c, const GraphData& G, uint64_t l1u, uint64_t sum_I, uint64_t sum_I2,
-                  const uint32_t* d_hits1, double eps, double delta, percis_estimate_info* I) {
-    HIPCHK(c, launch_fill_u32((uint32_t*)G.d_red, 0u, 2, c->stream));
-    HIPCHK(c, launch_hit_weight_max(G.d_dv, d_hits1, G.n, G.d_red, c->stream));
+                  const uint32_t* d_hits1, double eps, double delta, percis_estimate_info* I, hipStream_t stream) {
+    HIPCHK(c, launch_fill_u32((uint32_t*)G.d_red, 0u, 2, stream));
+    HIPCHK(c, launch_hit_weight_max(G.d_dv, d_hits1, G.n, G.d_red, stream));
     uint64_t bits = 0;
-    HIPCHK(c, hipMemcpyAsync(&bits, G.d_red, sizeof bits, hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, hipMemcpyAsync(&bits, G.d_red, sizeof bits, hipMemcpyDeviceToHost, stream));
+    HIPCHK(c, hipStreamSynchronize(stream));
     double hw;
     std::memcpy(&hw, &bits, sizeof hw);
     const double l1 = (double)l1u;
@@ -645,10 +649,11 @@ int phase1_bounds(percis_ctx* c, const GraphData& G, uint64_t l1u, uint64_t sum_
 
 // p_out[v] = d_v h_v / l (Algorithm 1's estimate), computed on the device and
 // copied to the host array p_out.
-int estimates_to_host(percis_ctx* c, const GraphData& G, const uint32_t* d_hits, uint64_t l, double* p_out) {
-    HIPCHK(c, launch_estimates(G.d_dv, d_hits, G.n, l, G.d_p, c->stream));
-    HIPCHK(c, hipMemcpyAsync(p_out, G.d_p, sizeof(double) * G.n, hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(c, hipStreamSynchronize(c->stream));
+int estimates_to_host(percis_ctx* c, const GraphData& G, const uint32_t* d_hits, uint64_t l, double* p_out,
+                      hipStream_t stream) {
+    HIPCHK(c, launch_estimates(G.d_dv, d_hits, G.n, l, G.d_p, stream));
+    HIPCHK(c, hipMemcpyAsync(p_out, G.d_p, sizeof(double) * G.n, hipMemcpyDeviceToHost, stream));
+    HIPCHK(c, hipStreamSynchronize(stream));
     return PERCIS_OK;
 }
 
@@ -867,6 +872,10 @@ static int launch_status(percis_ctx* c, const DevStats& hl, const percis_stats& 
 
 // Reads a finished launch's statistics (`tstats`, per task, and the
 // launch-wide counters) and checks that every task ran all its samples.
+static int tally_tasks(percis_ctx* c, const std::vector<TaskSpec>& tasks, const DevStats* hts, const DevStats& hl,
+                       double ms, double pair_ms, const double* pass_ms, std::vector<percis_stats>* out,
+                       percis_stats* launch);
+
 static int collect_tasks(percis_ctx* c, const std::vector<TaskSpec>& tasks, const DevStats* tstats,
                          const DevStats* lstats, double ms, double pair_ms, const double* pass_ms,
                          std::vector<percis_stats>* out, percis_stats* launch) {
@@ -876,6 +885,15 @@ static int collect_tasks(percis_ctx* c, const std::vector<TaskSpec>& tasks, cons
     HIPCHK(c, hipMemcpyAsync(hts.data(), tstats, sizeof(DevStats) * nt, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipMemcpyAsync(&hl, lstats, sizeof hl, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
+    return tally_tasks(c, tasks, hts.data(), hl, ms, pair_ms, pass_ms, out, launch);
+}
+
+// The statistics of a finished launch, already on the host: per task (hts)
+// and launch-wide (hl).
+static int tally_tasks(percis_ctx* c, const std::vector<TaskSpec>& tasks, const DevStats* hts, const DevStats& hl,
+                       double ms, double pair_ms, const double* pass_ms, std::vector<percis_stats>* out,
+                       percis_stats* launch) {
+    const int nt = (int)tasks.size();
     percis_stats agg{};
     agg.first_overflow = ~0ull;
     if (out) out->resize(nt);
@@ -933,6 +951,64 @@ int run_tasks(percis_ctx* c, const std::vector<TaskSpec>& tasks, std::vector<per
     return collect_tasks(c, tasks, c->d_task_stats, c->d_stats, ms, pair_ms, pass_ms, out, launch);
 }
 
+int async_launch_init(percis_ctx* c, AsyncLaunch* a, int cap) {
+    *a = AsyncLaunch{};
+    a->cap = cap;
+    int rc;
+    if ((rc = dalloc(c, a->d_tasks, (size_t)cap)) || (rc = dalloc(c, a->d_tstats, (size_t)cap)) ||
+        (rc = dalloc(c, a->d_lstats, 1)))
+        return rc;
+    if (hipHostMalloc((void**)&a->h_tstats, sizeof(DevStats) * cap) != hipSuccess ||
+        hipHostMalloc((void**)&a->h_lstats, sizeof(DevStats)) != hipSuccess)
+        return fail(c, PERCIS_E_NOMEM, "cannot allocate pinned statistics buffers");
+    HIPCHK(c, hipEventCreate(&a->start));
+    HIPCHK(c, hipEventCreate(&a->end));
+    HIPCHK(c, hipEventCreate(&a->done));
+    return PERCIS_OK;
+}
+
+void async_launch_free(AsyncLaunch* a) {
+    dfree(a->d_tasks);
+    dfree(a->d_tstats);
+    dfree(a->d_lstats);
+    if (a->h_tstats) (void)hipHostFree(a->h_tstats);
+    if (a->h_lstats) (void)hipHostFree(a->h_lstats);
+    a->h_tstats = a->h_lstats = nullptr;
+    for (hipEvent_t* e : {&a->start, &a->end, &a->done})
+        if (*e) (void)hipEventDestroy(*e), *e = nullptr;
+}
+
+// Enqueues a launch of `tasks` on the context's stream and returns at once:
+// the kernels, then copies of the statistics into the pinned buffers, then
+// the `done` event. Launches on one stream run one after the other.
+int launch_tasks_async(percis_ctx* c, const std::vector<TaskSpec>& tasks, AsyncLaunch* a) {
+    const int nt = (int)tasks.size();
+    if (nt < 1 || nt > a->cap) return fail(c, PERCIS_E_INVAL, "%d tasks in one launch (1 .. %d)", nt, a->cap);
+    int rc = set_device(c);
+    if (rc) return rc;
+    a->tasks = tasks;
+    LaunchPlan lp;
+    if ((rc = plan_tasks(c, tasks, a->d_tasks, a->d_tstats, a->table, &lp))) return rc;
+    LaunchBufs B = ctx_bufs(c);
+    B.stats = a->d_lstats;
+    HIPCHK(c, hipEventRecord(a->start, c->stream));
+    if ((rc = enqueue_tasks(c, lp, a->d_tasks, B, c->stream, false))) return rc;
+    HIPCHK(c, hipEventRecord(a->end, c->stream));
+    HIPCHK(c, hipMemcpyAsync(a->h_tstats, a->d_tstats, sizeof(DevStats) * nt, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(a->h_lstats, a->d_lstats, sizeof(DevStats), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipEventRecord(a->done, c->stream));
+    return PERCIS_OK;
+}
+
+// Waits for a launch of launch_tasks_async and reads its statistics (as
+// run_tasks reports them).
+int finish_tasks_async(percis_ctx* c, AsyncLaunch* a, std::vector<percis_stats>* out, percis_stats* launch) {
+    HIPCHK(c, hipEventSynchronize(a->done));
+    float ms = 0.f;
+    HIPCHK(c, hipEventElapsedTime(&ms, a->start, a->end));
+    return tally_tasks(c, a->tasks, a->h_tstats, *a->h_lstats, ms, 0.0, nullptr, out, launch);
+}
+
 GraphData* get_graph(percis_ctx* c, int32_t id) {
     if (id < 0 || id >= (int32_t)c->graphs.size() || !c->graphs[id]) return nullptr;
     return c->graphs[id];
@@ -975,7 +1051,8 @@ static int estimate_graph(percis_ctx* c, int32_t id, double eps, double delta, u
         }
         I.phase1_ms = s1.kernel_ms;
         auto tb = std::chrono::steady_clock::now();
-        if ((rc = phase1_bounds(c, *G, I.l1, ts[0].sum_I, ts[0].sum_I2, G->d_hits, eps, delta, &I))) return rc;
+        if ((rc = phase1_bounds(c, *G, I.l1, ts[0].sum_I, ts[0].sum_I2, G->d_hits, eps, delta, &I, c->stream)))
+            return rc;
         auto te = std::chrono::steady_clock::now();
         I.bounds_ms = std::chrono::duration<double, std::milli>(te - tb).count();
     }
@@ -993,7 +1070,7 @@ static int estimate_graph(percis_ctx* c, int32_t id, double eps, double delta, u
         if (info) *info = I;
         return rc;
     }
-    if ((rc = estimates_to_host(c, *G, G->d_hits, I.l, p_out))) return rc;
+    if ((rc = estimates_to_host(c, *G, G->d_hits, I.l, p_out, c->stream))) return rc;
     I.total_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     if (info) *info = I;
     return PERCIS_OK;

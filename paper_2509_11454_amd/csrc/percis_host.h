@@ -139,13 +139,36 @@ int dalloc(percis_ctx* c, T*& p, size_t count) {
     return PERCIS_OK;
 }
 
+// A task launch that the caller keeps in flight (the query server runs two
+// at a time on the context's stream): device task table and statistics,
+// their pinned host copies, and events.
+struct AsyncLaunch {
+    int cap = 0;                       // tasks the buffers hold
+    std::vector<TaskSpec> tasks;       // the launch's tasks
+    std::vector<DevTask> table;        // host task table (read by the upload until the launch ends)
+    DevTask* d_tasks = nullptr;
+    DevStats* d_tstats = nullptr;      // per task
+    DevStats* d_lstats = nullptr;      // launch-wide
+    DevStats* h_tstats = nullptr;      // pinned copies
+    DevStats* h_lstats = nullptr;
+    hipEvent_t start = nullptr, end = nullptr, done = nullptr;
+};
+int async_launch_init(percis_ctx* c, AsyncLaunch* a, int cap);
+void async_launch_free(AsyncLaunch* a);
+int launch_tasks_async(percis_ctx* c, const std::vector<TaskSpec>& tasks, AsyncLaunch* a);
+int finish_tasks_async(percis_ctx* c, AsyncLaunch* a, std::vector<percis_stats>* out, percis_stats* launch);
+
 int set_device(percis_ctx* c);
 int graph_upload(percis_ctx* c, GraphData& G, bool states);
 GraphData* get_graph(percis_ctx* c, int32_t id);
 int run_tasks(percis_ctx* c, const std::vector<TaskSpec>& tasks, std::vector<percis_stats>* out, percis_stats* launch);
+// The bounds of Algorithm 1 from phase 1 (the device reduction of the hits
+// runs on `stream`, which is synchronised).
 int phase1_bounds(percis_ctx* c, const GraphData& G, uint64_t l1, uint64_t sum_I, uint64_t sum_I2,
-                  const uint32_t* d_hits1, double eps, double delta, percis_estimate_info* I);
+                  const uint32_t* d_hits1, double eps, double delta, percis_estimate_info* I, hipStream_t stream);
 int vertex_diam_ub(percis_ctx* c, GraphData& G, int64_t* D);
-int estimates_to_host(percis_ctx* c, const GraphData& G, const uint32_t* d_hits, uint64_t l, double* p_out);
+// p_out[v] = d_v h_v / l through the graph's staging array, on `stream` (synchronised).
+int estimates_to_host(percis_ctx* c, const GraphData& G, const uint32_t* d_hits, uint64_t l, double* p_out,
+                      hipStream_t stream);
 
 }  // namespace percis

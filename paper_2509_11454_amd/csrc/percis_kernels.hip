@@ -55,6 +55,7 @@ constexpr int SCAN_UNROLL = PERCIS_SCAN_UNROLL;  // entries per thread per step 
 constexpr int WALK_UNROLL = 4;  // in-row chunks of 64 loaded together by the walk's row scan
 constexpr int ARC_UNROLL = 4;   // DAG-arc chunks of 64 loaded together by the walk
 constexpr int KCAP = 64;        // predecessors a walk step gathers from the arc list
+constexpr int SEGCAP = 64;      // path positions whose arc-list segment a sample keeps
 constexpr int MLCAP = 128;      // arcs into the other ball that a chunk's first pass lists
 
 // Slot scratch is private to one workgroup (one CU), so every access to it is
@@ -396,6 +397,11 @@ struct SampleShared {
     int32_t ml_w[MLCAP];  // those arcs: head node, and staged tail | (head's position in the other table + 1) << 8
     int32_t ml_m[MLCAP];
     int32_t narcs;        // DAG arcs recorded by this sample (may exceed the slot's capacity)
+    // The arcs into the nodes at distance q from s are recorded by one stage
+    // of the search (the s-side level q, or the t-side step into that
+    // distance), so they lie in arcs[seg_lo[q], seg_hi[q]) (seg_hi = -1:
+    // not kept, q >= SEGCAP or no such stage yet).
+    int32_t seg_lo[SEGCAP], seg_hi[SEGCAP];
     int32_t wk_u[KCAP];   // predecessors of the walk's current node, and their sigma_s
     uint64_t wk_w[KCAP];
     int32_t level_table;  // the level being built decides first visits by its side's table
@@ -1042,8 +1048,24 @@ __device__ __forceinline__ void run_sample(const GGraph& g, const GSlots& sl, in
             }
         }
     }
+    if (tid < SEGCAP) sh.seg_hi[tid] = -1;
     level_barrier();
     phase_mark(0);
+    // Thread 0's arc-list position at the last stage boundary. It is read only
+    // where no stage records arcs: between the two barriers that close a BFS
+    // level, and after a sweep step's closing barrier (the next step records
+    // nothing before its staging barrier, which thread 0 must reach too).
+    int32_t arc_mark = 0;
+    auto close_segment = [&](int32_t q) {
+        if (tid == 0) {
+            const int32_t hi = sh.narcs;
+            if (q >= 1 && q < SEGCAP) {
+                sh.seg_lo[q] = arc_mark;
+                sh.seg_hi[q] = hi;
+            }
+            arc_mark = hi;
+        }
+    };
 
     // ---- balanced bidirectional BFS
     // Thread 0 plans each level (side, append position, fresh accumulators)
@@ -1069,6 +1091,9 @@ __device__ __forceinline__ void run_sample(const GGraph& g, const GSlots& sl, in
                 sh.spill_req[side] = 0;
             }
         }
+        // the arcs of this level: into s-level a + 1, or (the t side's meeting
+        // level, the first sweep step) into the distance a + 1 from s
+        if (side == 0 || sh.nmeet > 0) close_segment(sh.a + 1);
         if (tid == 0) {
             if (side == 0) {
                 sh.lo_s = nlo; sh.hi_s = nhi; sh.tail_s = nhi; sh.a++;
@@ -1146,11 +1171,13 @@ __device__ __forceinline__ void run_sample(const GGraph& g, const GSlots& sl, in
             } else if (j >= 1 && sh.push_cost < sh.deg_t_prev) {
                 push_meeting<BSZ, LDS, CMP>(g, sl, so, V, rc, sh.nmeet, (uint32_t)j, sh, cn);
                 level_barrier();
+                close_segment(sh.a + 1);
                 j--;
             }
             for (; j >= 1; j--) {
                 pull_level<BSZ, LDS, CMP>(g, sl, so, V, rc, ldq(tls + j - 1), ldq(tls + j), (uint32_t)j + 1, sh, cn);
                 level_barrier();
+                close_segment(L - j + 1);  // into t-level j - 1
             }
         }
         phase_mark(2);
@@ -1166,7 +1193,6 @@ __device__ __forceinline__ void run_sample(const GGraph& g, const GSlots& sl, in
             const int32_t aM = sh.a;
             uint64_t r = dbg ? dbg_r : draw_bounded(T.seed, T.phase, idx, 2, sh.sigma);
             const int32_t na = __builtin_amdgcn_readfirstlane(sh.narcs);
-            const bool by_arcs = na <= sl.acap;
             const G<DagArc>* arcs = sl.arcs + (int64_t)blockIdx.x * sl.acap;
             const unsigned long long below = (1ull << lane) - 1;  // lanes under this one
             int32_t w = sh.t;
@@ -1175,16 +1201,26 @@ __device__ __forceinline__ void run_sample(const GGraph& g, const GSlots& sl, in
                 const bool on_s = p <= aM;
                 int32_t sel = -1;
                 int kc = KCAP + 1;
-                if (by_arcs) {
+                // the arcs into w (at distance p + 1): its stage's segment of the
+                // list when kept, else the whole list; usable if none was dropped
+                int32_t a_lo = 0, a_hi = na;
+                if (p + 1 < SEGCAP) {
+                    const int32_t h = __builtin_amdgcn_readfirstlane(sh.seg_hi[p + 1]);
+                    if (h >= 0) {
+                        a_lo = __builtin_amdgcn_readfirstlane(sh.seg_lo[p + 1]);
+                        a_hi = h;
+                    }
+                }
+                if (a_hi <= sl.acap) {
                     kc = 0;
-                    for (int base = 0; base < na; base += 64 * ARC_UNROLL) {
+                    for (int base = a_lo; base < a_hi; base += 64 * ARC_UNROLL) {
                         DagArc a[ARC_UNROLL];
                         bool m[ARC_UNROLL];
 #pragma unroll
                         for (int k = 0; k < ARC_UNROLL; k++) {
                             const int i = base + k * 64 + lane;
                             m[k] = false;
-                            if (i < na) {
+                            if (i < a_hi) {
                                 const u32x4 av = *reinterpret_cast<const G<u32x4>*>(arcs + i);
                                 a[k] = DagArc{(int32_t)av.x, (int32_t)av.y, ((uint64_t)av.w << 32) | av.z};
                                 m[k] = a[k].head == w;

@@ -2,14 +2,21 @@
 //
 // A query asks for Algorithm 1 (PercIS) on one resident graph with its own
 // (eps, delta, seed). Queries wait in arrival order until their hit buffer
-// (4 bytes per node) fits in the server's device-memory budget; admitted
-// queries run their two sampling phases in chunks. Every step is one task
-// launch that carries one chunk of every active query (in admission order,
-// up to the step's sample budget), so queries of different graphs and sizes
-// overlap on the device and a query that arrives while others run starts at
-// the next step. A query's samples are indices of its own (seed, phase)
-// stream, so its result is the same alone or in any mix, and equals
-// percis_graph_estimate for the same arguments.
+// (4 bytes per node) fits in the server's memory pool, one device block of
+// the budget's size allocated when the server is created and sub-allocated
+// per query (first fit); admitted queries run their two sampling phases in
+// chunks. A launch carries the first phase of every query that is in it and
+// then second phases in arrival order, filled up to the step's sample
+// budget, so queries of different graphs and sizes share the device and a
+// query that arrives while others run joins the next launch.
+//
+// Two launches are in flight on the context's stream: while the device runs
+// one, the host reads the statistics of the one before, and the per-query
+// work between phases (the bounds of Algorithm 1, the estimates) runs on a
+// second stream, so the device does not wait for the host. A query's
+// samples are indices of its own (seed, phase) stream, so its result is the
+// same alone or in any mix, and equals percis_graph_estimate for the same
+// arguments.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -17,6 +24,7 @@
 #include <cmath>
 #include <cstring>
 #include <deque>
+#include <map>
 #include <new>
 #include <unordered_map>
 #include <vector>
@@ -38,14 +46,62 @@ struct Query {
     uint64_t seed = 0;
     QState state = QUEUED;
     int status = PERCIS_OK;
-    uint32_t* d_hits = nullptr;
+    uint32_t* d_hits = nullptr;    // in the server's pool
+    int64_t off = -1;              // offset of d_hits in the pool
     int64_t bytes = 0;
-    uint64_t next = 0;             // next sample index of the current phase
+    uint64_t planned = 0;          // samples of the current phase handed to launches
+    uint64_t done = 0;             // samples of the current phase finished
     uint64_t target = 0;           // samples of the current phase
     uint64_t sum_I = 0, sum_I2 = 0, overflow = 0;
     percis_estimate_info info{};
     std::vector<double> p;
     std::chrono::steady_clock::time_point t_submit, t_admit;
+};
+
+constexpr int kMaxLaunchTasks = 4096;  // query chunks one launch carries at most
+constexpr int kInFlight = 2;           // launches on the device at a time
+
+// First-fit allocator over the pool: free ranges by offset.
+struct Pool {
+    int64_t size = 0;
+    std::map<int64_t, int64_t> free_;   // offset -> length
+
+    void reset(int64_t n) {
+        size = n;
+        free_.clear();
+        free_[0] = n;
+    }
+    int64_t alloc(int64_t n) {
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second < n) continue;
+            const int64_t at = it->first, len = it->second;
+            free_.erase(it);
+            if (len > n) free_[at + n] = len - n;
+            return at;
+        }
+        return -1;
+    }
+    void release(int64_t at, int64_t n) {
+        auto it = free_.emplace(at, n).first;
+        auto next = std::next(it);
+        if (next != free_.end() && at + n == next->first) {
+            it->second += next->second;
+            free_.erase(next);
+        }
+        if (it != free_.begin()) {
+            auto prev = std::prev(it);
+            if (prev->first + prev->second == at) {
+                prev->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+};
+
+struct Flight {
+    AsyncLaunch launch;
+    std::vector<Query*> owners;
+    bool busy = false;
 };
 
 }  // namespace
@@ -57,6 +113,12 @@ struct percis_server {
     uint64_t chunk = 0;
     uint64_t step_samples = 0;
     int64_t next_id = 1;
+    void* pool_mem = nullptr;
+    Pool pool;
+    hipStream_t post = nullptr;                     // per-query work between phases
+    Flight flights[kInFlight];
+    int head = 0;                                   // oldest launch in flight
+    int inflight = 0;
     std::deque<Query*> queued;
     std::vector<Query*> active;                     // admission order
     std::unordered_map<int64_t, Query*> by_id;
@@ -68,47 +130,116 @@ struct percis_server {
 namespace {
 
 void release(percis_server* s, Query* q) {
-    if (q->d_hits) {
-        (void)hipFree(q->d_hits);
+    if (q->off >= 0) {
+        s->pool.release(q->off, q->bytes);
+        q->off = -1;
         q->d_hits = nullptr;
         s->in_use -= q->bytes;
     }
 }
 
-// Admits queued queries in arrival order while their buffers fit.
-int admit(percis_server* s) {
+// Admits queued queries in arrival order while their buffers fit the pool.
+void admit(percis_server* s) {
     while (!s->queued.empty()) {
         Query* q = s->queued.front();
-        if (s->in_use + q->bytes > s->budget && !s->active.empty()) break;
-        if (s->in_use + q->bytes > s->budget && q->bytes > s->budget) {
+        if (q->bytes > s->budget) {
             q->state = FAILED;
             q->status = PERCIS_E_NOMEM;
             s->queued.pop_front();
             continue;
         }
-        void* p = nullptr;
-        if (hipMalloc(&p, (size_t)q->bytes) != hipSuccess) {
-            (void)hipGetLastError();
-            if (s->active.empty()) {
-                q->state = FAILED;
-                q->status = PERCIS_E_NOMEM;
-                s->queued.pop_front();
-                continue;
-            }
-            break;
-        }
-        q->d_hits = (uint32_t*)p;
+        const int64_t at = s->pool.alloc(q->bytes);
+        if (at < 0) break;
+        q->off = at;
+        q->d_hits = (uint32_t*)((char*)s->pool_mem + at);
         s->in_use += q->bytes;
         s->peak_in_use = std::max(s->peak_in_use, s->in_use);
         q->state = PHASE1;
         q->info.l1 = (uint64_t)std::ceil(std::max(1000.0, std::log(1.0 / q->delta) / q->eps));
         q->target = q->info.l1;
-        q->next = 0;
+        q->planned = q->done = 0;
         q->t_admit = std::chrono::steady_clock::now();
         s->queued.pop_front();
         s->active.push_back(q);
     }
+}
+
+// Plans one launch of at most step_samples samples: first phase 1 of every
+// admitted query in it (short, and it decides the size of phase 2), at most
+// `chunk` samples each, then phase 2 in arrival order, each query taking
+// what it still needs from what the launch has left. A query is then never
+// slowed by queries that arrived after it, beyond their phase 1.
+void plan(percis_server* s, std::vector<TaskSpec>& tasks, std::vector<Query*>& owners) {
+    uint64_t left = s->step_samples;
+    for (int ph = 1; ph <= 2 && left > 0; ph++) {
+        for (Query* q : s->active) {
+            if (left == 0 || (int)tasks.size() >= kMaxLaunchTasks) break;
+            if ((int)q->state != ph || q->planned >= q->target) continue;
+            uint64_t take = std::min<uint64_t>(q->target - q->planned, left);
+            if (ph == 1) take = std::min<uint64_t>(take, s->chunk);
+            tasks.push_back(TaskSpec{q->graph, (uint32_t)ph, q->planned, take, q->seed, q->d_hits, q->planned > 0});
+            owners.push_back(q);
+            q->planned += take;
+            left -= take;
+        }
+    }
+}
+
+// Plans and enqueues launches until kInFlight are on the device or there is
+// nothing to hand out.
+int fill(percis_server* s) {
+    percis_ctx* c = s->ctx;
+    while (s->inflight < kInFlight) {
+        Flight& f = s->flights[(s->head + s->inflight) % kInFlight];
+        std::vector<TaskSpec> tasks;
+        f.owners.clear();
+        plan(s, tasks, f.owners);
+        if (tasks.empty()) break;
+        const int rc = launch_tasks_async(c, tasks, &f.launch);
+        if (rc) return rc;
+        f.busy = true;
+        s->inflight++;
+    }
     return PERCIS_OK;
+}
+
+// A query whose current phase has finished: the bounds of Algorithm 1 after
+// phase 1 (phase 2 then starts at the next launch), the estimate after
+// phase 2. Device work on the server's second stream, after `after` (the
+// launch that finished the phase). Returns 1 if the query is done (or failed).
+int finish_phase(percis_server* s, Query* q, hipEvent_t after, int* rc_out) {
+    percis_ctx* c = s->ctx;
+    *rc_out = PERCIS_OK;
+    GraphData& G = *get_graph(c, q->graph);
+    if (q->overflow) {
+        q->state = FAILED;
+        q->status = PERCIS_E_SIGMA_OVERFLOW;
+        q->info.overflow = q->overflow;
+        return 1;
+    }
+    if (hipStreamWaitEvent(s->post, after, 0) != hipSuccess) {
+        *rc_out = fail(c, PERCIS_E_DEVICE, "cannot order the server's streams");
+        return 0;
+    }
+    if (q->state == PHASE1) {
+        if ((*rc_out = phase1_bounds(c, G, q->info.l1, q->sum_I, q->sum_I2, q->d_hits, q->eps, q->delta, &q->info,
+                                     s->post)))
+            return 0;
+        if (q->info.l >= 4294967295ull) {
+            q->state = FAILED;
+            q->status = PERCIS_E_TOO_LARGE;
+            return 1;
+        }
+        q->state = PHASE2;
+        q->target = q->info.l;
+        q->planned = q->done = 0;
+        return 0;
+    }
+    q->p.resize(G.n);
+    if ((*rc_out = estimates_to_host(c, G, q->d_hits, q->info.l, q->p.data(), s->post))) return 0;
+    q->state = DONE;
+    q->info.total_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - q->t_submit).count();
+    return 1;
 }
 
 }  // namespace
@@ -119,12 +250,27 @@ int percis_server_create(percis_ctx* ctx, int64_t memory_budget_bytes, uint64_t 
                          percis_server** out) {
     if (!ctx || !out || memory_budget_bytes <= 0 || chunk_samples == 0 || step_samples == 0) return PERCIS_E_INVAL;
     if (ctx->host_only) return fail(ctx, PERCIS_E_STATE, "host-only context cannot serve");
+    int rc = set_device(ctx);
+    if (rc) return rc;
     percis_server* s = new (std::nothrow) percis_server();
     if (!s) return PERCIS_E_NOMEM;
     s->ctx = ctx;
-    s->budget = memory_budget_bytes;
+    s->budget = memory_budget_bytes / 256 * 256;
     s->chunk = chunk_samples;
     s->step_samples = std::max(step_samples, chunk_samples);
+    if (hipMalloc(&s->pool_mem, (size_t)std::max<int64_t>(s->budget, 256)) != hipSuccess) {
+        (void)hipGetLastError();
+        delete s;
+        return fail(ctx, PERCIS_E_NOMEM, "cannot allocate the %lld-byte query pool", (long long)memory_budget_bytes);
+    }
+    s->pool.reset(s->budget);
+    rc = hipStreamCreateWithFlags(&s->post, hipStreamNonBlocking) == hipSuccess ? PERCIS_OK
+         : fail(ctx, PERCIS_E_DEVICE, "cannot create the server's stream");
+    for (int i = 0; i < kInFlight && rc == PERCIS_OK; i++) rc = async_launch_init(ctx, &s->flights[i].launch, kMaxLaunchTasks);
+    if (rc) {
+        percis_server_destroy(s);
+        return rc;
+    }
     *out = s;
     return PERCIS_OK;
 }
@@ -133,12 +279,13 @@ void percis_server_destroy(percis_server* s) {
     if (!s) return;
     if (s->ctx && !s->ctx->host_only) {
         (void)hipSetDevice(s->ctx->device);
-        (void)hipDeviceSynchronize();
+        if (s->ctx->stream) (void)hipStreamSynchronize(s->ctx->stream); else (void)hipDeviceSynchronize();
+        if (s->post) (void)hipStreamSynchronize(s->post);
     }
-    for (auto& kv : s->by_id) {
-        release(s, kv.second);
-        delete kv.second;
-    }
+    for (auto& kv : s->by_id) delete kv.second;
+    for (Flight& f : s->flights) async_launch_free(&f.launch);
+    if (s->post) (void)hipStreamDestroy(s->post);
+    if (s->pool_mem) (void)hipFree(s->pool_mem);
     delete s;
 }
 
@@ -175,65 +322,36 @@ int percis_server_step(percis_server* s, int32_t* completed) {
     int rc = set_device(c);
     if (rc) return rc;
     admit(s);
-    if (s->active.empty()) return PERCIS_OK;
+    if ((rc = fill(s))) return rc;
+    if (s->inflight == 0) return PERCIS_OK;
 
-    // one chunk of every active query, in admission order, within the step budget
-    std::vector<TaskSpec> tasks;
-    std::vector<Query*> owners;
-    uint64_t planned = 0;
-    for (Query* q : s->active) {
-        if (planned >= s->step_samples) break;
-        const uint64_t left = q->target - q->next;
-        const uint64_t take = std::min<uint64_t>(left, std::min<uint64_t>(s->chunk, s->step_samples - planned));
-        if (take == 0) continue;
-        const uint32_t phase = q->state == PHASE1 ? 1u : 2u;
-        tasks.push_back(TaskSpec{q->graph, phase, q->next, take, q->seed, q->d_hits, q->next > 0});
-        owners.push_back(q);
-        planned += take;
-    }
-    if (tasks.empty()) return PERCIS_OK;
+    // the oldest launch: its statistics, then the queries whose phase it ended
+    Flight& f = s->flights[s->head];
     std::vector<percis_stats> ts;
     percis_stats launch{};
-    rc = run_tasks(c, tasks, &ts, &launch);
+    rc = finish_tasks_async(c, &f.launch, &ts, &launch);
+    s->head = (s->head + 1) % kInFlight;
+    s->inflight--;
+    f.busy = false;
     if (rc != PERCIS_OK && rc != PERCIS_E_SIGMA_OVERFLOW) return rc;
     s->samples_done += launch.samples;
-    s->kernel_ms += launch.kernel_ms + launch.pair_ms;
-
+    s->kernel_ms += launch.kernel_ms;
     int32_t done = 0;
-    for (size_t i = 0; i < owners.size(); i++) {
-        Query* q = owners[i];
-        q->next += tasks[i].count;
+    for (size_t i = 0; i < f.owners.size(); i++) {
+        Query* q = f.owners[i];
+        q->done += f.launch.tasks[i].count;
         q->sum_I += ts[i].sum_I;
         q->sum_I2 += ts[i].sum_I2;
         q->overflow += ts[i].overflow;
-        if (q->next < q->target) continue;
-        GraphData& G = *get_graph(c, q->graph);
-        if (q->overflow) {
-            q->state = FAILED;
-            q->status = PERCIS_E_SIGMA_OVERFLOW;
-            q->info.overflow = q->overflow;
-        } else if (q->state == PHASE1) {
-            if ((rc = phase1_bounds(c, G, q->info.l1, q->sum_I, q->sum_I2, q->d_hits, q->eps, q->delta, &q->info)))
-                return rc;
-            if (q->info.l >= 4294967295ull) {
-                q->state = FAILED;
-                q->status = PERCIS_E_TOO_LARGE;
-            } else {
-                q->state = PHASE2;
-                q->target = q->info.l;
-                q->next = 0;
-                continue;
-            }
-        } else {
-            q->p.resize(G.n);
-            if ((rc = estimates_to_host(c, G, q->d_hits, q->info.l, q->p.data()))) return rc;
-            q->state = DONE;
-            q->info.total_ms =
-                std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - q->t_submit).count();
-        }
-        done++;
     }
-    // retire finished queries and free their buffers for the next admissions
+    for (size_t i = 0; i < f.owners.size(); i++) {
+        Query* q = f.owners[i];
+        if (q->done < q->target || q->planned > q->done || q->state == DONE || q->state == FAILED) continue;
+        int err = PERCIS_OK;
+        done += finish_phase(s, q, f.launch.done, &err);
+        if (err) return err;
+    }
+    // retire finished queries; their pool space admits the next ones
     std::vector<Query*> still;
     for (Query* q : s->active) {
         if (q->state == DONE || q->state == FAILED) release(s, q);
@@ -241,6 +359,7 @@ int percis_server_step(percis_server* s, int32_t* completed) {
     }
     s->active.swap(still);
     admit(s);
+    if ((rc = fill(s))) return rc;
     if (completed) *completed = done;
     return PERCIS_OK;
 }

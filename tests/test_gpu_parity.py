@@ -81,10 +81,13 @@ def test_debug_path_sigma_extremes():
 
 def test_walk_many_predecessors_and_arc_overflow():
     """Nodes with more than 64 DAG predecessors, and searches that record more
-    DAG arcs than a slot keeps, make the walk scan in-rows instead of the arc
-    list; the paths still equal the oracle's."""
+    DAG arcs than a slot keeps (16384 in a per-node slot; [1, 150, 150, 1]
+    records 22650, of which the level into distance 2 alone 22500), make the
+    walk scan in-rows instead of the arc list for those steps, while steps
+    whose own segment of the list is complete still use it; the paths still
+    equal the oracle's."""
     from paper_2509_11454_amd import percis as P
-    for g in [W.layered_graph([1, 100, 100, 1]), W.layered_graph([1, 3, 70, 2, 1]),
+    for g in [W.layered_graph([1, 100, 100, 1]), W.layered_graph([1, 150, 150, 1]), W.layered_graph([1, 3, 70, 2, 1]),
               W.layered_graph([1, 90, 60, 1], directed=True), W.layered_graph([1, 65, 1])]:
         c = P.Context(0)
         c.load_csr(g.n, g.row_ptr, g.col, directed=g.directed)
