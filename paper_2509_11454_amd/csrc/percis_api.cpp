@@ -318,6 +318,9 @@ constexpr int64_t kBitmapPlanes = 2;  // s-side and t-side visited
 // past a dropped arc scans its node's in-row instead)
 constexpr int64_t kArcsPerSlot = 16384;
 constexpr int64_t kArcsPerCompactSlot = 4096;
+// Arcs into the other ball a level lists past its LDS list (8 bytes each,
+// per slot); a meeting level with more rescans its rows for them.
+constexpr int64_t kMeetListPerSlot = 8192;
 // Samples per pair-kernel chunk by default (the pair, wide and handed-on lists
 // take 16 bytes each per sample). Fewer chunks end fewer sampler tails: R-MAT
 // 24 directed, 10^7 samples: 2^22 8.66M, 2^23 8.86M, 2^24 9.11M samples/s.
@@ -349,7 +352,8 @@ static int64_t bitmap_words(int64_t act) { return ((std::max<int64_t>(act, 1) + 
 // (stride a multiple of 64): records and queues, the bitmap planes and the
 // DAG-arc list.
 static int64_t node_slot_bytes(int64_t stride, int64_t words) {
-    return stride * kSlotBytesPerNode + 8 + kBitmapPlanes * words * 4 + kArcsPerSlot * (int64_t)sizeof(DagArc);
+    return stride * kSlotBytesPerNode + 8 + kBitmapPlanes * words * 4 + kArcsPerSlot * (int64_t)sizeof(DagArc) +
+           kMeetListPerSlot * 8;
 }
 
 // ns per-node slots laid out from p (node_slot_bytes each, all zero before use).
@@ -364,6 +368,8 @@ static DevSlots node_slots_at(char* p, int64_t ns, int64_t stride, int64_t words
     s.q_d = (int32_t*)p; p += cnt * 4;
     s.tls = (int32_t*)p; p += ns * (stride + 2) * 4;
     s.bm = (uint32_t*)p; p += ns * kBitmapPlanes * words * 4;
+    s.mlx = (uint32_t*)p; p += ns * kMeetListPerSlot * 8;
+    s.mlxcap = (int32_t)kMeetListPerSlot;
     s.arcs = (DagArc*)p;
     s.acap = (int32_t)kArcsPerSlot;
     return s;
@@ -372,7 +378,8 @@ static DevSlots node_slots_at(char* p, int64_t ns, int64_t stride, int64_t words
 // Bytes of one compact slot (records by table position, whatever the graph).
 static int64_t compact_slot_bytes() {
     const int64_t cap = sampler_table_cap(true);
-    return 2 * cap * (int64_t)sizeof(CRec) + 4 * cap * 4 + (cap + 2) * 4 + kArcsPerCompactSlot * (int64_t)sizeof(DagArc);
+    return 2 * cap * (int64_t)sizeof(CRec) + 4 * cap * 4 + (cap + 2) * 4 + kArcsPerCompactSlot * (int64_t)sizeof(DagArc) +
+           kMeetListPerSlot * 8;
 }
 
 // nc compact slots laid out from p (compact_slot_bytes each, all zero before use).
@@ -385,6 +392,8 @@ static DevSlots compact_slots_at(char* p, int64_t nc) {
     d.q_t = (int32_t*)p; p += nc * cap * 4;
     d.q_d = (int32_t*)p; p += nc * 2 * cap * 4;
     d.tls = (int32_t*)p; p += nc * (cap + 2) * 4;
+    d.mlx = (uint32_t*)p; p += nc * kMeetListPerSlot * 8;
+    d.mlxcap = (int32_t)kMeetListPerSlot;
     d.arcs = (DagArc*)p;
     d.acap = (int32_t)kArcsPerCompactSlot;
     return d;

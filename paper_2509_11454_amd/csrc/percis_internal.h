@@ -82,6 +82,8 @@ struct DevSlots {
     DagArc* arcs;     // [slots][acap] arcs of the sample's shortest-path DAG, for the walk
     int32_t acap;     // arcs per slot
     CRec* crec;       // compact slot set: [slots][2][stride] records
+    uint32_t* mlx;    // [slots][mlxcap][2] arcs into the other ball past the LDS list (head, staged tail | position)
+    int32_t mlxcap;   // entries per slot
 };
 
 // Device-side accumulators of one sampling call.

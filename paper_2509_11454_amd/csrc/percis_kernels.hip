@@ -56,7 +56,8 @@ constexpr int WALK_UNROLL = 4;  // in-row chunks of 64 loaded together by the wa
 constexpr int ARC_UNROLL = 4;   // DAG-arc chunks of 64 loaded together by the walk
 constexpr int KCAP = 64;        // predecessors a walk step gathers from the arc list
 constexpr int SEGCAP = 64;      // path positions whose arc-list segment a sample keeps
-constexpr int MLCAP = 128;      // arcs into the other ball that a chunk's first pass lists
+constexpr int MLCAP = 128;      // arcs into the other ball that a chunk's first pass lists in LDS
+                                // (more go to the slot's device list, sl.mlxcap of them)
 
 // Slot scratch is private to one workgroup (one CU), so every access to it is
 // a workgroup-scope atomic: coherent among the workgroup's waves without the
@@ -75,6 +76,7 @@ __device__ __forceinline__ G<T>* gptr(T* p) { return (G<T>*)p; }
 // 16-byte records move as one vector access (a class type cannot be copied
 // through an address-space-qualified pointer).
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 template <class T>
 __device__ __forceinline__ const G<T>* gptr(const T* p) { return (const G<T>*)p; }
 
@@ -118,10 +120,12 @@ struct GSlots {
     G<DagArc>* arcs;
     int32_t acap;
     G<CRec>* crec;
+    G<uint32_t>* mlx;
+    int32_t mlxcap;
 };
 __device__ __forceinline__ GSlots sview(const DevSlots& s) {
     return GSlots{gptr(s.rec), gptr(s.q_s), gptr(s.q_t), gptr(s.q_d), gptr(s.tls), s.stride,
-                  gptr(s.bm),  s.words,     gptr(s.arcs), s.acap,       gptr(s.crec)};
+                  gptr(s.bm),  s.words,     gptr(s.arcs), s.acap,       gptr(s.crec), gptr(s.mlx), s.mlxcap};
 }
 
 // Bitmap operations on one plane of a slot's device bitmaps.
@@ -635,6 +639,7 @@ __device__ __forceinline__ void expand_bfs(const GGraph& g, const GSlots& sl, in
     const int tid = threadIdx.x;
     const bool by_table = LDS && sh.level_table;   // else: bitmap (device mode) or record CAS (LDS mode)
     G<DagArc>* arcs = sl.arcs + (int64_t)blockIdx.x * sl.acap;
+    G<uint32_t>* mlx = sl.mlx + (int64_t)blockIdx.x * sl.mlxcap * 2;
     const G<int32_t>* rp = SIDE ? g.irp : g.rp;
     const G<int32_t>* col = SIDE ? g.icol : g.col;
     G<int32_t>* q = (SIDE ? sl.q_t : sl.q_s) + so;
@@ -664,9 +669,12 @@ __device__ __forceinline__ void expand_bfs(const GGraph& g, const GSlots& sl, in
                     cn.E++;
                     if ((in >> k) & 1u) {
                         const int i = atomicAdd(&sh.mcnt, 1);
+                        const int32_t mk = jj[k] | ((po[k] + 1) << 8);
                         if (i < MLCAP) {
                             sh.ml_w[i] = w[k];
-                            sh.ml_m[i] = jj[k] | ((po[k] + 1) << 8);
+                            sh.ml_m[i] = mk;
+                        } else if (i < MLCAP + sl.mlxcap) {
+                            *reinterpret_cast<G<u32x2>*>(mlx + 2 * (i - MLCAP)) = u32x2{(uint32_t)w[k], (uint32_t)mk};
                         }
                     }
                 }
@@ -676,7 +684,7 @@ __device__ __forceinline__ void expand_bfs(const GGraph& g, const GSlots& sl, in
             // only when mcnt > 0, so every thread makes the same choice
             const int mc = sh.mcnt;
             meets = mc > 0 || sh.level_meets != 0;
-            listed = meets && mc <= MLCAP;
+            listed = meets && mc <= MLCAP + sl.mlxcap;
             if (listed) n2 = mc;
             if (mc > 0 && tid == 0) sh.level_meets = 1;
         }
@@ -693,10 +701,17 @@ __device__ __forceinline__ void expand_bfs(const GGraph& g, const GSlots& sl, in
                     w[k] = 0;
                     po[k] = -1;
                     if (i < n2) {
-                        const int m = sh.ml_m[i];
+                        int32_t m;
+                        if (i < MLCAP) {
+                            m = sh.ml_m[i];
+                            w[k] = sh.ml_w[i];
+                        } else {
+                            const u32x2 v = *reinterpret_cast<const G<u32x2>*>(mlx + 2 * (i - MLCAP));
+                            w[k] = (int32_t)v.x;
+                            m = (int32_t)v.y;
+                        }
                         jj[k] = m & 255;
                         po[k] = (m >> 8) - 1;
-                        w[k] = sh.ml_w[i];
                         into_other |= 1u << k;
                     }
                 }
