@@ -316,7 +316,8 @@ def run_batch(args):
     uniform states) with 1e5 samples each: one autotuned launch over all
     graphs, captured as a HIP graph and replayed (the headline value), beside
     the same launch issued eagerly, 64 per-graph launches and one sample per
-    launch."""
+    launch. The autotuner's probe is a launch of 2e5 samples spread over all
+    64 graphs (untimed set-up)."""
     import torch
     import workloads as W
     from paper_2509_11454_amd import percis as P
@@ -333,8 +334,7 @@ def run_batch(args):
     c.load_csr(g0.n, g0.row_ptr, g0.col)
     c.set_states(k0)
     ids = [0] + [c.add_graph(g.n, g.row_ptr, g.col, k) for g, k in graphs[1:]]
-    big = max(range(64), key=lambda i: graphs[i][0].n)
-    tune = c.autotune(ids[big], 20000)
+    tune = c.autotune(-1, 200_000)
     print("[bench] autotune: %s" % tune, file=sys.stderr, flush=True)
     hits = [torch.zeros(g.n, dtype=torch.int32, device="cuda") for g, _ in graphs]
     tasks = [dict(graph=ids[i], first=0, count=per_graph, seed=args.seed + i, phase=0, hits=hits[i])

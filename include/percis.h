@@ -350,21 +350,44 @@ int percis_exact(percis_ctx* ctx, int32_t graph, double* p_out, double* kernel_m
  * sampler runs them; the lists take 48 bytes of device memory per sample of a
  * chunk. Results do not depend on it. Reading it gives the chunk in use. */
 #define PERCIS_OPT_PAIR_CHUNK  7
+/* PERCIS_OPT_BALANCE: the side rule of the balanced bidirectional search
+ * (Section III-B): the s ball grows the next level while the degree sum of
+ * its frontier is at most BALANCE % of the t ball's, else the t ball grows.
+ * 25 .. 400, 0 = auto (100: the ball with the smaller frontier degree sum).
+ * The shortest-path counts, the canonical walk and so every result are the
+ * same under any rule; only the work per sample changes. A captured launch
+ * keeps the rule in force when it was captured. Reading it gives the rule in
+ * use. */
+#define PERCIS_OPT_BALANCE     8
 int percis_set_option(percis_ctx* ctx, int option, int64_t value);
 int percis_get_option(percis_ctx* ctx, int option, int64_t* value);
 
-/* Autotuner: times probe_samples samples of graph `graph` (stream phase 3,
- * seed `seed`) under every launch shape that can run (threads per sample
- * 128/256/512/1024, visited sets in LDS tables or device bitmaps, slots
- * filling the device) and keeps the fastest as the context's shape. The
- * chosen shape is reported in *result (may be NULL). Results of sampling
- * calls never depend on the shape. */
+/* Autotuner: times one launch of probe_samples samples (stream phase 3, seed
+ * `seed`) of graph `graph`, or split evenly over every graph with states when
+ * `graph` is -1, under a staged search, and keeps the fastest knobs as the
+ * context's options (PERCIS_OPT_BLOCK, _BITMAPS, _COMPACT, _SLOTS, _BALANCE):
+ *   1. the automatic shape (every option 0), then threads per sample 128, 256,
+ *      512, 1024 x visited sets in device bitmaps, in LDS tables, in LDS
+ *      tables on compact slots (the work granularity and the frontier layout);
+ *   2. the best shape on 3/4 and 1/2 of its slots (the batch width);
+ *   3. the best so far under the side rules 50 and 200 (PERCIS_OPT_BALANCE).
+ * Each candidate runs one untimed launch, then two timed ones; the faster
+ * counts. A candidate that cannot run (memory, occupancy) is passed over.
+ * The choice is reported in *result (may be NULL). Results of sampling calls
+ * never depend on any of these knobs. Errors: E_INVAL (no graph, probe size
+ * outside 1 .. 2^32 - 1), E_STATE (no states; no graph with states for -1;
+ * host-only context), E_DEVICE (no candidate could run); the options are
+ * restored to their values before the call on error. */
 typedef struct {
-    int32_t block;          /* threads per sample */
+    int32_t block;          /* threads per sample of the first pass (the compact slots' when compact is 2) */
     int32_t bitmaps;        /* visited sets: 1 = device bitmaps, 2 = LDS tables */
-    int32_t slots;          /* concurrent samples */
-    int32_t candidates;     /* shapes timed */
-    double samples_per_s;   /* probe throughput of the chosen shape */
+    int32_t slots;          /* concurrent samples of the first pass */
+    int32_t candidates;     /* candidates timed */
+    double samples_per_s;   /* probe throughput of the choice */
+    int32_t compact;        /* 1 = per-node slots only, 2 = compact slots first */
+    int32_t balance;        /* side rule (PERCIS_OPT_BALANCE) */
+    int32_t defer_block;    /* threads per sample of the pass over the samples handed on (compact 2), else 0 */
+    double auto_samples_per_s; /* probe throughput with every option 0 */
 } percis_tuning;
 int percis_autotune(percis_ctx* ctx, int32_t graph, uint64_t probe_samples, uint64_t seed, percis_tuning* result);
 

@@ -326,6 +326,10 @@ constexpr int64_t kMeetListPerSlot = 8192;
 // 24 directed, 10^7 samples: 2^22 8.66M, 2^23 8.86M, 2^24 9.11M samples/s.
 constexpr uint64_t kPairChunk = 1ull << 24;
 constexpr uint64_t kMaxPairChunk = 1ull << 30;  // list entries index their chunk in 32 bits
+// side rule of the bidirectional search: the s ball grows while its frontier
+// degree sum is at most kBalance % of the t ball's (100: the smaller frontier)
+constexpr uint32_t kBalance = 100;
+constexpr int kMinBalance = 25, kMaxBalance = 400;
 constexpr uint64_t kNoAllocChunk = 1ull << 16;  // samples per chunk of a no-allocation call
 constexpr int64_t kWideSlots = 16;           // workgroups of the 128-bit path
 constexpr int64_t kWideBytesPerNode = 4 + 16 + 4;
@@ -799,6 +803,7 @@ static int enqueue_tasks(percis_ctx* c, const LaunchPlan& lp, const DevTask* tab
     a.work = B.work;
     a.npairs = B.work + 1;
     a.stats = B.stats;
+    a.balance = c->opt_balance > 0 ? (uint32_t)c->opt_balance : kBalance;
     // the per-node shape of this launch: wider workgroups for a small launch
     // unless the caller fixed the shape
     SamplerShape shape = B.shape;
@@ -1734,6 +1739,13 @@ int percis_set_option(percis_ctx* c, int option, int64_t value) {
             if ((uint64_t)value > kMaxPairChunk) return fail(c, PERCIS_E_INVAL, "pair chunk must be at most 2^30 samples");
             c->opt_pair_chunk = value;
             break;
+        case PERCIS_OPT_BALANCE:
+            if (value != 0 && (value < kMinBalance || value > kMaxBalance))
+                return fail(c, PERCIS_E_INVAL, "balance must be 0 (auto) or %d .. %d", kMinBalance, kMaxBalance);
+            // the rule only steers the search, so slots stay valid; a captured
+            // launch keeps the rule it was captured with
+            c->opt_balance = value;
+            return PERCIS_OK;
         default: return fail(c, PERCIS_E_INVAL, "unknown option %d", option);
     }
     if (!c->host_only && sync_ctx(c) == PERCIS_OK) free_slots(c);
@@ -1748,6 +1760,10 @@ int percis_get_option(percis_ctx* c, int option, int64_t* value) {
     }
     if (option == PERCIS_OPT_PAIR_CHUNK) {
         *value = c->opt_pair_chunk > 0 ? c->opt_pair_chunk : (int64_t)kPairChunk;
+        return PERCIS_OK;
+    }
+    if (option == PERCIS_OPT_BALANCE) {
+        *value = c->opt_balance > 0 ? c->opt_balance : (int64_t)kBalance;
         return PERCIS_OK;
     }
     if (option != PERCIS_OPT_SLOTS && option != PERCIS_OPT_BLOCK && option != PERCIS_OPT_BITMAPS &&
@@ -1826,57 +1842,131 @@ int percis_exact(percis_ctx* c, int32_t graph, double* p_out, double* kernel_ms)
 
 int percis_autotune(percis_ctx* c, int32_t graph, uint64_t probe_samples, uint64_t seed, percis_tuning* result) {
     if (!c) return PERCIS_E_INVAL;
-    GraphData* G = get_graph(c, graph);
-    if (!G) return fail(c, PERCIS_E_INVAL, "no graph %d", graph);
-    if (!G->has_graph || !G->has_states) return fail(c, PERCIS_E_STATE, "graph %d has no states", graph);
+    if (c->host_only) return fail(c, PERCIS_E_STATE, "host-only context");
     if (probe_samples < 1 || probe_samples >= (1ull << 32)) return fail(c, PERCIS_E_INVAL, "bad probe size");
-    int rc = graph_upload(c, *G, true);
-    if (rc) return rc;
-    const int64_t act = std::max<int64_t>(1, max_active(c));
-    const int64_t saved_block = c->opt_block, saved_bitmaps = c->opt_bitmaps, saved_slots = c->opt_slots;
-    struct Cand {
-        int64_t block, bitmaps;
-    };
-    std::vector<Cand> cands;
-    for (int64_t b : {128, 256, 512, 1024}) {
-        if (sampler_table_lds(false, (int)b) + sampler_static_lds() <= kLdsPerCu) cands.push_back({b, 2});
-        cands.push_back({b, 1});
-    }
-    std::vector<TaskSpec> one(1);
-    one[0] = TaskSpec{graph, 3, 0, probe_samples, seed, G->d_hits, false};
-    double best_rate = -1.0;
-    Cand best{saved_block, saved_bitmaps};
-    int tried = 0;
-    for (const Cand& cd : cands) {
-        c->opt_block = cd.block;
-        c->opt_bitmaps = cd.bitmaps;
-        c->opt_slots = 0;
-        if ((rc = sync_ctx(c))) return rc;
-        free_slots(c);
-        percis_stats st{};
-        rc = run_tasks(c, one, nullptr, &st);  // the first run warms up, the second is timed
-        if (rc == PERCIS_OK) rc = run_tasks(c, one, nullptr, &st);
-        if (rc != PERCIS_OK && rc != PERCIS_E_SIGMA_OVERFLOW) continue;  // a shape that cannot run is skipped
-        tried++;
-        const double rate = st.kernel_ms > 0 ? probe_samples / st.kernel_ms * 1e3 : 0.0;
-        if (rate > best_rate) {
-            best_rate = rate;
-            best = cd;
+    // the probe: stream phase 3 of the one graph, or an equal share of every
+    // graph with states (graph -1), as one launch
+    std::vector<int32_t> ids;
+    if (graph == -1) {
+        for (int32_t i = 0; i < (int32_t)c->graphs.size(); i++) {
+            const GraphData* G = c->graphs[i];
+            if (G && G->has_graph && G->has_states) ids.push_back(i);
         }
+        if (ids.empty()) return fail(c, PERCIS_E_STATE, "no graph has states");
+    } else {
+        GraphData* G = get_graph(c, graph);
+        if (!G) return fail(c, PERCIS_E_INVAL, "no graph %d", graph);
+        if (!G->has_graph || !G->has_states) return fail(c, PERCIS_E_STATE, "graph %d has no states", graph);
+        ids.push_back(graph);
     }
-    c->opt_slots = saved_slots;
-    c->opt_block = tried ? best.block : saved_block;
-    c->opt_bitmaps = tried ? best.bitmaps : saved_bitmaps;
-    if ((rc = sync_ctx(c))) return rc;
-    free_slots(c);
-    if (!tried) return fail(c, PERCIS_E_DEVICE, "no launch shape could run");
+    int rc;
+    std::vector<TaskSpec> probe;
+    const uint64_t share = std::max<uint64_t>(1, probe_samples / ids.size());
+    uint64_t total = 0;
+    for (int32_t id : ids) {
+        GraphData* G = get_graph(c, id);
+        if ((rc = graph_upload(c, *G, true))) return rc;
+        probe.push_back(TaskSpec{id, 3, 0, share, seed, G->d_hits, false});
+        total += share;
+    }
+    const int64_t act = std::max<int64_t>(1, max_active(c));
+    struct Knobs {
+        int64_t block, bitmaps, compact, slots, balance;
+    };
+    const Knobs saved{c->opt_block, c->opt_bitmaps, c->opt_compact, c->opt_slots, c->opt_balance};
+    auto apply = [&](const Knobs& k) -> int {
+        const bool shape = k.block != c->opt_block || k.bitmaps != c->opt_bitmaps || k.compact != c->opt_compact ||
+                           k.slots != c->opt_slots;
+        c->opt_block = k.block;
+        c->opt_bitmaps = k.bitmaps;
+        c->opt_compact = k.compact;
+        c->opt_slots = k.slots;
+        c->opt_balance = k.balance;
+        int r = sync_ctx(c);
+        if (r == PERCIS_OK && shape) free_slots(c);
+        return r;
+    };
+    // one untimed launch, then the faster of two timed ones; a shape that
+    // cannot run (no memory for its slots, no occupancy) rates 0
+    int timed = 0;
+    auto rate_of = [&](const Knobs& k, double* rate) -> int {
+        *rate = 0.0;
+        int r = apply(k);
+        if (r) return r;
+        percis_stats st{};
+        double best_ms = 0.0;
+        for (int rep = 0; rep < 3; rep++) {
+            r = run_tasks(c, probe, nullptr, &st);
+            if (r != PERCIS_OK && r != PERCIS_E_SIGMA_OVERFLOW) return PERCIS_OK;
+            if (rep > 0 && st.kernel_ms > 0 && (best_ms == 0.0 || st.kernel_ms < best_ms)) best_ms = st.kernel_ms;
+        }
+        timed++;
+        if (best_ms > 0) *rate = (double)total / best_ms * 1e3;
+        return PERCIS_OK;
+    };
+    Knobs best{0, 0, 0, 0, 0};
+    double best_rate = 0.0, auto_rate = 0.0;
+    auto consider = [&](const Knobs& k) -> int {
+        double r = 0.0;
+        int e = rate_of(k, &r);
+        if (e) return e;
+        if (r > best_rate) {
+            best_rate = r;
+            best = k;
+        }
+        return PERCIS_OK;
+    };
+    auto restore = [&]() { (void)apply(saved); };
+    // stage 1: the automatic shape, then threads per sample x where the
+    // visited sets live (device bitmaps, LDS tables, LDS tables on compact slots)
+    if ((rc = consider(best))) return restore(), rc;
+    auto_rate = best_rate;
+    for (int64_t b : {128, 256, 512, 1024}) {
+        if (sampler_table_lds(false, (int)b) + sampler_static_lds() <= kLdsPerCu) {
+            if ((rc = consider(Knobs{b, 2, 1, 0, 0}))) return restore(), rc;
+            if ((rc = consider(Knobs{b, 2, 2, 0, 0}))) return restore(), rc;
+        }
+        if ((rc = consider(Knobs{b, 1, 1, 0, 0}))) return restore(), rc;
+    }
+    if (best_rate <= 0.0) {
+        restore();
+        return fail(c, PERCIS_E_DEVICE, "no launch shape could run");
+    }
+    // stage 2: fewer concurrent samples than fill the device (less pressure on
+    // the L2 and on the memory system)
+    if ((rc = apply(best))) return restore(), rc;
+    if ((rc = ensure_slots(c, act))) return restore(), rc;
+    const int64_t full = c->ncslots > 0 ? c->ncslots : c->nslots;
+    // a slot count turns the automatic choices off: pin what they chose
+    const int64_t chose_compact = c->ncslots > 0 ? 2 : 1, chose_bitmaps = c->shape.lds_sets ? 2 : 1;
+    for (int64_t num : {3, 2}) {
+        const int64_t s = full * num / 4;
+        if (s < 1) continue;
+        Knobs k = best;
+        k.slots = s;
+        k.compact = chose_compact;
+        k.bitmaps = chose_bitmaps;
+        if ((rc = consider(k))) return restore(), rc;
+    }
+    // stage 3: the side rule of the bidirectional search
+    for (int64_t bal : {50, 200}) {
+        Knobs k = best;
+        k.balance = bal;
+        if ((rc = consider(k))) return restore(), rc;
+    }
+    if ((rc = apply(best))) return restore(), rc;
     if ((rc = ensure_slots(c, act))) return rc;
     if (result) {
-        result->block = (int32_t)c->shape.block;
+        const bool cm = c->ncslots > 0;
+        result->block = (int32_t)(cm ? c->cshape.block : c->shape.block);
         result->bitmaps = c->shape.lds_sets ? 2 : 1;
-        result->slots = c->nslots;
-        result->candidates = tried;
+        result->slots = (int32_t)(cm ? c->ncslots : c->nslots);
+        result->candidates = timed;
         result->samples_per_s = best_rate;
+        result->compact = cm ? 2 : 1;
+        result->balance = (int32_t)(c->opt_balance > 0 ? c->opt_balance : kBalance);
+        result->defer_block = cm ? (int32_t)c->shape.block : 0;
+        result->auto_samples_per_s = auto_rate;
     }
     return PERCIS_OK;
 }

@@ -99,7 +99,7 @@ struct percis_ctx {
     uint64_t generation = 0;               // bumped whenever a captured launch's buffers or inputs change
 
     int64_t opt_slots = 0, opt_scratch_mb = 0, opt_block = 0, opt_bitmaps = 0, opt_compact = 0, opt_defer_block = 0;
-    int64_t opt_pair_chunk = 0;
+    int64_t opt_pair_chunk = 0, opt_balance = 0;
     void* noalloc = nullptr;               // this device's copy of the no-allocation scratch
 };
 

@@ -125,6 +125,8 @@ struct PairRec {
 struct SampleLaunch {
     const DevTask* tasks;            // device array
     int ntasks;
+    uint32_t balance;                // the s side grows while its frontier degree sum is at most
+                                     // balance % of the t side's (100: the balanced rule)
     unsigned long long base, count;  // the chunk
     PairRec* pairs;                  // [count] capacity
     unsigned long long* npairs;      // entries listed (written by the pair kernel)

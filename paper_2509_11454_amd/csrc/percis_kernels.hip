@@ -429,6 +429,7 @@ struct SampleShared {
     // the task's counters when the workgroup moves to another task
     unsigned long long acc_samples, acc_reach, acc_sum_I, acc_sum_I2, acc_ovf, acc_first;
     int32_t acc_task;
+    uint32_t balance;     // side rule of plan_level (SampleLaunch::balance)
 };
 
 // Is x in side `side`'s ball? Exact.
@@ -982,7 +983,7 @@ __device__ void push_meeting(const GGraph& g, const GSlots& sl, int64_t so, cons
 // accumulators. Called by one thread.
 template <int TB>
 __device__ __forceinline__ void plan_level(SampleShared& sh) {
-    sh.side = (sh.deg_s <= sh.deg_t) ? 0 : 1;
+    sh.side = (sh.deg_s * 100 <= sh.deg_t * sh.balance) ? 0 : 1;
     sh.tail = sh.side == 0 ? sh.hi_s : sh.hi_t;
     // a level adds at most its frontier degree sum of new nodes
     const unsigned long long deg = sh.side == 0 ? sh.deg_s : sh.deg_t;
@@ -1511,6 +1512,7 @@ __global__ __launch_bounds__(BSZ) SAMPLER_OCCUPANCY void sampler_kernel(DevSlots
         sh.spills = 0;
         sh.deferred = 0;
         sh.walk_errs = 0;
+        sh.balance = L.balance;
         sh.acc_task = -1;
         flush_task_stats(sh, L);
     }
@@ -1555,6 +1557,7 @@ __global__ __launch_bounds__(BSZ) void debug_path_kernel(DevGraph g, DevSlots sl
     }
     if (threadIdx.x == 0) {
         for (int i = 0; i < 5; i++) sh.phase_ticks[i] = 0;
+        sh.balance = 100;
     }
     __syncthreads();
     DevTask T = {};

@@ -18,6 +18,7 @@ HOST_ONLY = -1
 OK, E_INVAL, E_STATE, E_NOMEM, E_DEVICE, E_DEGENERATE, E_TOO_LARGE, E_SIGMA_OVERFLOW = 0, -1, -2, -3, -4, -5, -6, -7
 DIRECTED, DEVICE_PTRS, ACCUMULATE = 0x1, 0x2, 0x4
 OPT_SLOTS, OPT_SCRATCH_MB, OPT_BLOCK, OPT_BITMAPS, OPT_COMPACT, OPT_DEFER_BLOCK, OPT_PAIR_CHUNK = 1, 2, 3, 4, 5, 6, 7
+OPT_BALANCE = 8
 
 if not os.path.exists(LIB_PATH):
     raise ImportError("libpercis.so is not built (%s); run __graft_entry__.build() or "
@@ -67,7 +68,8 @@ class Task(C.Structure):
 
 class Tuning(C.Structure):
     _fields_ = [("block", C.c_int32), ("bitmaps", C.c_int32), ("slots", C.c_int32), ("candidates", C.c_int32),
-                ("samples_per_s", C.c_double)]
+                ("samples_per_s", C.c_double), ("compact", C.c_int32), ("balance", C.c_int32),
+                ("defer_block", C.c_int32), ("auto_samples_per_s", C.c_double)]
 
     def to_dict(self):
         return {k: (float(getattr(self, k)) if t is C.c_double else int(getattr(self, k))) for k, t in self._fields_}

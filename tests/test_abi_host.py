@@ -156,6 +156,18 @@ def test_option_validation(P):
     assert e.value.status == P.E_INVAL
     c.set_option(P.OPT_PAIR_CHUNK, 0)
     assert c.get_option(P.OPT_PAIR_CHUNK) == 1 << 24
+    assert c.get_option(P.OPT_BALANCE) == 100   # the balanced rule
+    for v in (25, 50, 200, 400):
+        c.set_option(P.OPT_BALANCE, v)
+        assert c.get_option(P.OPT_BALANCE) == v
+    for v in (1, 24, 401):
+        with pytest.raises(P.PercisError):
+            c.set_option(P.OPT_BALANCE, v)
+    c.set_option(P.OPT_BALANCE, 0)
+    assert c.get_option(P.OPT_BALANCE) == 100
+    with pytest.raises(P.PercisError) as e:   # nothing to time on a host-only context
+        c.autotune(-1, 1000)
+    assert e.value.status == P.E_STATE
 
 
 def test_batch_capture_needs_a_device(P):

@@ -425,16 +425,60 @@ def test_tasks_many_graphs_one_launch():
 
 
 def test_autotune_keeps_results():
+    """The staged search times the automatic shape, 4 block sizes on device
+    bitmaps, LDS tables and compact slots, two slot counts and two side
+    rules; the knobs it keeps are the context's options and leave every
+    result unchanged, on one graph and over all resident graphs (-1)."""
+    import torch
     from paper_2509_11454_amd import percis as P
     g, k = W.workload_er1000()
     c = gpu_context(g, k)
     h0, s0 = gpu_hits(c, 0, 4000, 17)
     t = c.autotune(0, 5000)
-    assert t["candidates"] >= 3 and t["block"] in (256, 512, 1024) and t["bitmaps"] in (1, 2)
-    assert c.get_option(P.OPT_BLOCK) == t["block"]
+    print("autotune:", t, flush=True)
+    assert t["candidates"] >= 12 and t["block"] in (64, 128, 256, 512, 1024) and t["bitmaps"] in (1, 2)
+    assert t["compact"] in (1, 2) and t["balance"] in (50, 100, 200)
+    assert t["samples_per_s"] >= t["auto_samples_per_s"] > 0
+    assert c.get_option(P.OPT_BLOCK) == t["block"] and c.get_option(P.OPT_BALANCE) == t["balance"]
+    assert c.get_option(P.OPT_COMPACT) == t["compact"] and c.get_option(P.OPT_SLOTS) == t["slots"]
     h1, s1 = gpu_hits(c, 0, 4000, 17)
     assert np.array_equal(h0, h1)
     same_stats(s0, s1)
+    g2, k2 = special_cases()[4]
+    gid = c.add_graph(g2.n, g2.row_ptr, g2.col, k2)
+    t2 = c.autotune(-1, 8000)
+    assert t2["candidates"] >= 12
+    h2, s2 = gpu_hits(c, 0, 4000, 17)
+    assert np.array_equal(h0, h2)
+    same_stats(s0, s2)
+    og, st = oracle_objects(g2, k2)
+    ho, so = oracle_hits(og, st, 0, 3000, 5)
+    hits = torch.zeros(g2.n, dtype=torch.int32, device="cuda")
+    (sg,), _ = c.sample_tasks([dict(graph=gid, first=0, count=3000, seed=5, phase=0, hits=hits)])
+    assert np.array_equal(ho, hits.cpu().numpy().view(np.uint32))
+    same_stats(so, sg)
+
+
+@pytest.mark.parametrize("compact", [1, 2])
+def test_side_rule_keeps_results(compact):
+    """PERCIS_OPT_BALANCE only changes which ball grows: hits and sample
+    statistics equal the oracle's under the rules 25, 100 and 400, on a
+    skewed R-MAT graph and on a directed one, per-node and compact slots."""
+    from paper_2509_11454_amd import percis as P
+    rng = np.random.default_rng(31)
+    cases = [W.rmat_graph(12, 8, seed=3), W.rmat_graph(11, 8, seed=4, directed=True)]
+    for g in cases:
+        k = W.skewed_states(g.n, rng, zero_frac=0.5)
+        og, st = oracle_objects(g, k)
+        ho, so = oracle_hits(og, st, 0, 6000, 23)
+        c = gpu_context(g, k)
+        c.set_option(P.OPT_COMPACT, compact)
+        for bal in (25, 100, 400):
+            c.set_option(P.OPT_BALANCE, bal)
+            hg, sg = gpu_hits(c, 0, 6000, 23)
+            assert np.array_equal(ho, hg), (g.name, bal)
+            same_stats(so, sg)
+        c.close()
 
 
 @pytest.mark.parametrize("ci", [0, 4, 6, 8, 11, 13, 15])

@@ -9,7 +9,7 @@ to its truncated BFS by the CPU tests):
   the compact slots and of samples whose visited set spilled to device
   memory, and the step itself by additivity;
 - 64 Barabasi-Albert graphs: every graph's 10^5 samples from inside the one
-  captured, autotuned launch;
+  captured launch, with the knobs the autotuner chose over all 64 graphs;
 - serving: one query per resident graph (66), each the same in the mix,
   alone in the server, through percis_graph_estimate and from the oracle's
   phase-1 statistics and phase-2 hits.
@@ -87,8 +87,8 @@ def test_rmat24_directed_window_and_full_step():
 
 @pytest.mark.timeout(900)
 def test_ba64_captured_launch_full_parity():
-    """The benchmark's batch: 64 BA graphs, the shape autotuned on the
-    largest, 10^5 samples per graph (seed 1 + graph index) in one captured
+    """The benchmark's batch: 64 BA graphs, the knobs autotuned over all
+    of them, 10^5 samples per graph (seed 1 + graph index) in one captured
     launch; each graph's hits and statistics from the replay equal the
     oracle's over the same 10^5 samples."""
     import torch
@@ -99,8 +99,7 @@ def test_ba64_captured_launch_full_parity():
     c.load_csr(g0.n, g0.row_ptr, g0.col)
     c.set_states(k0)
     ids = [0] + [c.add_graph(g.n, g.row_ptr, g.col, kk) for g, kk in graphs[1:]]
-    big = max(range(64), key=lambda i: graphs[i][0].n)
-    tune = c.autotune(ids[big], 20000)
+    tune = c.autotune(-1, 200_000)
     print("autotune:", tune, flush=True)
     per = 100_000
     hits = [torch.zeros(g.n, dtype=torch.int32, device="cuda") for g, _ in graphs]
