@@ -12,19 +12,25 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "percis_oracle.c")
-_LIB = os.path.join(_HERE, "liboracle.so")
+# PERCIS_ORACLE_LIB names a prebuilt copy to load instead (the sanitizer run)
+_LIB = os.environ.get("PERCIS_ORACLE_LIB") or os.path.join(_HERE, "liboracle.so")
 _lib = None
 
 
-def build(force=True):
-    """Compile the oracle with gcc into oracle/liboracle.so."""
-    if not force and os.path.exists(_LIB) and os.path.getmtime(_LIB) >= os.path.getmtime(_SRC):
-        return _LIB
-    tmp = _LIB + ".tmp%d" % os.getpid()
-    subprocess.check_call(["gcc", "-O2", "-std=c11", "-shared", "-fPIC", "-Wall", "-Wextra",
-                           "-Wno-unused-parameter", "-o", tmp, _SRC, "-lm"])
-    os.replace(tmp, _LIB)
-    return _LIB
+def build(force=True, sanitize=False, out=None):
+    """Compile the oracle with gcc into oracle/liboracle.so; sanitize=True
+    builds a copy at `out` with clang's AddressSanitizer and
+    UndefinedBehaviorSanitizer (one runtime with the library's host code)."""
+    lib = out or _LIB
+    if not sanitize and not force and os.path.exists(lib) and os.path.getmtime(lib) >= os.path.getmtime(_SRC):
+        return lib
+    tmp = lib + ".tmp%d" % os.getpid()
+    cc = ["/opt/rocm/llvm/bin/clang", "-fsanitize=address,undefined", "-fno-omit-frame-pointer",
+          "-fno-sanitize-recover=undefined"] if sanitize else ["gcc"]
+    subprocess.check_call(cc + ["-O2", "-std=c11", "-shared", "-fPIC", "-Wall", "-Wextra",
+                                "-Wno-unused-parameter", "-o", tmp, _SRC, "-lm"])
+    os.replace(tmp, lib)
+    return lib
 
 
 class _Stats(C.Structure):

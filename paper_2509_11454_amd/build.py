@@ -1,6 +1,10 @@
 """Builds the HIP library libpercis.so for gfx950, in-tree.
 
     python -m paper_2509_11454_amd.build
+
+build(sanitize=True, out=PATH) builds a copy whose host code carries
+AddressSanitizer and UndefinedBehaviorSanitizer checks (device code is built
+as usual); a process that loads it must preload clang's ASan runtime.
 """
 import os
 import subprocess
@@ -30,13 +34,22 @@ def hipcc():
     raise RuntimeError("hipcc not found")
 
 
-def build(verbose=False):
-    os.makedirs(LIBDIR, exist_ok=True)
+# host-only sanitizer flags: each -fsanitize= is passed to the host compile
+# and link only
+SANITIZE_FLAGS = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+                  "-Xarch_host", "-fno-omit-frame-pointer", "-Xarch_host", "-fno-sanitize-recover=undefined"]
+
+
+def build(verbose=False, sanitize=False, out=None):
+    lib = out or LIB
+    objdir = os.path.dirname(lib)
+    os.makedirs(objdir, exist_ok=True)
+    extra = SANITIZE_FLAGS if sanitize else []
     objs = []
     for src in SOURCES:
         path = os.path.join(CSRC, src)
-        obj = os.path.join(LIBDIR, src + ".o")
-        cmd = [hipcc()] + HIPCC_FLAGS + ["-I", os.path.join(ROOT, "include"), "-I", CSRC]
+        obj = os.path.join(objdir, src + ".o")
+        cmd = [hipcc()] + HIPCC_FLAGS + extra + ["-I", os.path.join(ROOT, "include"), "-I", CSRC]
         if src.endswith(".cpp"):
             cmd += ["-x", "hip"]
         cmd += ["-c", path, "-o", obj]
@@ -44,15 +57,15 @@ def build(verbose=False):
             print(" ".join(cmd), flush=True)
         subprocess.check_call(cmd)
         objs.append(obj)
-    tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [hipcc(), "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + objs
+    tmp = lib + ".tmp%d" % os.getpid()
+    cmd = [hipcc(), "--offload-arch=" + ARCH, "-shared", "-fPIC"] + extra + ["-o", tmp] + objs
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
-    os.replace(tmp, LIB)
+    os.replace(tmp, lib)
     for o in objs:
         os.remove(o)
-    return LIB
+    return lib
 
 
 if __name__ == "__main__":

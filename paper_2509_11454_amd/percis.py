@@ -12,7 +12,8 @@ import numpy as np
 import torch  # loaded first: libpercis then binds to the same HIP runtime
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "lib", "libpercis.so")
+# PERCIS_LIB_PATH names another build to load (the sanitizer run)
+LIB_PATH = os.environ.get("PERCIS_LIB_PATH") or os.path.join(_HERE, "lib", "libpercis.so")
 
 HOST_ONLY = -1
 OK, E_INVAL, E_STATE, E_NOMEM, E_DEVICE, E_DEGENERATE, E_TOO_LARGE, E_SIGMA_OVERFLOW = 0, -1, -2, -3, -4, -5, -6, -7
