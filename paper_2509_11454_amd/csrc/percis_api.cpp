@@ -58,6 +58,7 @@ static void graph_free_device(GraphData& G) {
     if (G.d_icol != G.d_col) dfree(G.d_icol); else G.d_icol = nullptr;
     dfree(G.d_rp);
     dfree(G.d_col);
+    G.d_ccol = nullptr;  // inside the in-row buffer
     dfree(G.d_orig);
     dfree(G.d_newid);
     dfree(G.d_hits);
@@ -71,6 +72,7 @@ static void graph_clear(GraphData& G) {
     G.h_col.clear();
     G.h_irp.clear();
     G.h_icol.clear();
+    G.h_ccol.clear();
     G.h_orig.clear();
     G.h_newid.clear();
     G.has_graph = false;
@@ -116,19 +118,31 @@ static int graph_load(percis_ctx* c, GraphData& G, int32_t n, int64_t m, const i
                     return fail(c, PERCIS_E_INVAL, "undirected graph lacks arc %d -> %d (reverse of %d -> %d)", v, u, u, v);
             }
     }
-    // internal ids: nodes with an arc first (in caller order), then the rest;
-    // keeping the order of nodes with arcs keeps every row sorted
-    std::vector<uint8_t> has_arc(n, 0);
-    for (int32_t u = 0; u < n; u++)
-        if (rp[u + 1] > rp[u]) has_arc[u] = 1;
-    for (int64_t e = 0; e < m; e++) has_arc[cl[e]] = 1;
+    // Internal ids: nodes with an arc first, by degree (out + in) from the
+    // largest down, ties in caller order; then the nodes without arcs. The
+    // arcs a search touches mostly end at high-degree nodes, so their node
+    // records, bitmap words and row bounds share cache lines.
+    std::vector<int64_t> deg(n, 0);
+    for (int32_t u = 0; u < n; u++) deg[u] = rp[u + 1] - rp[u];
+    if (directed)
+        for (int64_t e = 0; e < m; e++) deg[cl[e]]++;
+    int64_t dmax = 0;
+    for (int32_t u = 0; u < n; u++) dmax = std::max(dmax, deg[u]);
     std::vector<int32_t> newid(n), orig(n);
-    int32_t next = 0;
-    for (int32_t v = 0; v < n; v++)
-        if (has_arc[v]) { newid[v] = next; orig[next] = v; next++; }
-    const int32_t n_act = next;
-    for (int32_t v = 0; v < n; v++)
-        if (!has_arc[v]) { newid[v] = next; orig[next] = v; next++; }
+    {
+        // counting sort on degree, largest first, stable in caller order
+        std::vector<int64_t> start((size_t)dmax + 2, 0);
+        for (int32_t u = 0; u < n; u++) start[(size_t)(dmax - deg[u]) + 1]++;
+        for (size_t d = 1; d < start.size(); d++) start[d] += start[d - 1];
+        for (int32_t u = 0; u < n; u++) {
+            const int32_t id = (int32_t)start[(size_t)(dmax - deg[u])]++;
+            newid[u] = id;
+            orig[id] = u;
+        }
+    }
+    int32_t n_act = 0;
+    while (n_act < n && deg[orig[n_act]] > 0) n_act++;
+    std::vector<int64_t>().swap(deg);
     std::vector<int32_t> rp2(n + 1, 0), cl2((size_t)m);
     for (int32_t i = 0; i < n; i++) {
         const int32_t v = orig[i];
@@ -139,16 +153,25 @@ static int graph_load(percis_ctx* c, GraphData& G, int32_t n, int64_t m, const i
     graph_clear(G);
     if (directed) {
         // in-adjacency by a counting sort on the head; scanning tails in
-        // increasing order keeps every in-row sorted
+        // caller order keeps every in-row in caller order
         std::vector<int32_t> irp(n + 1, 0), icl((size_t)m);
         for (int64_t e = 0; e < m; e++) irp[cl2[e] + 1]++;
         for (int32_t v = 0; v < n; v++) irp[v + 1] += irp[v];
         std::vector<int32_t> pos(irp.begin(), irp.end() - 1);
-        for (int32_t u = 0; u < n; u++)
+        for (int32_t v = 0; v < n; v++) {
+            const int32_t u = newid[v];
             for (int32_t e = rp2[u]; e < rp2[u + 1]; e++) icl[pos[cl2[e]]++] = u;
+        }
+        // the canonical walk reads in-rows in caller order; the searches read
+        // them sorted by internal id
+        G.h_ccol = icl;
+        for (int32_t v = 0; v < n; v++) std::sort(icl.begin() + irp[v], icl.begin() + irp[v + 1]);
         G.h_irp.swap(irp);
         G.h_icol.swap(icl);
+    } else {
+        G.h_ccol = cl2;
     }
+    for (int32_t v = 0; v < n; v++) std::sort(cl2.begin() + rp2[v], cl2.begin() + rp2[v + 1]);
     G.h_rp.swap(rp2);
     G.h_col.swap(cl2);
     G.h_orig.swap(orig);
@@ -246,19 +269,23 @@ int graph_upload(percis_ctx* c, GraphData& G, bool states) {
     const int32_t n = G.n;
     const int64_t m = G.m;
     if (!G.graph_on_device) {
+        // the in-row buffer (col itself if undirected) holds 2m entries: the
+        // in-rows sorted by internal id, then the same rows in caller order
         if ((rc = dalloc(c, G.d_rp, (size_t)n + 1))) return rc;
-        if ((rc = dalloc(c, G.d_col, (size_t)m))) return rc;
+        if ((rc = dalloc(c, G.d_col, (size_t)(G.directed ? m : 2 * m)))) return rc;
         HIPCHK(c, hipMemcpy(G.d_rp, G.h_rp.data(), sizeof(int32_t) * (n + 1), hipMemcpyHostToDevice));
         if (m) HIPCHK(c, hipMemcpy(G.d_col, G.h_col.data(), sizeof(int32_t) * m, hipMemcpyHostToDevice));
         if (G.directed) {
             if ((rc = dalloc(c, G.d_irp, (size_t)n + 1))) return rc;
-            if ((rc = dalloc(c, G.d_icol, (size_t)m))) return rc;
+            if ((rc = dalloc(c, G.d_icol, (size_t)(2 * m)))) return rc;
             HIPCHK(c, hipMemcpy(G.d_irp, G.h_irp.data(), sizeof(int32_t) * (n + 1), hipMemcpyHostToDevice));
             if (m) HIPCHK(c, hipMemcpy(G.d_icol, G.h_icol.data(), sizeof(int32_t) * m, hipMemcpyHostToDevice));
         } else {
             G.d_irp = G.d_rp;
             G.d_icol = G.d_col;
         }
+        G.d_ccol = G.d_icol + m;
+        if (m) HIPCHK(c, hipMemcpy(G.d_ccol, G.h_ccol.data(), sizeof(int32_t) * m, hipMemcpyHostToDevice));
         if ((rc = dalloc(c, G.d_hits, (size_t)n))) return rc;
         if ((rc = dalloc(c, G.d_orig, (size_t)n))) return rc;
         if ((rc = dalloc(c, G.d_newid, (size_t)n))) return rc;
@@ -278,6 +305,7 @@ static DevGraph dev_graph(const GraphData& G) {
     g.col = G.d_col;
     g.irp = G.d_irp;
     g.icol = G.d_icol;
+    g.ccol = G.d_ccol;
     g.orig = G.d_orig;
     return g;
 }
@@ -584,7 +612,8 @@ int vertex_diam_ub(percis_ctx* c, GraphData& G, int64_t* D) {
     int64_t d = 0;
     int32_t levels = 0, rounds = 0;
     const hipError_t e =
-        run_vertex_diam_ub(G.d_rp, G.d_col, G.n_act, G.m, G.directed, scratch, &d, &levels, &rounds, c->stream);
+        run_vertex_diam_ub(G.d_rp, G.d_col, G.d_orig, G.n_act, G.m, G.directed, scratch, &d, &levels, &rounds,
+                           c->stream);
     (void)hipFree(scratch);
     if (e != hipSuccess) return fail(c, PERCIS_E_DEVICE, "VertexDiamUB: %s", hipGetErrorString(e));
     G.D_cached = d;

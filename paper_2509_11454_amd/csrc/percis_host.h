@@ -19,9 +19,11 @@ struct GraphData {
     int64_t m = 0;
     std::vector<int32_t> h_rp, h_col;      // out-adjacency, rows sorted
     std::vector<int32_t> h_irp, h_icol;    // in-adjacency (directed graphs only)
+    std::vector<int32_t> h_ccol;           // in-rows with entries in caller id order (the canonical walk)
     std::vector<int32_t> h_orig, h_newid;  // internal id -> caller id, and back
     bool graph_on_device = false;
     int32_t *d_rp = nullptr, *d_col = nullptr, *d_irp = nullptr, *d_icol = nullptr, *d_orig = nullptr;
+    int32_t* d_ccol = nullptr;
     uint32_t* d_hits = nullptr;            // hits buffer owned by the library
 
     int32_t* d_newid = nullptr;            // caller id -> internal id (device)

@@ -7,10 +7,11 @@
 namespace percis {
 
 // Device view of the graph in internal node ids: nodes with at least one
-// arc get ids 0..n_act-1 in increasing order of the caller's ids, nodes
-// without arcs follow. Relative order among nodes with arcs is kept, so the
-// ascending-id order of predecessors (which fixes the canonical path) is the
-// caller's order. Rows are sorted by increasing id.
+// arc get ids 0..n_act-1 by degree (out + in), largest first, ties in caller
+// order; nodes without arcs follow. Rows and in-rows are sorted by internal
+// id, so the lanes that share a row touch neighbouring records. The
+// canonical path takes predecessors in ascending caller id: ccol holds the
+// in-rows again with their entries in that order.
 struct DevGraph {
     int32_t n;
     int32_t n_act;
@@ -18,6 +19,7 @@ struct DevGraph {
     const int32_t* col;   // [m]
     const int32_t* irp;   // [n+1] in-adjacency (same arrays if undirected)
     const int32_t* icol;  // [m]
+    const int32_t* ccol;  // [m] in-rows (bounds irp), entries in ascending caller id; = icol + m
     const int32_t* orig;  // [n] internal id -> caller's id
 };
 

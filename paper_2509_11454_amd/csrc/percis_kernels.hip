@@ -102,7 +102,7 @@ struct GGraph {
     const G<int32_t>* rp;
     const G<int32_t>* col;
     const G<int32_t>* irp;
-    const G<int32_t>* icol;
+    const G<int32_t>* icol;  // the caller-ordered in-rows follow at icol + m (m = irp[n])
     const G<int32_t>* orig;
 };
 __device__ __forceinline__ GGraph gview(const DevGraph& g) {
@@ -978,6 +978,76 @@ __device__ void push_meeting(const GGraph& g, const GSlots& sl, int64_t so, cons
     }
 }
 
+// One step of the canonical walk with kc > KCAP predecessors, the arcs into
+// w among arcs[a_lo, a_hi): lists them in xb[0, kc) as (internal id, caller
+// id, sigma_s low, high), then finds the predecessor of smallest caller id
+// whose cumulative sigma_s in caller id order exceeds r by radix selection
+// on the caller ids (below 2^25, digits of 7 + 6 + 6 + 6 bits): each round
+// sums sigma_s per digit value over the entries with the digits fixed so far
+// (histogram in LDS) and fixes the digit where the cumulative sum passes r.
+// Subtracts from r the sigma_s of the predecessors passed over. One wave;
+// returns -1 if r is not below the total. Kept out of line so that the
+// sampler's main body does not carry its registers.
+__device__ __noinline__ int32_t walk_select_radix(const G<DagArc>* arcs, int32_t a_lo, int32_t a_hi, int32_t w,
+                                                  const G<int32_t>* orig, G<u32x4>* xb, int kc, uint64_t& r,
+                                                  uint64_t* hist) {
+    const int lane = (int)(threadIdx.x & 63);
+    const unsigned long long below = (1ull << lane) - 1;
+    int n = 0;
+    for (int base = a_lo; base < a_hi; base += 64) {
+        const int i = base + lane;
+        bool m = false;
+        u32x4 av = u32x4{0u, 0u, 0u, 0u};
+        if (i < a_hi) {
+            av = *reinterpret_cast<const G<u32x4>*>(arcs + i);
+            m = (int32_t)av.y == w;
+        }
+        const unsigned long long bal = __ballot(m);
+        const int pos = n + __popcll(bal & below);
+        if (m && pos < kc) xb[pos] = u32x4{av.x, (uint32_t)orig[(int32_t)av.x], av.z, av.w};
+        n += __popcll(bal);
+    }
+    if (n != kc) return -1;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    uint32_t prefix = 0;
+    int hi = 25;
+    for (int d = 0; d < 4; d++) {
+        const int nb = d == 0 ? 7 : 6, lo = hi - nb, nbk = 1 << nb;
+        for (int b = lane; b < nbk; b += 64) hist[b] = 0;
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        for (int i = lane; i < kc; i += 64) {
+            const u32x4 e = xb[i];
+            if ((e.y >> hi) == prefix)
+                atomicAdd((unsigned long long*)&hist[(e.y >> lo) & (nbk - 1)], ((unsigned long long)e.w << 32) | e.z);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        const uint64_t b0 = 2 * lane < nbk ? hist[2 * lane] : 0;
+        const uint64_t b1 = 2 * lane + 1 < nbk ? hist[2 * lane + 1] : 0;
+        const uint64_t incl = wave_incl_scan_u64(b0 + b1);
+        const unsigned long long over = __ballot(incl > r);
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        if (!over) return -1;
+        const int l = __ffsll((long long)over) - 1;
+        const uint64_t before = lane_u64(incl - b0 - b1, l), first = lane_u64(b0, l);
+        const bool upper = r >= before + first;
+        r -= upper ? before + first : before;
+        prefix = (prefix << nb) | (uint32_t)(2 * l + (upper ? 1 : 0));
+        hi = lo;
+    }
+    for (int base = 0; base < kc; base += 64) {
+        const int i = base + lane;
+        int32_t u = -1;
+        if (i < kc) {
+            const u32x4 e = xb[i];
+            if (e.y == prefix) u = (int32_t)e.x;
+        }
+        const unsigned long long f = __ballot(u >= 0);
+        if (f) return lane_i32(u, __ffsll((long long)f) - 1);
+    }
+    return -1;
+}
+
 // Next BFS level: the side with the smaller frontier degree sum (Section
 // III-B's balanced expansion), its queue's append position, fresh
 // accumulators. Called by one thread.
@@ -1239,22 +1309,27 @@ __device__ __forceinline__ void run_sample(const GGraph& g, const GSlots& sl, in
         // ---- canonical backward walk by wave 0
         // The predecessors of the current node w are the DAG arcs into w that
         // the search recorded (each with sigma_s of its tail); the walk takes
-        // the one of smallest id whose cumulative sigma_s, in id order, exceeds
-        // r. Without a complete arc list (or with more than KCAP
-        // predecessors) a step scans w's in-row instead: the same choice.
+        // the one of smallest caller id whose cumulative sigma_s, in caller id
+        // order, exceeds r. Without a complete arc list (or with more than
+        // KCAP predecessors) a step scans w's in-row instead, whose entries
+        // are in caller id order: the same choice.
         // (a debug call's path index past sigma_st gets L and sigma_st only)
         if (!sh.ovf && wid == 0 && !(dbg && dbg_r >= sh.sigma)) {
             const int32_t aM = sh.a;
             uint64_t r = dbg ? dbg_r : draw_bounded(T.seed, T.phase, idx, 2, sh.sigma);
             const int32_t na = __builtin_amdgcn_readfirstlane(sh.narcs);
             const G<DagArc>* arcs = sl.arcs + (int64_t)blockIdx.x * sl.acap;
+            // a step with more than KCAP predecessors lists them in the slot's
+            // device list, free after the search
+            G<u32x4>* xb = reinterpret_cast<G<u32x4>*>(sl.mlx + (int64_t)blockIdx.x * sl.mlxcap * 2);
+            const int xcap = sl.mlxcap / 2;
             const unsigned long long below = (1ull << lane) - 1;  // lanes under this one
             int32_t w = sh.t;
             int err = 0;
             for (int32_t p = L - 1; p >= 1; p--) {
                 const bool on_s = p <= aM;
                 int32_t sel = -1;
-                int kc = KCAP + 1;
+                int kc = INT32_MAX;  // predecessors in the list (INT32_MAX: no complete list)
                 // the arcs into w (at distance p + 1): its stage's segment of the
                 // list when kept, else the whole list; usable if none was dropped
                 int32_t a_lo = 0, a_hi = na;
@@ -1293,40 +1368,52 @@ __device__ __forceinline__ void run_sample(const GGraph& g, const GSlots& sl, in
                     }
                     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
                     if (kc <= KCAP) {
-                        int32_t ui = INT32_MAX;
-                        uint64_t wi = 0, ci = 0;  // weight, cumulative weight up to and with ui
+                        // order by caller id: each lane swaps its predecessor's
+                        // internal id in the list for the caller's
+                        int32_t ui = -1, uo = INT32_MAX;
+                        uint64_t wi = 0, ci = 0;  // weight, cumulative weight up to and with uo
                         if (lane < kc) {
                             ui = sh.wk_u[lane];
                             wi = sh.wk_w[lane];
+                            uo = g.orig[ui];
                         }
+                        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+                        if (lane < kc) sh.wk_u[lane] = uo;
+                        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
                         for (int j = 0; j < kc; j++)
-                            if (sh.wk_u[j] <= ui) ci += sh.wk_w[j];
+                            if (sh.wk_u[j] <= uo) ci += sh.wk_w[j];
                         const bool cand = lane < kc && ci > r;
-                        int32_t best = cand ? ui : INT32_MAX;
+                        int32_t best = cand ? uo : INT32_MAX;
 #pragma unroll
                         for (int o = 32; o > 0; o >>= 1) best = min(best, __shfl_xor(best, o, 64));
                         best = __builtin_amdgcn_readfirstlane(best);
                         if (best != INT32_MAX) {
-                            const unsigned long long hit = __ballot(cand && ui == best);
+                            const unsigned long long hit = __ballot(cand && uo == best);
                             const int l = __ffsll((long long)hit) - 1;
                             r -= lane_u64(ci, l) - lane_u64(wi, l);
-                            sel = best;
+                            sel = lane_i32(ui, l);
                         }
+                    } else if (CMP && kc <= xcap) {
+                        // (compact slots only: the call costs the per-node
+                        // kernels' searches more registers than it saves)
+                        sel = walk_select_radix(arcs, a_lo, a_hi, w, g.orig, xb, kc, r, sh.sig);
                     }
                     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
                 }
-                if (kc > KCAP) {
-                    // in-row scan: in-neighbours one level closer to s (s-level p,
-                    // or t-level L - p past the meeting layer), weighed by sigma_s
+                if (kc > (CMP ? xcap : KCAP)) {
+                    // in-row scan in caller id order: in-neighbours one level closer
+                    // to s (s-level p, or t-level L - p past the meeting layer),
+                    // weighed by sigma_s
                     const uint32_t want = on_s ? (uint32_t)p + 1 : (uint32_t)(L - p) + 1;
                     const int32_t beg = lane_i32(g.irp[w], 0), end = lane_i32(g.irp[w + 1], 0);
+                    const G<int32_t>* ccol = g.icol + lane_i32(g.irp[g.n], 0);
                     for (int32_t base = beg; base < end && sel < 0; base += 64 * WALK_UNROLL) {
                         int32_t u[WALK_UNROLL];
                         uint64_t wt[WALK_UNROLL];
 #pragma unroll
                         for (int k = 0; k < WALK_UNROLL; k++) {
                             const int32_t i = base + k * 64 + lane;
-                            u[k] = i < end ? g.icol[i] : -1;
+                            u[k] = i < end ? ccol[i] : -1;
                         }
 #pragma unroll
                         for (int k = 0; k < WALK_UNROLL; k++) {
@@ -1767,7 +1854,7 @@ __device__ bool wide_walk(const DevGraph& g, const int32_t* dist, const u128* si
     for (int32_t pos = L; pos >= 1; pos--) {
         int32_t next = -1;
         for (int32_t e = g.irp[w]; e < g.irp[w + 1]; e++) {
-            const int32_t u = g.icol[e];
+            const int32_t u = g.ccol[e];  // ascending caller id
             if (dist[u] != pos - 1) continue;
             if (r < sig[u]) { next = u; break; }
             r -= sig[u];

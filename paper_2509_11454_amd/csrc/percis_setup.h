@@ -33,12 +33,14 @@ hipError_t launch_state_build(const StateArrays& a, void* scratch, const uint64_
 
 // VertexDiamUB: connected components of the active nodes (weakly connected for
 // directed graphs), their sizes and, for undirected graphs, the eccentricity
-// of each component's smallest node. Scratch holds diam_scratch_bytes(n_act, m)
-// bytes; m = rp[n_act] arcs. The host drives the hooking rounds and the BFS
-// levels, so the call synchronises `stream`.
+// of each component's node of smallest caller id (orig: internal id -> caller
+// id). Scratch holds diam_scratch_bytes(n_act, m) bytes; m = rp[n_act] arcs.
+// The host drives the hooking rounds and the BFS levels, so the call
+// synchronises `stream`.
 int64_t diam_scratch_bytes(int32_t n_act, int64_t m);
-hipError_t run_vertex_diam_ub(const int32_t* rp, const int32_t* col, int32_t n_act, int64_t m, bool directed,
-                              void* scratch, int64_t* D_out, int32_t* levels_out, int32_t* rounds_out, hipStream_t stream);
+hipError_t run_vertex_diam_ub(const int32_t* rp, const int32_t* col, const int32_t* orig, int32_t n_act, int64_t m,
+                              bool directed, void* scratch, int64_t* D_out, int32_t* levels_out, int32_t* rounds_out,
+                              hipStream_t stream);
 
 // *out := max(*out, bits of max_v d_v h_v) over v < n (non-negative doubles
 // order like their bit patterns). *out must be initialised by the caller.

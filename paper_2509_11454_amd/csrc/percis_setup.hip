@@ -12,7 +12,8 @@
 // * VertexDiamUB of Algorithm 1 (Section III-B): connected components of the
 //   active nodes by min-label hooking with pointer jumping (weakly connected
 //   components for directed graphs); for undirected graphs one multi-source
-//   BFS from every component's smallest node gives that node's eccentricity,
+//   BFS from every component's node of smallest caller id gives that node's
+//   eccentricity,
 //   and a component bounds the vertex diameter by min(|C| - 2, 2 ecc - 1);
 //   for directed graphs by |C| - 2.
 // * The largest phase-1 weight max_v d_v h_v (the bound of Proposition 3 is
@@ -161,6 +162,10 @@ hipError_t run_scan(const F& f, int64_t count, T* sums, hipStream_t stream) {
 // ---------------------------------------------------------------------------
 // State build.
 // ---------------------------------------------------------------------------
+
+__global__ void fill_i32_kernel(int32_t* p, int64_t count, int32_t value) {
+    for (int64_t i = gtid(); i < count; i += gstride()) p[i] = value;
+}
 
 __global__ void zero_u32_kernel(uint32_t* p, int64_t count) {
     for (int64_t i = gtid(); i < count; i += gstride()) p[i] = 0u;
@@ -447,12 +452,19 @@ __global__ void wcc_compress_kernel(int32_t* parent, int32_t na) {
     }
 }
 
-// dist := 0 at roots (each component's smallest node), -1 elsewhere; the
-// roots form the first BFS frontier; ctr[1] counts them.
-__global__ void bfs_init_kernel(const int32_t* parent, int32_t na, int32_t* dist, int32_t* q, uint32_t* ctr) {
+// first[c] := the smallest caller id in component c (c = its hooking root);
+// first must hold INT32_MAX at the component roots.
+__global__ void comp_first_kernel(const int32_t* parent, const int32_t* orig, int32_t na, int32_t* first) {
+    for (int64_t v = gtid(); v < na; v += gstride()) atomicMin(&first[parent[v]], orig[v]);
+}
+
+// dist := 0 at each component's BFS root (its node of smallest caller id),
+// -1 elsewhere; the roots form the first BFS frontier; ctr[1] counts them.
+__global__ void bfs_init_kernel(const int32_t* parent, const int32_t* orig, const int32_t* first, int32_t na,
+                                int32_t* dist, int32_t* q, uint32_t* ctr) {
     const int64_t na_pad = ((int64_t)na + 63) / 64 * 64;
     for (int64_t v = gtid(); v < na_pad; v += gstride()) {
-        const bool root = v < na && parent[v] == v;
+        const bool root = v < na && orig[v] == first[parent[v]];
         if (v < na) dist[v] = root ? 0 : -1;
         const uint64_t bal = __ballot(root);
         uint32_t at = 0;
@@ -659,8 +671,9 @@ int64_t diam_scratch_bytes(int32_t n_act, int64_t m) {
     return 6 * ((4 * na + 255) / 256 * 256) + 256 + max_segments((int32_t)na, m) * (int64_t)sizeof(int2);
 }
 
-hipError_t run_vertex_diam_ub(const int32_t* rp, const int32_t* col, int32_t na, int64_t m, bool directed,
-                              void* scratch, int64_t* D_out, int32_t* levels_out, int32_t* rounds_out, hipStream_t stream) {
+hipError_t run_vertex_diam_ub(const int32_t* rp, const int32_t* col, const int32_t* orig, int32_t na, int64_t m,
+                              bool directed, void* scratch, int64_t* D_out, int32_t* levels_out, int32_t* rounds_out,
+                              hipStream_t stream) {
     *D_out = 0;
     *levels_out = 0;
     *rounds_out = 0;
@@ -698,7 +711,11 @@ hipError_t run_vertex_diam_ub(const int32_t* rp, const int32_t* col, int32_t na,
     const int32_t* dist_arg = nullptr;
     const int32_t* ecc_arg = nullptr;
     if (!directed) {
-        hipLaunchKernelGGL(bfs_init_kernel, dim3(g), dim3(EB), 0, stream, (const int32_t*)parent, na, dist, qa, ctr);
+        // qb (free until the first level) holds each component's smallest caller id
+        hipLaunchKernelGGL(fill_i32_kernel, dim3(g), dim3(EB), 0, stream, qb, (int64_t)na, INT32_MAX);
+        hipLaunchKernelGGL(comp_first_kernel, dim3(g), dim3(EB), 0, stream, (const int32_t*)parent, orig, na, qb);
+        hipLaunchKernelGGL(bfs_init_kernel, dim3(g), dim3(EB), 0, stream, (const int32_t*)parent, orig,
+                           (const int32_t*)qb, na, dist, qa, ctr);
         uint32_t nin = 0;
         if ((e = hipMemcpyAsync(&nin, ctr + 1, sizeof nin, hipMemcpyDeviceToHost, stream)) != hipSuccess) return e;
         if ((e = hipStreamSynchronize(stream)) != hipSuccess) return e;

@@ -80,12 +80,12 @@ def test_debug_path_sigma_extremes():
 
 
 def test_walk_many_predecessors_and_arc_overflow():
-    """Nodes with more than 64 DAG predecessors, and searches that record more
-    DAG arcs than a slot keeps (16384 in a per-node slot; [1, 150, 150, 1]
-    records 22650, of which the level into distance 2 alone 22500), make the
-    walk scan in-rows instead of the arc list for those steps, while steps
-    whose own segment of the list is complete still use it; the paths still
-    equal the oracle's."""
+    """Nodes with more than 64 DAG predecessors (radix selection over the arc
+    list), and searches that record more DAG arcs than a slot keeps (16384 in
+    a per-node slot; [1, 150, 150, 1] records 22650, of which the level into
+    distance 2 alone 22500), which make the walk scan in-rows instead for
+    those steps, while steps whose own segment of the list is complete still
+    use it; the paths still equal the oracle's."""
     from paper_2509_11454_amd import percis as P
     for g in [W.layered_graph([1, 100, 100, 1]), W.layered_graph([1, 150, 150, 1]), W.layered_graph([1, 3, 70, 2, 1]),
               W.layered_graph([1, 90, 60, 1], directed=True), W.layered_graph([1, 65, 1])]:
@@ -100,6 +100,75 @@ def test_walk_many_predecessors_and_arc_overflow():
             assert (L, sig, ovf) == (L0, sig0, 0), g.name
             assert p == O.path(og, s, t, r)[2], (g.name, r)
         c.close()
+
+
+@pytest.mark.parametrize("k,directed", [(40, False), (70, False), (300, False), (300, True), (5000, False)])
+def test_walk_predecessor_order_is_caller_order(k, directed):
+    """s -> k middle nodes -> t, each middle node with 0..6 pendant leaves,
+    every id shuffled: the library numbers nodes by degree, so t's
+    predecessors sit in another order internally than by caller id. Every
+    walk step must still take them in caller id order: up to 64 predecessors
+    from the arc list in LDS, 65..4096 by radix selection on their caller
+    ids, more by the in-row scan in caller order. Paths for r across
+    [0, sigma) equal the oracle's."""
+    from paper_2509_11454_amd import percis as P
+    rng = np.random.default_rng(1000 + k + directed)
+    pend = rng.integers(0, 7, size=k)
+    n = 2 + k + int(pend.sum())
+    edges, leaf = [], 2 + k
+    for i in range(k):
+        m = 2 + i
+        edges += [(0, m), (m, 1)]
+        for _ in range(int(pend[i])):
+            edges.append((m, leaf))
+            leaf += 1
+    lab = rng.permutation(n)
+    g = W.from_edge_list(n, [(int(lab[a]), int(lab[b])) for a, b in edges], directed=directed)
+    s, t = int(lab[0]), int(lab[1])
+    c = P.Context(0)
+    c.load_csr(g.n, g.row_ptr, g.col, directed=g.directed)
+    og = O.Graph(g.n, g.row_ptr, g.col, g.directed)
+    L0, sig0, _ = O.path(og, s, t, 0)
+    assert (L0, sig0) == (2, k)
+    rs = {0, 1, k // 3, k // 2, k - 2, k - 1} | {int(x) for x in rng.integers(0, k, size=24)}
+    for r in sorted(rs):
+        L, sig, ovf, p = c.debug_path(s, t, r)
+        assert (L, sig, ovf) == (L0, sig0, 0)
+        assert p == O.path(og, s, t, r)[2], (k, directed, r)
+    c.close()
+
+
+@pytest.mark.parametrize("directed,compact", [(False, 1), (False, 2), (True, 1), (True, 2)])
+def test_walk_caller_order_sampling(directed, compact):
+    """Sampling parity where walk steps pick among 300 predecessors of mixed
+    degree: 40 sources joined to 300 middle nodes (0..6 pendant leaves each),
+    all joined to t, ids shuffled; t has state 0 and every other node 65535,
+    so every pair ends at t and the pairs from a source walk through t's 300
+    predecessors. 2e4 samples on per-node and on compact slots."""
+    rng = np.random.default_rng(77 + directed)
+    q, k = 40, 300
+    pend = rng.integers(0, 7, size=k)
+    n = 1 + q + k + int(pend.sum())
+    t0, edges, leaf = 0, [], 1 + q + k
+    for i in range(k):
+        m = 1 + q + i
+        edges += [(src, m) for src in range(1, 1 + q)] + [(m, t0)]
+        for _ in range(int(pend[i])):
+            edges.append((m, leaf))
+            leaf += 1
+    lab = rng.permutation(n)
+    g = W.from_edge_list(n, [(int(lab[a]), int(lab[b])) for a, b in edges], directed=directed)
+    kk = np.full(n, 65535, np.uint16)
+    kk[lab[t0]] = 0
+    og, st = oracle_objects(g, kk)
+    ho, so = oracle_hits(og, st, 0, 20000, 3)
+    from paper_2509_11454_amd import percis as P
+    c = gpu_context(g, kk)
+    c.set_option(P.OPT_COMPACT, compact)
+    hg, sg = gpu_hits(c, 0, 20000, 3)
+    assert np.array_equal(ho, hg)
+    same_stats(so, sg)
+    c.close()
 
 
 @pytest.mark.parametrize("sizes,directed", [([1, 3, 70, 2, 1], False), ([5, 40, 80, 40, 5], False),
