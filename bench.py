@@ -385,6 +385,7 @@ def run_batch(args):
     avg_kernel_s = sum(kern) / len(kern) / 1e3
     b_alg = algorithmic_bytes(launch)
     achieved = b_alg / avg_kernel_s / 1e9
+    traffic = measured_traffic("ba64", total)
     out = {
         "metric": METRIC, "value": value, "unit": "samples/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": elapsed / args.steps * 1e3, "higher_is_better": True,
@@ -393,14 +394,17 @@ def run_batch(args):
                                "%d samples per graph in one launch, captured as a HIP graph and replayed" % per_graph,
                    "nodes": sum(g.n for g, _ in graphs), "arcs": sum(g.m for g, _ in graphs), "tuning": tune},
         "gteps": launch["edges"] * args.steps / elapsed / 1e9,
+        "per_sample": {k: launch[k] / total for k in ("edges", "sigma_adds", "vertices_expanded",
+                                                       "vertices_discovered", "sum_I", "spilled")},
         "eager_launch": {"value": eager_rate, "unit": "samples/s", "form": "the same launch, issued kernel by kernel"},
         "per_graph_launches": {"value": seq_rate, "unit": "samples/s", "form": "64 launches, one graph each"},
         "one_sample_per_launch": {"value": opl_rate, "unit": "samples/s", "samples": nops},
         "speedup_vs_per_graph": value / seq_rate,
         "speedup_vs_one_per_launch": value / opl_rate,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "sampler_kernel",
-                     "kernel_ms": avg_kernel_s * 1e3, "algorithmic_bytes_per_launch": b_alg},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": "sampler_kernel",
+                     "kernel_ms": avg_kernel_s * 1e3, "algorithmic_bytes_per_launch": b_alg,
+                     "hbm_gbs_measured": (traffic / avg_kernel_s / 1e9) if traffic else None},
     }
     print(json.dumps(out), flush=True)
 
