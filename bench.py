@@ -16,6 +16,7 @@ import argparse
 import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -36,10 +37,16 @@ WORKLOADS = {
 
 
 def kernel_source_hash():
+    """Hash of the sampler's source (percis_kernels.hip, percis_internal.h)
+    with comments and whitespace removed: a comment edit keeps the committed
+    counters valid, a code edit does not."""
     h = hashlib.sha256()
     for f in ("percis_kernels.hip", "percis_internal.h"):
-        with open(os.path.join(ROOT, "paper_2509_11454_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_2509_11454_amd", "csrc", f)) as fh:
+            text = fh.read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        h.update(" ".join(text.split()).encode())
     return h.hexdigest()[:16]
 
 

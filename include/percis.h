@@ -151,7 +151,9 @@ int percis_set_states(percis_ctx* ctx, const uint16_t* k, uint32_t flags);
 /* Draws samples first .. first+count-1 of the stream (seed, phase): for each,
  * the pair (s,t) of Algorithm 2, a shortest-path-counting BFS (balanced
  * bidirectional, Section III-B), the r-th shortest path in canonical order
- * (r uniform in [0, sigma_st)), and one hit to each internal node.
+ * (r uniform in [0, sigma_st); walking back from t, the predecessors of a node
+ * are taken in ascending caller id, each covering sigma_s of the indices),
+ * and one hit to each internal node.
  * hits[n] (uint32) receives the per-node hit counts; hit counts over disjoint
  * index ranges add up. The random stream is Philox4x64-10 with key
  * (seed, phase) and counter (sample index, variate, attempt, 0), so results do
@@ -237,16 +239,17 @@ int percis_sample_tasks(percis_ctx* ctx, int32_t ntasks, const percis_task* task
 /* The same launch as a HIP graph, for callers that run one task set again and
  * again (a batch step): percis_batch_capture uploads the task table, makes
  * sure the device copies, slots and list buffers exist, and captures the
- * launch's kernels (task clearing, then per chunk of at most 2^22 samples the
+ * launch's kernels (task clearing, then per chunk (PERCIS_OPT_PAIR_CHUNK) the
  * pair kernel, the sampler and the 128-bit path) on a private stream into a
  * graph owned by *batch. percis_batch_replay launches the graph, waits, and
  * fills each task's stats (the pointers given at capture) and launch_stats
  * (may be NULL) as percis_sample_tasks does; kernel_ms is the graph's device
  * time and pair_ms 0. A replay gives exactly the hits and statistics of
  * percis_sample_tasks on the same tasks. The capture holds device addresses
- * and each graph's total weight: after percis_load_csr, percis_set_states,
- * percis_set_option, or a launch with a larger chunk than any before on this
- * context, a replay returns PERCIS_E_STATE (capture again). Destroy batches
+ * and each graph's total weight: after percis_load_csr, percis_set_states
+ * (successful or not), percis_set_option (other than PERCIS_OPT_BALANCE, whose
+ * rule a capture keeps), or a launch with a larger chunk than any before on
+ * this context, a replay returns PERCIS_E_STATE (capture again). Destroy batches
  * before their context. Replays of one context run one at a time. */
 typedef struct percis_batch percis_batch;
 int percis_batch_capture(percis_ctx* ctx, int32_t ntasks, const percis_task* tasks, percis_batch** batch);
@@ -275,7 +278,7 @@ int percis_set_vertex_diameter(percis_ctx* ctx, int64_t D);
 /* VertexDiamUB of Algorithm 1 (Section III-B) for graph `graph` into *D: the
  * override if one is set, else computed on the device once per loaded graph
  * (connected components by min-label hooking; for an undirected graph, per
- * component, a BFS from its smallest node u gives min(|comp| - 2,
+ * component, a BFS from its node u of smallest caller id gives min(|comp| - 2,
  * 2 ecc(u) - 1); for a directed graph the largest weakly connected
  * component's size minus 2; components of one node give 0). Synchronises the
  * context's stream. */
@@ -319,9 +322,9 @@ int percis_exact(percis_ctx* ctx, int32_t graph, double* p_out, double* kernel_m
 /* Tuning knobs (launch shape only; results never depend on them).
  * PERCIS_OPT_SLOTS: concurrent samples (resident workgroups), 0 = auto.
  * PERCIS_OPT_COMPACT: compact slots, whose node records are indexed by the
- * node's place in the side's LDS table (about 150 KB per slot instead of
+ * node's place in the side's LDS table (about 300 KB per slot instead of
  * ~48 bytes per node of the graph): 1 = off; 2 = on, with the per-node slots
- * redoing every sample that a side's table cannot hold (more than 768 nodes);
+ * redoing every sample that a side's table cannot hold (more than 1536 nodes);
  * 0 = auto (on when LDS tables are used and the per-node slots are too few,
  * for lack of memory, to fill the device). Reads 1 or 2 once a graph is
  * loaded. PERCIS_OPT_SLOTS reads the compact slots' count when they are on.
@@ -332,7 +335,8 @@ int percis_exact(percis_ctx* ctx, int32_t graph, double* p_out, double* kernel_m
  * per sample on fewer slots: such a launch is bound by its slowest samples).
  * PERCIS_OPT_BITMAPS: how a sample's visited sets are kept: 1 = one bitmap
  * per side in device memory; 2 = an exact hash table per side in LDS (8 KB
- * per sample), moved to the device bitmap if a side grows past 768 nodes;
+ * per sample, 64 KB at 512 threads or more), moved to the device bitmap if a
+ * side grows past 3/4 of it (768 nodes; 6144 at 512 threads or more);
  * 0 = auto (2 unless it lowers the number of resident samples).
  * Reading PERCIS_OPT_SLOTS, _BLOCK or _BITMAPS after a graph is loaded gives
  * the shape in use (BITMAPS then reads 1 or 2). */

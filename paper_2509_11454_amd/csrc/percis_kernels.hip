@@ -1,39 +1,48 @@
 // PercIS sampler kernels for gfx950 (MI355X).
 //
-// One persistent workgroup per slot. A slot owns per-node scratch (one 32-byte
-// record per node holding the levels and shortest-path counts from both ends,
-// and three queues) that is all-zero between samples; every sample clears
-// exactly what it touched. Visited sets are bitmaps -- in LDS when they fit,
-// otherwise in the slot's scratch -- so that the per-edge test touches one
-// bit. Workgroups claim launch indices from a global counter; a launch is a
-// table of tasks (sample ranges of possibly different graphs), and results
-// never depend on the launch shape: every sample's randomness is keyed on its
-// index (Philox4x64-10, counter (index, variate, attempt, 0), key
-// (seed, phase)), and all accumulation is integer.
+// One persistent workgroup per slot claims launch indices from a global
+// counter; a launch is a table of tasks (sample ranges of possibly different
+// graphs). Results never depend on the launch shape: every sample's
+// randomness is keyed on its index (Philox4x64-10, counter (index, variate,
+// attempt, 0), key (seed, phase)), and all accumulation is integer.
+//
+// Slots come in two kinds. A per-node slot owns one 32-byte record per node
+// (levels and shortest-path counts from both ends), three queues, two device
+// bitmap planes and a DAG-arc list. A compact slot indexes its records by the
+// node's position in its side's LDS visited table instead, so it costs a
+// fixed few hundred KB whatever the graph; a sample whose side outgrows the
+// table is handed on to the per-node slots and redone there. Visited sets
+// are exact LDS hash tables; a per-node side that outgrows its table moves to
+// its device bitmap plane. Every slot is all-zero between samples: each
+// sample clears exactly what it touched.
 //
 // Per sample (Algorithm 2 of the paper's appendix, then RandomSP of
 // Section III-B):
-//   1. pair: U_s uniform in [0, C) picks rank s = min{d : U_s < P[d]};
-//      U_t uniform in [0, c_s) picks t = min{d > s : U_t < F_s(d)} with
+//   1. pair (pair_kernel, one lane per sample, ahead of the sampler): U_s
+//      uniform in [0, C) picks rank s = min{d : U_s < P[d]}; U_t uniform in
+//      [0, c_s) picks t = min{d > s : U_t < F_s(d)} with
 //      F_s(d) = (d - s + 1) k_s - (W_s - W_{d+1}); both bounded draws use
-//      Lemire's multiply-and-reject, both searches are 64-way (one wave).
+//      Lemire's multiply-and-reject, both searches are per-lane bisections.
+//      Pairs with an end without arcs are counted as unreachable there.
 //   2. balanced bidirectional BFS with shortest-path counting: the side whose
 //      frontier has the smaller degree sum expands one full level, edge-
 //      balanced across the workgroup; the first level that reaches the other
 //      ball fixes d(s,t) = L and the meeting layer M, and
-//      sigma_st = sum_{w in M} sigma_s(w) sigma_t(w).
+//      sigma_st = sum_{w in M} sigma_s(w) sigma_t(w). That last level keeps
+//      only its arcs into the other ball (listed by a barrier-free first
+//      pass).
 //   3. shortest-path counts from s are pulled level by level from M down to
-//      t through the t-ball (each t-side node sums the counts of its
-//      in-neighbours one level farther from t), so that every node of the
-//      shortest-path DAG knows sigma_s.
+//      t through the t-ball, so that every node of the shortest-path DAG knows
+//      sigma_s; every sigma_s add records its DAG arc, in one list segment per
+//      distance from s.
 //   4. r uniform in [0, sigma_st); the canonical backward walk from t takes,
-//      among the in-neighbours one level closer to s (ascending id), the
-//      first whose cumulative sigma_s exceeds r (a 64-lane prefix scan per
-//      chunk of the in-row); every node passed on the way is an internal node
-//      of the chosen path and gets one hit.
-// A count that reaches 2^64 anywhere on the way to t is caught by a flag that
-// is set on a wrapping add and propagated along DAG arcs; the sample then adds
-// no hits and is counted as overflowed.
+//      among the predecessors one level closer to s in ascending caller id,
+//      the first whose cumulative sigma_s exceeds r (from the step's segment
+//      of the arc list, else from the in-row in caller order); once the walk
+//      reaches s, every internal node of the path gets one hit.
+// Counts are exact: a sample whose sigma_st reaches 2^64 is listed and redone
+// by wide_kernel with 128-bit counts; only a count that saturates 128 bits is
+// an overflow (no hits).
 #include "percis_internal.h"
 
 namespace percis {
