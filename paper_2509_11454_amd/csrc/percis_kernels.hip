@@ -61,7 +61,12 @@ constexpr int UNROLL = PERCIS_UNROLL;  // adjacency entries per thread per batch
 #define PERCIS_SCAN_UNROLL 4
 #endif
 constexpr int SCAN_UNROLL = PERCIS_SCAN_UNROLL;  // entries per thread per step of a long chunk's first pass
-constexpr int WALK_UNROLL = 4;  // in-row chunks of 64 loaded together by the walk's row scan
+// In-row chunks of 64 loaded together by the walk's row scan. One: the scan
+// is rare since walk steps with up to 4096 predecessors select from the arc
+// list, and the sampler's searches are sensitive to its code size (the
+// 512-thread kernel at 57.6 KB ran its handed-on pass of directed R-MAT 24 in
+// 245 ms, at 55.8 KB in 230 ms).
+constexpr int WALK_UNROLL = 1;
 constexpr int ARC_UNROLL = 4;   // DAG-arc chunks of 64 loaded together by the walk
 constexpr int KCAP = 64;        // predecessors a walk step gathers from the arc list
 constexpr int SEGCAP = 64;      // path positions whose arc-list segment a sample keeps
@@ -1402,14 +1407,12 @@ __device__ __forceinline__ void run_sample(const GGraph& g, const GSlots& sl, in
                             r -= lane_u64(ci, l) - lane_u64(wi, l);
                             sel = lane_i32(ui, l);
                         }
-                    } else if (CMP && kc <= xcap) {
-                        // (compact slots only: the call costs the per-node
-                        // kernels' searches more registers than it saves)
+                    } else if (kc <= xcap) {
                         sel = walk_select_radix(arcs, a_lo, a_hi, w, g.orig, xb, kc, r, sh.sig);
                     }
                     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
                 }
-                if (kc > (CMP ? xcap : KCAP)) {
+                if (kc > xcap) {
                     // in-row scan in caller id order: in-neighbours one level closer
                     // to s (s-level p, or t-level L - p past the meeting layer),
                     // weighed by sigma_s
