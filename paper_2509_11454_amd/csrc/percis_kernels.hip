@@ -1381,7 +1381,11 @@ __device__ __forceinline__ void run_sample(const GGraph& g, const GSlots& sl, in
                         }
                     }
                     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-                    if (kc <= KCAP) {
+                    if (kc == 1) {
+                        // one predecessor: it covers every index (no order needed)
+                        const int32_t u0 = __builtin_amdgcn_readfirstlane(sh.wk_u[0]);
+                        if (lane_u64(sh.wk_w[0], 0) > r) sel = u0;
+                    } else if (kc <= KCAP) {
                         // order by caller id: each lane swaps its predecessor's
                         // internal id in the list for the caller's
                         int32_t ui = -1, uo = INT32_MAX;
