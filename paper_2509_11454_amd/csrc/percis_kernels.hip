@@ -23,7 +23,8 @@
 //      [0, c_s) picks t = min{d > s : U_t < F_s(d)} with
 //      F_s(d) = (d - s + 1) k_s - (W_s - W_{d+1}); both bounded draws use
 //      Lemire's multiply-and-reject, both searches are per-lane bisections.
-//      Pairs with an end without arcs are counted as unreachable there.
+//      Pairs whose s has no out-arcs or whose t has no in-arcs are counted as
+//      unreachable there.
 //   2. balanced bidirectional BFS with shortest-path counting: the side whose
 //      frontier has the smaller degree sum expands one full level, edge-
 //      balanced across the workgroup; the first level that reaches the other
@@ -1684,8 +1685,9 @@ __global__ void fill_u8_kernel(uint8_t* p, int64_t bytes) {
 
 // The pairs of one chunk of a launch, one lane per sample (Algorithm 2: U_s
 // picks rank s by the prefix sums P, U_t picks rank t > s by F_s, both
-// searches binary). Pairs with an end without arcs are counted as samples of
-// their task (unreachable); the others are listed for the sampler.
+// searches binary). Pairs whose s has no out-arcs or whose t has no in-arcs
+// are counted as samples of their task (unreachable); the others are listed
+// for the sampler.
 __global__ __launch_bounds__(256) void pair_kernel(SampleLaunch L) {
     const int lane = threadIdx.x & 63;
     const unsigned long long below = (1ull << lane) - 1;
@@ -1718,7 +1720,10 @@ __global__ __launch_bounds__(256) void pair_kernel(SampleLaunch L) {
             });
             s = cdf.perm[sr];
             t = cdf.perm[tr];
-            trivial = s >= T.g.n_act || t >= T.g.n_act;
+            // no path if s has no out-arcs or t no in-arcs (for an undirected
+            // graph: an end without arcs)
+            trivial = s >= T.g.n_act || t >= T.g.n_act || T.g.rp[s + 1] == T.g.rp[s] ||
+                      T.g.irp[t + 1] == T.g.irp[t];
             listed = !trivial;
         }
         const unsigned long long lst = __ballot(listed);
