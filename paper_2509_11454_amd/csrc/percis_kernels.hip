@@ -1592,8 +1592,12 @@ __device__ __forceinline__ Vis<LDS> slot_vis(const GSlots& sl, int slot) {
 #ifndef PERCIS_SAMPLER_WAVES_PER_EU
 #define PERCIS_SAMPLER_WAVES_PER_EU 5
 #endif
+// A workgroup of 512 threads or more has 8+ waves, so at most 2 fit on a CU
+// (4 waves per SIMD) whatever the register budget: those kernels get the
+// 4-wave budget (128 VGPRs) instead of spilling at 96.
 #if PERCIS_SAMPLER_WAVES_PER_EU > 0
-#define SAMPLER_OCCUPANCY __attribute__((amdgpu_waves_per_eu(PERCIS_SAMPLER_WAVES_PER_EU)))
+#define SAMPLER_OCCUPANCY \
+    __attribute__((amdgpu_waves_per_eu(BSZ >= 512 && PERCIS_SAMPLER_WAVES_PER_EU > 4 ? 4 : PERCIS_SAMPLER_WAVES_PER_EU)))
 #else
 #define SAMPLER_OCCUPANCY
 #endif
