@@ -1,11 +1,12 @@
 // Host side of the PercIS library: the C ABI of include/percis.h.
 //
-// Responsibilities: validation of inputs, the device copies of the graphs
-// (out- and in-adjacency, in internal ids), the exact integer pair
-// distribution built from the states (the preprocessing of Algorithm 2),
-// per-slot scratch, task launches, the autotuner, and the scalar bounds of
-// Algorithm 1 (VertexDiamUB, Propositions 2 and 3, Theorem 1). Every
-// per-sample step runs on the device.
+// Responsibilities: validation of inputs, the internal numbering of a graph
+// (nodes with arcs by degree, rows sorted, in-rows also kept in caller order)
+// and its device copies, driving the device builds of the exact integer pair
+// distribution (the preprocessing of Algorithm 2) and of VertexDiamUB,
+// per-slot scratch, task launches and captures, the autotuner, and the scalar
+// bounds of Algorithm 1 (Propositions 2 and 3, Theorem 1). Every per-sample
+// step runs on the device.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
