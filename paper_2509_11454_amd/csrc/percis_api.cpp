@@ -17,6 +17,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "percis.h"
@@ -82,6 +83,42 @@ static void graph_clear(GraphData& G) {
     G.D_cached = -1;
 }
 
+// Host threads for a graph's load: one per 4 M arcs, at most the hardware's
+// threads and 16.
+static int host_threads(int64_t m) {
+    const int hw = std::max(1u, std::thread::hardware_concurrency());
+    return (int)std::max<int64_t>(1, std::min<int64_t>({(int64_t)hw, 16, m / (4 << 20) + 1}));
+}
+
+// nth contiguous row ranges with about equal arc counts: rows [r[t], r[t+1]).
+static std::vector<int32_t> row_split(const std::vector<int32_t>& rp, int nth) {
+    const int32_t n = (int32_t)rp.size() - 1;
+    const int64_t m = rp[n];
+    std::vector<int32_t> r(nth + 1, n);
+    r[0] = 0;
+    for (int t = 1; t < nth; t++) {
+        const int32_t target = (int32_t)(m * t / nth);
+        r[t] = std::max(r[t - 1], (int32_t)(std::lower_bound(rp.begin(), rp.end(), target) - rp.begin()));
+        r[t] = std::min(r[t], n);
+    }
+    return r;
+}
+
+// fn(t) for t in [0, nth) on nth threads (the caller's thread takes t = 0).
+template <class F>
+static void parallel_ranges(int nth, F fn) {
+    std::vector<std::thread> th;
+    for (int t = 1; t < nth; t++) {
+        try {
+            th.emplace_back(fn, t);
+        } catch (...) {
+            fn(t);  // no thread to be had: this range runs here
+        }
+    }
+    fn(0);
+    for (auto& x : th) x.join();
+}
+
 static int graph_load(percis_ctx* c, GraphData& G, int32_t n, int64_t m, const int32_t* row_ptr, const int32_t* col,
                       uint32_t flags) {
     if (n < 1 || m < 0 || !row_ptr || (m > 0 && !col)) return fail(c, PERCIS_E_INVAL, "bad graph arguments");
@@ -99,24 +136,58 @@ static int graph_load(percis_ctx* c, GraphData& G, int32_t n, int64_t m, const i
     if (rp[0] != 0 || (int64_t)rp[n] != m) return fail(c, PERCIS_E_INVAL, "row_ptr[0] must be 0 and row_ptr[n] = m");
     for (int32_t v = 0; v < n; v++)
         if (rp[v + 1] < rp[v]) return fail(c, PERCIS_E_INVAL, "row_ptr decreases at row %d", v);
-    for (int64_t e = 0; e < m; e++)
-        if (cl[e] < 0 || cl[e] >= n) return fail(c, PERCIS_E_INVAL, "col[%lld] = %d out of range", (long long)e, cl[e]);
-    for (int32_t v = 0; v < n; v++) {
-        int32_t* b = cl.data() + rp[v];
-        int32_t* e = cl.data() + rp[v + 1];
-        if (!std::is_sorted(b, e)) std::sort(b, e);
-        for (int32_t* p = b; p < e; p++) {
-            if (*p == v) return fail(c, PERCIS_E_INVAL, "self-loop at node %d", v);
-            if (p > b && p[-1] == *p) return fail(c, PERCIS_E_INVAL, "duplicate arc %d -> %d", v, *p);
+    // The checks and the renumbering below run over row ranges on host
+    // threads; each thread keeps the first failure of its range, and the
+    // first one over all ranges is reported, as a serial pass would.
+    const int nth = host_threads(m);
+    const std::vector<int32_t> rows = row_split(rp, nth);
+    {
+        std::vector<int64_t> bad(nth, -1);
+        parallel_ranges(nth, [&](int t) {
+            for (int64_t e = rp[rows[t]]; e < rp[rows[t + 1]]; e++)
+                if (cl[e] < 0 || cl[e] >= n) { bad[t] = e; return; }
+        });
+        for (int t = 0; t < nth; t++)
+            if (bad[t] >= 0)
+                return fail(c, PERCIS_E_INVAL, "col[%lld] = %d out of range", (long long)bad[t], cl[bad[t]]);
+    }
+    {
+        struct Bad { int32_t v = -1; int kind = 0; int32_t w = 0; };  // kind 1: self-loop, 2: duplicate
+        std::vector<Bad> bad(nth);
+        parallel_ranges(nth, [&](int t) {
+            for (int32_t v = rows[t]; v < rows[t + 1]; v++) {
+                int32_t* b = cl.data() + rp[v];
+                int32_t* e = cl.data() + rp[v + 1];
+                if (!std::is_sorted(b, e)) std::sort(b, e);
+                for (int32_t* q = b; q < e; q++) {
+                    if (*q == v) { bad[t] = Bad{v, 1, v}; return; }
+                    if (q > b && q[-1] == *q) { bad[t] = Bad{v, 2, *q}; return; }
+                }
+            }
+        });
+        for (int t = 0; t < nth; t++) {
+            if (bad[t].kind == 1) return fail(c, PERCIS_E_INVAL, "self-loop at node %d", bad[t].v);
+            if (bad[t].kind == 2) return fail(c, PERCIS_E_INVAL, "duplicate arc %d -> %d", bad[t].v, bad[t].w);
         }
     }
     const bool directed = (flags & PERCIS_DIRECTED) != 0;
     if (!directed) {
-        for (int32_t u = 0; u < n; u++)
-            for (int32_t e = rp[u]; e < rp[u + 1]; e++) {
-                const int32_t v = cl[e];
-                if (!std::binary_search(cl.data() + rp[v], cl.data() + rp[v + 1], u))
-                    return fail(c, PERCIS_E_INVAL, "undirected graph lacks arc %d -> %d (reverse of %d -> %d)", v, u, u, v);
+        std::vector<int64_t> bad(nth, -1);
+        parallel_ranges(nth, [&](int t) {
+            for (int32_t u = rows[t]; u < rows[t + 1]; u++)
+                for (int32_t e = rp[u]; e < rp[u + 1]; e++) {
+                    const int32_t v = cl[e];
+                    if (!std::binary_search(cl.data() + rp[v], cl.data() + rp[v + 1], u)) {
+                        bad[t] = e;
+                        return;
+                    }
+                }
+        });
+        for (int t = 0; t < nth; t++)
+            if (bad[t] >= 0) {
+                const int32_t v = cl[bad[t]];
+                const int32_t u = (int32_t)(std::upper_bound(rp.begin(), rp.end(), (int32_t)bad[t]) - rp.begin()) - 1;
+                return fail(c, PERCIS_E_INVAL, "undirected graph lacks arc %d -> %d (reverse of %d -> %d)", v, u, u, v);
             }
     }
     // Internal ids: nodes with an arc first, by degree (out + in) from the
@@ -124,9 +195,13 @@ static int graph_load(percis_ctx* c, GraphData& G, int32_t n, int64_t m, const i
     // arcs a search touches mostly end at high-degree nodes, so their node
     // records, bitmap words and row bounds share cache lines.
     std::vector<int64_t> deg(n, 0);
-    for (int32_t u = 0; u < n; u++) deg[u] = rp[u + 1] - rp[u];
+    parallel_ranges(nth, [&](int t) {
+        for (int32_t u = rows[t]; u < rows[t + 1]; u++) deg[u] = rp[u + 1] - rp[u];
+    });
     if (directed)
-        for (int64_t e = 0; e < m; e++) deg[cl[e]]++;
+        parallel_ranges(nth, [&](int t) {
+            for (int64_t e = rp[rows[t]]; e < rp[rows[t + 1]]; e++) __atomic_fetch_add(&deg[cl[e]], 1, __ATOMIC_RELAXED);
+        });
     int64_t dmax = 0;
     for (int32_t u = 0; u < n; u++) dmax = std::max(dmax, deg[u]);
     std::vector<int32_t> newid(n), orig(n);
@@ -145,34 +220,72 @@ static int graph_load(percis_ctx* c, GraphData& G, int32_t n, int64_t m, const i
     while (n_act < n && deg[orig[n_act]] > 0) n_act++;
     std::vector<int64_t>().swap(deg);
     std::vector<int32_t> rp2(n + 1, 0), cl2((size_t)m);
-    for (int32_t i = 0; i < n; i++) {
-        const int32_t v = orig[i];
-        rp2[i + 1] = rp2[i] + (rp[v + 1] - rp[v]);
-        int32_t o = rp2[i];
-        for (int32_t e = rp[v]; e < rp[v + 1]; e++) cl2[o++] = newid[cl[e]];
-    }
+    for (int32_t i = 0; i < n; i++) rp2[i + 1] = rp2[i] + (rp[orig[i] + 1] - rp[orig[i]]);
+    const std::vector<int32_t> rows2 = row_split(rp2, nth);
+    parallel_ranges(nth, [&](int t) {
+        for (int32_t i = rows2[t]; i < rows2[t + 1]; i++) {
+            const int32_t v = orig[i];
+            int32_t o = rp2[i];
+            for (int32_t e = rp[v]; e < rp[v + 1]; e++) cl2[o++] = newid[cl[e]];
+        }
+    });
+    std::vector<int32_t>().swap(cl);
     graph_clear(G);
     if (directed) {
-        // in-adjacency by a counting sort on the head; scanning tails in
-        // caller order keeps every in-row in caller order
+        // in-adjacency by a counting sort on the head, each thread over a
+        // range of tails in caller order (rows of the caller's numbering);
+        // the threads' counts give each one its place in every in-row, so
+        // every in-row lists its tails in caller order
         std::vector<int32_t> irp(n + 1, 0), icl((size_t)m);
-        for (int64_t e = 0; e < m; e++) irp[cl2[e] + 1]++;
-        for (int32_t v = 0; v < n; v++) irp[v + 1] += irp[v];
-        std::vector<int32_t> pos(irp.begin(), irp.end() - 1);
-        for (int32_t v = 0; v < n; v++) {
-            const int32_t u = newid[v];
-            for (int32_t e = rp2[u]; e < rp2[u + 1]; e++) icl[pos[cl2[e]]++] = u;
+        const int nt2 = std::max(1, std::min<int>(nth, (int)((int64_t)(512 << 20) / (4 * (int64_t)n + 4))));
+        const std::vector<int32_t> trows = row_split(rp, nt2);
+        std::vector<std::vector<int32_t>> cnt(nt2);
+        parallel_ranges(nt2, [&](int t) {
+            cnt[t].assign(n, 0);
+            for (int32_t v = trows[t]; v < trows[t + 1]; v++) {
+                const int32_t u = newid[v];
+                for (int32_t e = rp2[u]; e < rp2[u + 1]; e++) cnt[t][cl2[e]]++;
+            }
+        });
+        for (int32_t h = 0; h < n; h++) {
+            int32_t tot = 0;
+            for (int t = 0; t < nt2; t++) tot += cnt[t][h];
+            irp[h + 1] = irp[h] + tot;
         }
+        parallel_ranges(nth, [&](int t) {
+            // per head, each tail range's first slot
+            const int32_t h0 = (int32_t)((int64_t)n * t / nth), h1 = (int32_t)((int64_t)n * (t + 1) / nth);
+            for (int32_t h = h0; h < h1; h++) {
+                int32_t at = irp[h];
+                for (int r = 0; r < nt2; r++) {
+                    const int32_t k = cnt[r][h];
+                    cnt[r][h] = at;
+                    at += k;
+                }
+            }
+        });
+        parallel_ranges(nt2, [&](int t) {
+            for (int32_t v = trows[t]; v < trows[t + 1]; v++) {
+                const int32_t u = newid[v];
+                for (int32_t e = rp2[u]; e < rp2[u + 1]; e++) icl[cnt[t][cl2[e]]++] = u;
+            }
+        });
+        std::vector<std::vector<int32_t>>().swap(cnt);
         // the canonical walk reads in-rows in caller order; the searches read
         // them sorted by internal id
         G.h_ccol = icl;
-        for (int32_t v = 0; v < n; v++) std::sort(icl.begin() + irp[v], icl.begin() + irp[v + 1]);
+        const std::vector<int32_t> irows = row_split(irp, nth);
+        parallel_ranges(nth, [&](int t) {
+            for (int32_t v = irows[t]; v < irows[t + 1]; v++) std::sort(icl.begin() + irp[v], icl.begin() + irp[v + 1]);
+        });
         G.h_irp.swap(irp);
         G.h_icol.swap(icl);
     } else {
         G.h_ccol = cl2;
     }
-    for (int32_t v = 0; v < n; v++) std::sort(cl2.begin() + rp2[v], cl2.begin() + rp2[v + 1]);
+    parallel_ranges(nth, [&](int t) {
+        for (int32_t v = rows2[t]; v < rows2[t + 1]; v++) std::sort(cl2.begin() + rp2[v], cl2.begin() + rp2[v + 1]);
+    });
     G.h_rp.swap(rp2);
     G.h_col.swap(cl2);
     G.h_orig.swap(orig);

@@ -206,3 +206,43 @@ def test_task_hits_checked_before_any_launch(P):
             call([dict(task, hits=torch.zeros(g.n, dtype=torch.int64))])
     with pytest.raises(ValueError):
         c.sample_range(0, 10, 1, hits=np.zeros(g.n - 1, np.uint32))
+
+
+def test_threaded_graph_checks_report_the_first_failure(P):
+    """A graph of 2^20 nodes and ~12 M arcs is checked and renumbered on
+    several host threads; each planted fault must be caught and, with two
+    faults of one kind, the one a serial pass meets first is reported."""
+    g = W.rmat_graph(20, 12, seed=7, directed=True)
+    assert g.m > 8 << 20
+    c = ctx(P)
+    c.load_csr(g.n, g.row_ptr, g.col, directed=True)
+    rp = g.row_ptr.astype(np.int64)
+    deg = np.diff(rp)
+    early = int(np.nonzero(deg >= 2)[0][10])
+    late = int(np.nonzero(deg >= 2)[0][-10])
+    # a duplicate early and a self-loop late: the duplicate's row comes first
+    col = g.col.copy()
+    col[rp[early] + 1] = col[rp[early]]
+    col[rp[late]] = late
+    with pytest.raises(P.PercisError, match="duplicate arc %d -> " % early) as e:
+        c.load_csr(g.n, g.row_ptr, col, directed=True)
+    assert e.value.status == P.E_INVAL
+    # two out-of-range entries: the first index is named
+    col = g.col.copy()
+    col[g.m - 3] = g.n
+    col[rp[early]] = -1
+    with pytest.raises(P.PercisError, match=r"col\[%d\] = -1 out of range" % rp[early]):
+        c.load_csr(g.n, g.row_ptr, col, directed=True)
+    # an undirected graph with one reverse arc missing
+    u = W.rmat_graph(19, 12, seed=8, directed=False)
+    assert u.m > 8 << 20
+    c.load_csr(u.n, u.row_ptr, u.col)
+    ucol = u.col.copy()
+    urp = u.row_ptr.astype(np.int64)
+    v0 = int(np.nonzero(np.diff(urp) >= 3)[0][-5])
+    x = int(ucol[urp[v0]])
+    ucol[urp[v0]] = (x + 1) % u.n if (x + 1) % u.n != v0 else (x + 2) % u.n
+    with pytest.raises(P.PercisError, match="lacks arc") as e:
+        c.load_csr(u.n, u.row_ptr, ucol)
+    assert e.value.status == P.E_INVAL
+    c.close()
